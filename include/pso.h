@@ -1,0 +1,152 @@
+/*
+ * pso.h -- C ABI of libpso: global-best particle swarm optimisation on AMD
+ * Instinct MI355X (gfx950), after cuPSO (Wang, Ho, Tu, Hung, ACM SAC 2022).
+ *
+ * The library runs the per-iteration global-best PSO step on the GPU: the
+ * velocity and position update (Sec. 2.1, Eq. 1 and Eq. 2, with the clamps of
+ * Alg. 1 Step 2), the fitness (Alg. 1 Step 3), the personal-best update
+ * (Alg. 1 Step 4) and the aggregation into the swarm's global best (Alg. 1
+ * Step 5; Sec. 3.1 Alg. 2 and Sec. 3.2 Alg. 3 for the paper's queue and
+ * lock-protected aggregation, which this library replaces by a wavefront
+ * minimum, a workgroup (LDS) minimum and one packed 64-bit atomic minimum).
+ *
+ * Conventions for every call:
+ *   - Every call returns PSO_OK (0) or a negative PSO_E* code and never
+ *     aborts; pso_last_error() then describes the failure (thread-local text,
+ *     valid until the thread's next failing call).
+ *   - Pointers named *_host are host memory owned by the caller; the library
+ *     copies from or into them before returning and keeps no reference.
+ *   - A pso_swarm* is owned by the caller from pso_create/pso_create_in until
+ *     pso_destroy.  One swarm must not be used by two host threads at once.
+ *   - Work is enqueued on the swarm's HIP stream.  Calls that return results
+ *     to the host (pso_run, pso_get_*) synchronise that stream; the others
+ *     return as soon as the work is enqueued.
+ *   - The swarm minimises.  The paper's experiments maximise its Cubic
+ *     function (Sec. 5.1, Eq. 3); PSO_CUBIC is that function negated.
+ *
+ * State layout in device memory (structure of arrays, Sec. 4.1 Data
+ * Structure 2): position x, velocity v and personal-best position p are
+ * float arrays of D*N elements with element (d, i) -- dimension d of
+ * particle i -- at index d*N + i; the personal-best fitness pf holds N floats.
+ */
+#ifndef PSO_H
+#define PSO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define PSO_OK 0
+#define PSO_EINVAL (-1)  /* an argument is out of range or a handle is NULL */
+#define PSO_ENOMEM (-2)  /* device or pinned host memory could not be obtained */
+#define PSO_EDEVICE (-3) /* the HIP runtime or a kernel reported an error */
+#define PSO_EAGAIN (-4)  /* a result is not ready yet (server polling) */
+#define PSO_ESTATE (-5)  /* the call does not fit the object's current state */
+
+/* Fitness functions, all minimised over f(x) = F(x - shift). */
+#define PSO_SPHERE 0     /* sum z^2 */
+#define PSO_RASTRIGIN 1  /* 10 D + sum (z^2 - 10 cos(2 pi z)) */
+#define PSO_ROSENBROCK 2 /* sum_{d<D-1} 100 (z_{d+1} - z_d^2)^2 + (1 - z_d)^2, D >= 2 */
+#define PSO_ACKLEY 3     /* 20 - 20 exp(-0.2 sqrt(mean z^2)) + e - exp(mean cos(2 pi z)) */
+#define PSO_CUBIC 4      /* -(sum z^3 - 0.8 z^2 - 1000 z + 8000), Sec. 5.1 Eq. 3 negated */
+
+/* Aggregation variants (pso_set_variant). */
+#define PSO_SYNC 0  /* gbest of iteration t-1 for every particle of iteration t (Sec. 2.2) */
+#define PSO_ASYNC 1 /* a workgroup publishes a better gbest at once (Sec. 3.2) */
+
+typedef struct pso_swarm pso_swarm;
+
+/* Text of the calling thread's last failure ("" if none). */
+const char *pso_last_error(void);
+
+/* Device bytes a swarm of N particles in D dimensions needs when the caller
+ * provides the memory (pso_create_in); 0 if N or D is out of range. */
+size_t pso_workspace_bytes(int64_t N, int32_t D);
+
+/* Creates a swarm and runs Step 1 of Alg. 1 (Sec. 2.1) on the GPU: position
+ * and velocity uniform in [bounds[0], bounds[1]) and [-vmax, vmax), fitness,
+ * pbest <- position, gbest (iteration 0).  Parameters follow Table 1:
+ * w inertia weight, c1 cognitive and c2 social coefficient, bounds = {min_pos,
+ * max_pos} for every dimension, vmax = max_v with min_v = -vmax.
+ * fitness_id is one of PSO_SPHERE..PSO_CUBIC; seed keys the Philox4x32-10
+ * generator.  Requires 1 <= N < 2^32, 1 <= D <= 4096 (D >= 2 for
+ * Rosenbrock), finite parameters, bounds[0] < bounds[1], vmax > 0.
+ * The library allocates device memory and a stream; *out receives the handle.
+ * Errors: PSO_EINVAL, PSO_ENOMEM, PSO_EDEVICE. */
+int pso_create(int fitness_id, int64_t N, int32_t D, const float bounds[2], float w, float c1, float c2,
+               float vmax, uint64_t seed, pso_swarm **out);
+
+/* As pso_create, but the swarm lives in the caller's device memory
+ * dev_workspace (at least pso_workspace_bytes(N, D) bytes, 256-byte aligned)
+ * and its work goes to the caller's HIP stream hip_stream (a hipStream_t;
+ * NULL selects the null stream).  The caller keeps ownership of both and
+ * must keep them alive until pso_destroy. */
+int pso_create_in(int fitness_id, int64_t N, int32_t D, const float bounds[2], float w, float c1, float c2,
+                  float vmax, uint64_t seed, void *dev_workspace, size_t bytes, void *hip_stream,
+                  pso_swarm **out);
+
+/* Sets the shift vector s (D floats, host) of f(x) = F(x - s) and re-runs
+ * Step 1 so that the state is that of a fresh swarm with this shift.
+ * NULL restores s = 0. */
+int pso_set_shift(pso_swarm *s, const float *shift_host);
+
+/* Selects PSO_SYNC (default) or PSO_ASYNC for the iterations that follow. */
+int pso_set_variant(pso_swarm *s, int variant);
+
+/* Re-runs Step 1 in place: the swarm returns to iteration 0 with the same
+ * parameters, seed and shift.  Allocates nothing. */
+int pso_reset(pso_swarm *s);
+
+/* Enqueues one iteration t -> t+1 (Alg. 1 Steps 2-5) and returns.  Once a
+ * pso_run stop rule has been met, further steps leave the swarm unchanged. */
+int pso_step(pso_swarm *s);
+
+/* Runs up to max_iter more iterations, stopping after the first iteration
+ * (or at once) where |gbest_fit - f_star| < tol; tol <= 0 disables the test.
+ * Blocks until done, then writes the gbest fitness, the gbest position
+ * (D floats, host), the iteration at which the gbest last changed (0 = at
+ * initialisation) and the number of iterations this call ran.  Any output
+ * pointer may be NULL. */
+int pso_run(pso_swarm *s, int64_t max_iter, float tol, float f_star, float *gbest_value,
+            float *gbest_pos_host, int64_t *gbest_iter, int64_t *iters_done);
+
+/* Synchronises and reads the gbest fitness, position (D floats, host), the
+ * iteration of its last change and the number of iterations completed. */
+int pso_get_best(pso_swarm *s, float *gbest_value, float *gbest_pos_host, int64_t *gbest_iter,
+                 int64_t *iters_completed);
+
+/* Synchronises and copies the gbest keys of iterations t0 .. t0+count-1
+ * (key = order-preserving map of the gbest fitness << 32 | gbest index) into
+ * keys_host.  The library keeps the last 8192 iterations; older ones fail
+ * with PSO_ESTATE. */
+int pso_get_history(pso_swarm *s, int64_t t0, int64_t count, uint64_t *keys_host);
+
+/* Synchronises and copies the full state to host buffers: x, v, p (D*N
+ * floats each, layout above), pf (N floats), gbest key, gbest position (D),
+ * gbest iteration and iterations completed.  NULL buffers are skipped. */
+int pso_get_state(pso_swarm *s, float *x_host, float *v_host, float *p_host, float *pf_host,
+                  uint64_t *gbest_key, float *gbest_pos_host, int64_t *gbest_iter, int64_t *iters_completed);
+
+/* Replaces the state with the given one (same layout); the next iteration
+ * is iters_completed + 1.  Together with pso_get_state this checkpoints and
+ * resumes a swarm: the random numbers depend only on (seed, iteration,
+ * particle, dimension), so a resumed run repeats the uninterrupted one. */
+int pso_set_state(pso_swarm *s, const float *x_host, const float *v_host, const float *p_host,
+                  const float *pf_host, uint64_t gbest_key, const float *gbest_pos_host, int64_t gbest_iter,
+                  int64_t iters_completed);
+
+/* Blocks until the swarm's enqueued work is done; reports device errors. */
+int pso_sync(pso_swarm *s);
+
+/* Frees the library-owned memory and stream of the swarm.  NULL -> EINVAL. */
+int pso_destroy(pso_swarm *s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PSO_H */

@@ -1,0 +1,198 @@
+"""Global-best particle swarm optimisation on AMD Instinct MI355X (gfx950).
+
+A thin binding of libpso.so (include/pso.h): every function below marshals
+arguments for the C entry point of the same name; all computation happens in
+the library's HIP kernels.  PyTorch is used only for device memory and
+streams (pso_create_in with a torch tensor and torch's current stream).
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _native
+from ._native import (PSO_ACKLEY, PSO_ASYNC, PSO_CUBIC, PSO_EAGAIN, PSO_EDEVICE, PSO_EINVAL,  # noqa: F401
+                      PSO_ENOMEM, PSO_ESTATE, PSO_OK, PSO_RASTRIGIN, PSO_ROSENBROCK, PSO_SPHERE, PSO_SYNC)
+
+FITNESS = {"sphere": PSO_SPHERE, "rastrigin": PSO_RASTRIGIN, "rosenbrock": PSO_ROSENBROCK,
+           "ackley": PSO_ACKLEY, "cubic": PSO_CUBIC}
+
+
+class PsoError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        msg = _native.load().pso_last_error().decode(errors="replace")
+        super().__init__(f"{where} -> {code}: {msg}")
+        self.code = code
+
+
+def _check(code: int, where: str) -> int:
+    if code != PSO_OK:
+        raise PsoError(code, where)
+    return code
+
+
+def _fptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def fitness_id(f) -> int:
+    return FITNESS[f] if isinstance(f, str) else int(f)
+
+
+def lib():
+    return _native.load()
+
+
+def pso_workspace_bytes(N: int, D: int) -> int:
+    return int(lib().pso_workspace_bytes(N, D))
+
+
+def pso_create(fitness, N, D, bounds, w, c1, c2, vmax, seed) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    b = (ctypes.c_float * 2)(*bounds)
+    _check(lib().pso_create(fitness_id(fitness), N, D, b, w, c1, c2, vmax, seed, ctypes.byref(h)), "pso_create")
+    return h
+
+
+def pso_create_in(fitness, N, D, bounds, w, c1, c2, vmax, seed, dev_ptr: int, nbytes: int, stream_ptr: int):
+    h = ctypes.c_void_p()
+    b = (ctypes.c_float * 2)(*bounds)
+    _check(lib().pso_create_in(fitness_id(fitness), N, D, b, w, c1, c2, vmax, seed, ctypes.c_void_p(dev_ptr),
+                               nbytes, ctypes.c_void_p(stream_ptr), ctypes.byref(h)), "pso_create_in")
+    return h
+
+
+def pso_set_shift(h, shift):
+    if shift is None:
+        return _check(lib().pso_set_shift(h, None), "pso_set_shift")
+    s = np.ascontiguousarray(shift, np.float32)
+    return _check(lib().pso_set_shift(h, _fptr(s)), "pso_set_shift")
+
+
+def pso_set_variant(h, variant: int):
+    return _check(lib().pso_set_variant(h, variant), "pso_set_variant")
+
+
+def pso_reset(h):
+    return _check(lib().pso_reset(h), "pso_reset")
+
+
+def pso_step(h):
+    return _check(lib().pso_step(h), "pso_step")
+
+
+def pso_run(h, max_iter, D, tol=0.0, f_star=0.0):
+    val = ctypes.c_float()
+    pos = np.empty(D, np.float32)
+    git = ctypes.c_int64()
+    done = ctypes.c_int64()
+    _check(lib().pso_run(h, max_iter, tol, f_star, ctypes.byref(val), _fptr(pos), ctypes.byref(git),
+                         ctypes.byref(done)), "pso_run")
+    return dict(gbest_fit=np.float32(val.value), gbest_pos=pos, gbest_iter=git.value, iters=done.value)
+
+
+def pso_get_best(h, D):
+    val = ctypes.c_float()
+    pos = np.empty(D, np.float32)
+    git = ctypes.c_int64()
+    t = ctypes.c_int64()
+    _check(lib().pso_get_best(h, ctypes.byref(val), _fptr(pos), ctypes.byref(git), ctypes.byref(t)), "pso_get_best")
+    return dict(gbest_fit=np.float32(val.value), gbest_pos=pos, gbest_iter=git.value, t=t.value)
+
+
+def pso_get_history(h, t0, count):
+    out = np.empty(count, np.uint64)
+    _check(lib().pso_get_history(h, t0, count, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))),
+           "pso_get_history")
+    return out
+
+
+def pso_get_state(h, N, D):
+    st = dict(x=np.empty(D * N, np.float32), v=np.empty(D * N, np.float32), p=np.empty(D * N, np.float32),
+              pf=np.empty(N, np.float32), gpos=np.empty(D, np.float32))
+    key = ctypes.c_uint64()
+    git = ctypes.c_int64()
+    t = ctypes.c_int64()
+    _check(lib().pso_get_state(h, _fptr(st["x"]), _fptr(st["v"]), _fptr(st["p"]), _fptr(st["pf"]),
+                               ctypes.byref(key), _fptr(st["gpos"]), ctypes.byref(git), ctypes.byref(t)),
+           "pso_get_state")
+    st.update(gkey=key.value, giter=git.value, t=t.value)
+    return st
+
+
+def pso_set_state(h, st):
+    arrs = {k: np.ascontiguousarray(st[k], np.float32) for k in ("x", "v", "p", "pf", "gpos")}
+    return _check(lib().pso_set_state(h, _fptr(arrs["x"]), _fptr(arrs["v"]), _fptr(arrs["p"]), _fptr(arrs["pf"]),
+                                       int(st["gkey"]), _fptr(arrs["gpos"]), int(st["giter"]), int(st["t"])),
+                  "pso_set_state")
+
+
+def pso_sync(h):
+    return _check(lib().pso_sync(h), "pso_sync")
+
+
+def pso_destroy(h):
+    return _check(lib().pso_destroy(h), "pso_destroy")
+
+
+class Swarm:
+    """One swarm on the GPU: owns its handle; parameters as in Table 1."""
+
+    def __init__(self, fitness, N, D, bounds, w, c1, c2, vmax, seed, shift=None, variant=PSO_SYNC,
+                 workspace=None, stream=None):
+        self.N, self.D = int(N), int(D)
+        if workspace is None:
+            self.h = pso_create(fitness, N, D, bounds, w, c1, c2, vmax, seed)
+        else:
+            # torch tensor (device memory) + torch stream
+            self._ws = workspace
+            sp = 0 if stream is None else int(stream.cuda_stream)
+            self.h = pso_create_in(fitness, N, D, bounds, w, c1, c2, vmax, seed, int(workspace.data_ptr()),
+                                   int(workspace.numel() * workspace.element_size()), sp)
+        if shift is not None:
+            pso_set_shift(self.h, shift)
+        if variant != PSO_SYNC:
+            pso_set_variant(self.h, variant)
+
+    def step(self, n=1):
+        for _ in range(n):
+            pso_step(self.h)
+
+    def run(self, max_iter, tol=0.0, f_star=0.0):
+        return pso_run(self.h, max_iter, self.D, tol, f_star)
+
+    def reset(self):
+        pso_reset(self.h)
+
+    def best(self):
+        return pso_get_best(self.h, self.D)
+
+    def history(self, t0, count):
+        return pso_get_history(self.h, t0, count)
+
+    def state(self):
+        return pso_get_state(self.h, self.N, self.D)
+
+    def set_state(self, st):
+        pso_set_state(self.h, st)
+
+    def sync(self):
+        pso_sync(self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            pso_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

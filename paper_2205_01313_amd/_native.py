@@ -1,0 +1,65 @@
+"""ctypes declarations of libpso.so (include/pso.h).  Loading fails loudly if
+the library has not been built: there is no other implementation."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpso.so")
+
+PSO_OK, PSO_EINVAL, PSO_ENOMEM, PSO_EDEVICE, PSO_EAGAIN, PSO_ESTATE = 0, -1, -2, -3, -4, -5
+PSO_SPHERE, PSO_RASTRIGIN, PSO_ROSENBROCK, PSO_ACKLEY, PSO_CUBIC = 0, 1, 2, 3, 4
+PSO_SYNC, PSO_ASYNC = 0, 1
+
+c_int, c_i32, c_i64, c_u64, c_f, c_size, c_vp = (ctypes.c_int, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
+                                                   ctypes.c_float, ctypes.c_size_t, ctypes.c_void_p)
+P = ctypes.POINTER
+
+# name -> (restype, argtypes), in the order of include/pso.h
+SIGNATURES = {
+    "pso_last_error": (ctypes.c_char_p, []),
+    "pso_workspace_bytes": (c_size, [c_i64, c_i32]),
+    "pso_create": (c_int, [c_int, c_i64, c_i32, P(c_f), c_f, c_f, c_f, c_f, c_u64, P(c_vp)]),
+    "pso_create_in": (c_int, [c_int, c_i64, c_i32, P(c_f), c_f, c_f, c_f, c_f, c_u64, c_vp, c_size, c_vp, P(c_vp)]),
+    "pso_set_shift": (c_int, [c_vp, P(c_f)]),
+    "pso_set_variant": (c_int, [c_vp, c_int]),
+    "pso_reset": (c_int, [c_vp]),
+    "pso_step": (c_int, [c_vp]),
+    "pso_run": (c_int, [c_vp, c_i64, c_f, c_f, P(c_f), P(c_f), P(c_i64), P(c_i64)]),
+    "pso_get_best": (c_int, [c_vp, P(c_f), P(c_f), P(c_i64), P(c_i64)]),
+    "pso_get_history": (c_int, [c_vp, c_i64, c_i64, P(c_u64)]),
+    "pso_get_state": (c_int, [c_vp, P(c_f), P(c_f), P(c_f), P(c_f), P(c_u64), P(c_f), P(c_i64), P(c_i64)]),
+    "pso_set_state": (c_int, [c_vp, P(c_f), P(c_f), P(c_f), P(c_f), c_u64, P(c_f), c_i64, c_i64]),
+    "pso_sync": (c_int, [c_vp]),
+    "pso_destroy": (c_int, [c_vp]),
+}
+
+_lib = None
+
+
+def _single_hip_runtime():
+    """PyTorch ships its own HIP runtime, which it loads under a file name
+    different from the system one.  Importing torch before libpso.so makes
+    libpso bind to that same runtime, so a process never holds two (two
+    runtimes cannot share device pointers or streams)."""
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+
+
+def load(path: str = LIB_PATH):
+    """Load libpso.so and declare every entry point; raises if it is missing."""
+    global _lib
+    if _lib is None:
+        _single_hip_runtime()
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is not built; run paper_2205_01313_amd/build.py (hipcc, gfx950)")
+        lib = ctypes.CDLL(path)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib

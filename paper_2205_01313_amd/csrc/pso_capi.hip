@@ -1,0 +1,380 @@
+// pso_capi.hip -- host runtime behind include/pso.h: argument checks, device
+// memory and stream ownership, run loop with a device-side stop rule, and
+// state transfer.  Every entry point returns a status and never aborts.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/pso.h"
+#include "pso_device.hpp"
+#include "pso_kernels.hpp"
+
+using pso::Ctrl;
+using pso::Layout;
+using pso::SwarmArgs;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                           \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess) return fail(PSO_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int32_t MAX_D = 4096;
+
+} // namespace
+
+struct pso_swarm {
+    int fitness = 0;
+    int variant = PSO_SYNC;
+    uint64_t N = 0;
+    int32_t D = 0;
+    Layout L{};
+    SwarmArgs args{};
+    void *ws = nullptr;
+    bool owns_ws = false;
+    hipStream_t stream = nullptr;
+    bool owns_stream = false;
+    int device = 0;
+    Ctrl *host_ctrl = nullptr; // pinned mirror of the control block
+    float *host_gpos = nullptr; // pinned, D floats
+};
+
+namespace {
+
+int check_params(int fitness_id, int64_t N, int32_t D, const float bounds[2], float w, float c1, float c2,
+                 float vmax)
+{
+    if (fitness_id < PSO_SPHERE || fitness_id > PSO_CUBIC) return fail(PSO_EINVAL, "unknown fitness_id %d", fitness_id);
+    if (N < 1 || N >= (int64_t(1) << 32)) return fail(PSO_EINVAL, "N=%lld outside [1, 2^32)", (long long)N);
+    if (D < 1 || D > MAX_D) return fail(PSO_EINVAL, "D=%d outside [1, %d]", D, MAX_D);
+    if (fitness_id == PSO_ROSENBROCK && D < 2) return fail(PSO_EINVAL, "Rosenbrock needs D >= 2");
+    if (!bounds) return fail(PSO_EINVAL, "bounds is NULL");
+    if (!std::isfinite(bounds[0]) || !std::isfinite(bounds[1]) || !(bounds[0] < bounds[1]))
+        return fail(PSO_EINVAL, "bounds must be finite with bounds[0] < bounds[1]");
+    if (!std::isfinite(w) || !std::isfinite(c1) || !std::isfinite(c2))
+        return fail(PSO_EINVAL, "w, c1, c2 must be finite");
+    if (!std::isfinite(vmax) || !(vmax > 0.0f)) return fail(PSO_EINVAL, "vmax must be finite and > 0");
+    if (!std::isfinite(bounds[1] - bounds[0])) return fail(PSO_EINVAL, "bounds span overflows");
+    return PSO_OK;
+}
+
+int enqueue_init(pso_swarm *s)
+{
+    HIP_TRY(pso::launch_reset(s->args, s->stream));
+    HIP_TRY(pso::launch_init(s->fitness, s->args, s->stream));
+    return PSO_OK;
+}
+
+int create_common(int fitness_id, int64_t N, int32_t D, const float bounds[2], float w, float c1, float c2,
+                  float vmax, uint64_t seed, void *ws, size_t bytes, bool own, void *stream, pso_swarm **out)
+{
+    if (!out) return fail(PSO_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = check_params(fitness_id, N, D, bounds, w, c1, c2, vmax);
+    if (rc) return rc;
+    pso_swarm *s = new (std::nothrow) pso_swarm();
+    if (!s) return fail(PSO_ENOMEM, "host allocation failed");
+    s->fitness = fitness_id;
+    s->N = (uint64_t)N;
+    s->D = D;
+    s->L = pso::layout_of(s->N, D);
+    auto cleanup = [&](int code) {
+        if (s->owns_ws && s->ws) (void)hipFree(s->ws);
+        if (s->owns_stream && s->stream) (void)hipStreamDestroy(s->stream);
+        if (s->host_ctrl) (void)hipHostFree(s->host_ctrl);
+        if (s->host_gpos) (void)hipHostFree(s->host_gpos);
+        delete s;
+        return code;
+    };
+    if (hipGetDevice(&s->device) != hipSuccess) return cleanup(fail(PSO_EDEVICE, "no HIP device"));
+    if (own) {
+        if (hipMalloc(&s->ws, s->L.total) != hipSuccess)
+            return cleanup(fail(PSO_ENOMEM, "hipMalloc of %zu bytes failed", s->L.total));
+        s->owns_ws = true;
+        if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess)
+            return cleanup(fail(PSO_EDEVICE, "hipStreamCreate failed"));
+        s->owns_stream = true;
+    } else {
+        if (!ws) return cleanup(fail(PSO_EINVAL, "dev_workspace is NULL"));
+        if (reinterpret_cast<uintptr_t>(ws) & 255) return cleanup(fail(PSO_EINVAL, "dev_workspace not 256-byte aligned"));
+        if (bytes < s->L.total)
+            return cleanup(fail(PSO_EINVAL, "workspace of %zu bytes < %zu needed", bytes, s->L.total));
+        s->ws = ws;
+        s->stream = static_cast<hipStream_t>(stream);
+    }
+    if (hipHostMalloc(reinterpret_cast<void **>(&s->host_ctrl), sizeof(Ctrl), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&s->host_gpos), sizeof(float) * D, hipHostMallocDefault) != hipSuccess)
+        return cleanup(fail(PSO_ENOMEM, "pinned host allocation failed"));
+    s->args = pso::bind(s->ws, s->L, s->N, D);
+    s->args.lo = bounds[0];
+    s->args.hi = bounds[1];
+    s->args.w = w;
+    s->args.c1 = c1;
+    s->args.c2 = c2;
+    s->args.vmax = vmax;
+    s->args.k0 = (uint32_t)seed;
+    s->args.k1 = (uint32_t)(seed >> 32);
+    // shift = 0
+    std::vector<float> zero(D, 0.0f);
+    if (hipMemcpyAsync(const_cast<float *>(s->args.shift), zero.data(), sizeof(float) * D, hipMemcpyHostToDevice,
+                       s->stream) != hipSuccess)
+        return cleanup(fail(PSO_EDEVICE, "shift upload failed"));
+    rc = enqueue_init(s);
+    if (rc) return cleanup(rc);
+    if (hipStreamSynchronize(s->stream) != hipSuccess) return cleanup(fail(PSO_EDEVICE, "init failed"));
+    *out = s;
+    return PSO_OK;
+}
+
+int fetch_ctrl(pso_swarm *s, bool with_gpos)
+{
+    HIP_TRY(hipMemcpyAsync(s->host_ctrl, s->args.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s->stream));
+    if (with_gpos)
+        HIP_TRY(hipMemcpyAsync(s->host_gpos, s->args.gpos, sizeof(float) * s->D, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    if (s->host_ctrl->err) return fail(PSO_EDEVICE, "device error bits 0x%x", s->host_ctrl->err);
+    return PSO_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+const char *pso_last_error(void) { return g_err; }
+
+size_t pso_workspace_bytes(int64_t N, int32_t D)
+{
+    if (N < 1 || N >= (int64_t(1) << 32) || D < 1 || D > MAX_D) return 0;
+    return pso::layout_of((uint64_t)N, D).total;
+}
+
+int pso_create(int fitness_id, int64_t N, int32_t D, const float bounds[2], float w, float c1, float c2, float vmax,
+               uint64_t seed, pso_swarm **out)
+{
+    return create_common(fitness_id, N, D, bounds, w, c1, c2, vmax, seed, nullptr, 0, true, nullptr, out);
+}
+
+int pso_create_in(int fitness_id, int64_t N, int32_t D, const float bounds[2], float w, float c1, float c2,
+                  float vmax, uint64_t seed, void *dev_workspace, size_t bytes, void *hip_stream, pso_swarm **out)
+{
+    return create_common(fitness_id, N, D, bounds, w, c1, c2, vmax, seed, dev_workspace, bytes, false, hip_stream,
+                         out);
+}
+
+int pso_set_shift(pso_swarm *s, const float *shift_host)
+{
+    if (!s) return fail(PSO_EINVAL, "swarm is NULL");
+    std::vector<float> h(s->D, 0.0f);
+    if (shift_host) {
+        for (int d = 0; d < s->D; ++d) {
+            if (!std::isfinite(shift_host[d])) return fail(PSO_EINVAL, "shift[%d] is not finite", d);
+            h[d] = shift_host[d];
+        }
+    }
+    HIP_TRY(hipMemcpyAsync(const_cast<float *>(s->args.shift), h.data(), sizeof(float) * s->D,
+                           hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream)); // h is a stack buffer
+    return enqueue_init(s);
+}
+
+int pso_set_variant(pso_swarm *s, int variant)
+{
+    if (!s) return fail(PSO_EINVAL, "swarm is NULL");
+    if (variant != PSO_SYNC && variant != PSO_ASYNC) return fail(PSO_EINVAL, "unknown variant %d", variant);
+    if (variant == PSO_ASYNC) return fail(PSO_EINVAL, "asynchronous variant not available in this build");
+    s->variant = variant;
+    return PSO_OK;
+}
+
+int pso_reset(pso_swarm *s)
+{
+    if (!s) return fail(PSO_EINVAL, "swarm is NULL");
+    return enqueue_init(s);
+}
+
+int pso_step(pso_swarm *s)
+{
+    if (!s) return fail(PSO_EINVAL, "swarm is NULL");
+    HIP_TRY(pso::launch_step(s->fitness, s->variant, s->args, s->stream));
+    return PSO_OK;
+}
+
+int pso_run(pso_swarm *s, int64_t max_iter, float tol, float f_star, float *gbest_value, float *gbest_pos_host,
+            int64_t *gbest_iter, int64_t *iters_done)
+{
+    if (!s) return fail(PSO_EINVAL, "swarm is NULL");
+    if (max_iter < 0) return fail(PSO_EINVAL, "max_iter < 0");
+    if (std::isnan(tol) || std::isnan(f_star)) return fail(PSO_EINVAL, "tol and f_star must not be NaN");
+    HIP_TRY(pso::launch_arm(s->args, tol, f_star, s->stream));
+    if (tol > 0.0f) {
+        // Chunks of iterations with one chunk always queued ahead; the
+        // device skips iterations once the stop rule holds, and the host
+        // stops enqueueing when it sees the flag.
+        const double work = double(s->N) * double(s->D);
+        const int64_t chunk = std::max<int64_t>(8, std::min<int64_t>(256, int64_t((1 << 26) / work)));
+        hipEvent_t ev[2];
+        HIP_TRY(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+        if (hipEventCreateWithFlags(&ev[1], hipEventDisableTiming) != hipSuccess) {
+            (void)hipEventDestroy(ev[0]);
+            return fail(PSO_EDEVICE, "hipEventCreate failed");
+        }
+        unsigned int *flags = nullptr;
+        if (hipHostMalloc(reinterpret_cast<void **>(&flags), 2 * sizeof(unsigned int), hipHostMallocDefault) !=
+            hipSuccess) {
+            (void)hipEventDestroy(ev[0]);
+            (void)hipEventDestroy(ev[1]);
+            return fail(PSO_ENOMEM, "pinned host allocation failed");
+        }
+        int rc = PSO_OK;
+        int64_t done = 0;
+        int k = 0, inflight = 0;
+        while (done < max_iter && rc == PSO_OK) {
+            const int64_t n = std::min(chunk, max_iter - done);
+            for (int64_t j = 0; j < n && rc == PSO_OK; ++j)
+                if (pso::launch_step(s->fitness, s->variant, s->args, s->stream) != hipSuccess)
+                    rc = fail(PSO_EDEVICE, "step launch failed");
+            done += n;
+            if (hipMemcpyAsync(&flags[k], &s->args.ctrl->stop, sizeof(unsigned int), hipMemcpyDeviceToHost,
+                               s->stream) != hipSuccess ||
+                hipEventRecord(ev[k], s->stream) != hipSuccess)
+                rc = fail(PSO_EDEVICE, "stop flag copy failed");
+            ++inflight;
+            k ^= 1;
+            if (inflight == 2) { // wait for the older chunk
+                if (hipEventSynchronize(ev[k]) != hipSuccess) rc = fail(PSO_EDEVICE, "event wait failed");
+                --inflight;
+                if (flags[k]) break;
+            }
+        }
+        (void)hipStreamSynchronize(s->stream);
+        (void)hipHostFree(flags);
+        (void)hipEventDestroy(ev[0]);
+        (void)hipEventDestroy(ev[1]);
+        if (rc) return rc;
+    } else {
+        for (int64_t j = 0; j < max_iter; ++j) HIP_TRY(pso::launch_step(s->fitness, s->variant, s->args, s->stream));
+    }
+    int rc = fetch_ctrl(s, true);
+    if (rc) return rc;
+    const Ctrl &c = *s->host_ctrl;
+    if (gbest_value) *gbest_value = pso::key_fitness(c.gkey_prev);
+    if (gbest_pos_host) std::memcpy(gbest_pos_host, s->host_gpos, sizeof(float) * s->D);
+    if (gbest_iter) *gbest_iter = c.giter;
+    if (iters_done) *iters_done = c.t - c.t_run0;
+    return PSO_OK;
+}
+
+int pso_get_best(pso_swarm *s, float *gbest_value, float *gbest_pos_host, int64_t *gbest_iter,
+                 int64_t *iters_completed)
+{
+    if (!s) return fail(PSO_EINVAL, "swarm is NULL");
+    int rc = fetch_ctrl(s, true);
+    if (rc) return rc;
+    const Ctrl &c = *s->host_ctrl;
+    if (gbest_value) *gbest_value = pso::key_fitness(c.gkey_prev);
+    if (gbest_pos_host) std::memcpy(gbest_pos_host, s->host_gpos, sizeof(float) * s->D);
+    if (gbest_iter) *gbest_iter = c.giter;
+    if (iters_completed) *iters_completed = c.t;
+    return PSO_OK;
+}
+
+int pso_get_history(pso_swarm *s, int64_t t0, int64_t count, uint64_t *keys_host)
+{
+    if (!s) return fail(PSO_EINVAL, "swarm is NULL");
+    if (count < 0 || t0 < 0 || (count > 0 && !keys_host)) return fail(PSO_EINVAL, "bad history range");
+    int rc = fetch_ctrl(s, false);
+    if (rc) return rc;
+    const int64_t t = s->host_ctrl->t;
+    if (t0 + count > t + 1) return fail(PSO_ESTATE, "iterations %lld.. not run yet", (long long)(t + 1));
+    if (count > 0 && t0 < t + 1 - pso::HIST_CAP) return fail(PSO_ESTATE, "iteration %lld left the history", (long long)t0);
+    std::vector<unsigned long long> ring(pso::HIST_CAP);
+    HIP_TRY(hipMemcpy(ring.data(), s->args.hist, sizeof(unsigned long long) * pso::HIST_CAP, hipMemcpyDeviceToHost));
+    for (int64_t j = 0; j < count; ++j) keys_host[j] = ring[(t0 + j) & (pso::HIST_CAP - 1)];
+    return PSO_OK;
+}
+
+int pso_get_state(pso_swarm *s, float *x_host, float *v_host, float *p_host, float *pf_host, uint64_t *gbest_key,
+                  float *gbest_pos_host, int64_t *gbest_iter, int64_t *iters_completed)
+{
+    if (!s) return fail(PSO_EINVAL, "swarm is NULL");
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    const size_t nd = sizeof(float) * s->N * (size_t)s->D;
+    if (x_host) HIP_TRY(hipMemcpy(x_host, s->args.x, nd, hipMemcpyDeviceToHost));
+    if (v_host) HIP_TRY(hipMemcpy(v_host, s->args.v, nd, hipMemcpyDeviceToHost));
+    if (p_host) HIP_TRY(hipMemcpy(p_host, s->args.p, nd, hipMemcpyDeviceToHost));
+    if (pf_host) HIP_TRY(hipMemcpy(pf_host, s->args.pf, sizeof(float) * s->N, hipMemcpyDeviceToHost));
+    int rc = fetch_ctrl(s, true);
+    if (rc) return rc;
+    const Ctrl &c = *s->host_ctrl;
+    if (gbest_key) *gbest_key = c.gkey_prev;
+    if (gbest_pos_host) std::memcpy(gbest_pos_host, s->host_gpos, sizeof(float) * s->D);
+    if (gbest_iter) *gbest_iter = c.giter;
+    if (iters_completed) *iters_completed = c.t;
+    return PSO_OK;
+}
+
+int pso_set_state(pso_swarm *s, const float *x_host, const float *v_host, const float *p_host, const float *pf_host,
+                  uint64_t gbest_key, const float *gbest_pos_host, int64_t gbest_iter, int64_t iters_completed)
+{
+    if (!s) return fail(PSO_EINVAL, "swarm is NULL");
+    if (!x_host || !v_host || !p_host || !pf_host || !gbest_pos_host) return fail(PSO_EINVAL, "state buffer is NULL");
+    if (iters_completed < 0 || iters_completed >= (int64_t(1) << 32) - 1 || gbest_iter < 0 || gbest_iter > iters_completed)
+        return fail(PSO_EINVAL, "bad iteration counters");
+    if ((gbest_key & 0xFFFFFFFFull) >= s->N) return fail(PSO_EINVAL, "gbest index out of range");
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    const size_t nd = sizeof(float) * s->N * (size_t)s->D;
+    HIP_TRY(hipMemcpy(s->args.x, x_host, nd, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(s->args.v, v_host, nd, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(s->args.p, p_host, nd, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(s->args.pf, pf_host, sizeof(float) * s->N, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(s->args.gpos, gbest_pos_host, sizeof(float) * s->D, hipMemcpyHostToDevice));
+    Ctrl c;
+    std::memset(&c, 0, sizeof c);
+    c.gkey = gbest_key;
+    c.gkey_prev = gbest_key;
+    c.pubkey = gbest_key;
+    c.giter = gbest_iter;
+    c.t = iters_completed;
+    c.t_run0 = iters_completed;
+    HIP_TRY(hipMemcpy(s->args.ctrl, &c, sizeof c, hipMemcpyHostToDevice));
+    return PSO_OK;
+}
+
+int pso_sync(pso_swarm *s)
+{
+    if (!s) return fail(PSO_EINVAL, "swarm is NULL");
+    return fetch_ctrl(s, false);
+}
+
+int pso_destroy(pso_swarm *s)
+{
+    if (!s) return fail(PSO_EINVAL, "swarm is NULL");
+    (void)hipStreamSynchronize(s->stream);
+    if (s->owns_ws) (void)hipFree(s->ws);
+    if (s->owns_stream) (void)hipStreamDestroy(s->stream);
+    (void)hipHostFree(s->host_ctrl);
+    (void)hipHostFree(s->host_gpos);
+    delete s;
+    return PSO_OK;
+}
+
+} // extern "C"

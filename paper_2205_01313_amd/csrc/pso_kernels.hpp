@@ -1,0 +1,69 @@
+// pso_kernels.hpp -- device state of one swarm and the launchers of its
+// kernels (host side of the kernels in pso_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace pso {
+
+constexpr int HIST_CAP = 8192; // gbest keys kept per swarm (ring, power of two)
+
+// Control block of a swarm in device memory.  The fields that workgroups
+// update atomically sit on their own 256-byte lines.
+struct alignas(256) Ctrl {
+    // line 0: running minimum key of the current iteration (atomicMin target)
+    unsigned long long gkey;
+    unsigned char pad0[248];
+    // line 1: workgroups that finished the current launch
+    unsigned int arrive;
+    unsigned char pad1[252];
+    // line 2: bookkeeping, written by the last workgroup of each launch
+    unsigned long long gkey_prev; // gbest key after the previous iteration
+    long long giter;              // iteration at which the gbest last changed
+    long long t;                  // iterations completed
+    long long t_run0;             // t when the current pso_run began
+    unsigned int stop;            // 1 once the stop rule of the current run holds
+    unsigned int err;             // device-detected error bits
+    float tol, fstar;             // stop rule |gbest - fstar| < tol (tol <= 0: off)
+    unsigned char pad2[208];
+    // line 3: asynchronous variant -- seqlock over gpos
+    unsigned int seq;             // odd while a workgroup rewrites gpos
+    unsigned int lock;            // publisher lock
+    unsigned long long pubkey;    // key whose position gpos holds
+    unsigned char pad3[240];
+};
+static_assert(sizeof(Ctrl) == 1024, "Ctrl layout");
+
+constexpr unsigned int ERR_SEQLOCK_SPIN = 1u; // a seqlock wait gave up
+
+// Device pointers and parameters of one swarm, passed by value to kernels
+// (the kernel-argument segment is read through the scalar cache, the role
+// constant memory plays in Sec. 4.2).
+struct SwarmArgs {
+    float *x, *v, *p, *pf;      // D*N, D*N, D*N, N
+    float *gpos;                // D
+    const float *shift;         // D
+    unsigned long long *hist;   // HIST_CAP
+    Ctrl *ctrl;
+    uint32_t N;
+    int32_t D;
+    float lo, hi, w, c1, c2, vmax;
+    uint32_t k0, k1;            // Philox key = seed
+};
+
+// Byte layout of a swarm's workspace.
+struct Layout {
+    size_t ctrl, gpos, shift, hist, pf, x, v, p, total;
+};
+Layout layout_of(uint64_t N, int D);
+SwarmArgs bind(void *base, const Layout &L, uint64_t N, int D);
+
+// Launchers; all enqueue on `stream` and return the launch status.
+hipError_t launch_reset(const SwarmArgs &a, hipStream_t stream);
+hipError_t launch_init(int fitness, const SwarmArgs &a, hipStream_t stream);
+hipError_t launch_step(int fitness, int variant, const SwarmArgs &a, hipStream_t stream);
+hipError_t launch_arm(const SwarmArgs &a, float tol, float fstar, hipStream_t stream);
+
+} // namespace pso

@@ -18,3 +18,14 @@ def oracle_lib():
     import oracle
 
     return oracle.lib()
+
+
+def pytest_collection_modifyitems(config, items):
+    # GPU tests need the ROCm kernel driver; on a machine without one they are
+    # skipped (the CPU suite is selected with -m "not gpu" anyway).
+    if os.path.exists("/dev/kfd"):
+        return
+    skip = pytest.mark.skip(reason="no AMD GPU (/dev/kfd) on this machine")
+    for item in items:
+        if "gpu" in item.keywords:
+            item.add_marker(skip)

@@ -1,0 +1,172 @@
+"""GPU parity of the synchronous gbest PSO step against the oracle.
+
+The synchronous path computes exactly the oracle's binary32 definition, so
+the comparison is bit for bit: the gbest key of every iteration (fitness and
+index), the iteration of the last gbest change, and the full state
+(x, v, pbest position, pbest fitness, gbest position)."""
+import numpy as np
+import pytest
+
+import paper_2205_01313_amd as pso
+from paper_2205_01313_amd import workloads as wl
+from tests.gpu_util import announce, assert_state_equal, gpu_swarm, oracle_swarm
+
+pytestmark = pytest.mark.gpu
+
+
+def run_both(spec, T, nthreads=0, compare_state=True):
+    announce(f"{spec.fitness} N={spec.N} D={spec.D} T={T} seed={spec.seed}")
+    o = oracle_swarm(spec, nthreads).run_f32(T)
+    with gpu_swarm(spec) as g:
+        r = g.run(T)
+        hist = g.history(0, T + 1)
+        st = g.state()
+    bad = np.flatnonzero(hist != o["hist"])
+    assert bad.size == 0, f"gbest key differs first at iteration {bad[0]}: {hist[bad[0]]:x} vs {o['hist'][bad[0]]:x}"
+    assert r["iters"] == T and st["t"] == T
+    assert r["gbest_iter"] == o["giter"]
+    assert r["gbest_fit"] == o["gbest_fit"]
+    assert st["gkey"] == o["gkey"]
+    if compare_state:
+        assert_state_equal(st, o, spec.N, spec.D)
+    return o, st
+
+
+def test_small_sphere_full_run():
+    """Sphere D=2, N=1024, 1000 iterations, seed 0: whole trajectory."""
+    o, st = run_both(wl.small_sphere(), 1000)
+    assert o["gbest_fit"] < 1e-10
+
+
+@pytest.mark.parametrize("fit", wl.FITNESS_NAMES)
+@pytest.mark.parametrize("N,D", [(1, 3), (63, 1), (257, 2), (1000, 7), (4099, 32), (777, 33), (300, 70)])
+def test_ragged_shapes_all_fitness(fit, N, D):
+    if fit == "rosenbrock" and D < 2:
+        pytest.skip("Rosenbrock needs D >= 2")
+    spec = wl.SwarmSpec(fit, N, D, 40, seed=N * 31 + D, shift_amplitude=2.0)
+    run_both(spec, 40, nthreads=8)
+
+
+def test_golden_rastrigin_trajectory():
+    """Same run as tests/golden/rastrigin_d32_n4096_t50_seed1.txt."""
+    from tests.test_oracle_golden import load
+    giter, hist = load("rastrigin_d32_n4096_t50_seed1.txt")
+    spec = wl.SwarmSpec("rastrigin", 4096, 32, 50, seed=1, box=(-5.12, 5.12), vmax=1.024)
+    announce("golden rastrigin N=4096 D=32 T=50")
+    with gpu_swarm(spec) as g:
+        r = g.run(50)
+        h = g.history(0, 51)
+    assert np.array_equal(h, hist)
+    assert r["gbest_iter"] == giter
+
+
+def test_large_rastrigin_full_size_first_iterations():
+    """Rastrigin D=32, N=2^20 (the benchmark's workload) for 6 iterations: the
+    whole state, bit for bit."""
+    spec = wl.large_rastrigin(seed=0)
+    run_both(spec, 6, nthreads=16)
+
+
+@pytest.mark.parametrize("mk", [wl.deep_rosenbrock, wl.deep_ackley])
+def test_deep_d128_full_size_first_iterations(mk):
+    spec = mk(seed=3)
+    run_both(spec, 4, nthreads=16)
+
+
+def test_step_by_step_equals_run():
+    spec = wl.SwarmSpec("ackley", 3000, 9, 25, seed=5, shift_amplitude=3.0)
+    announce("step vs run")
+    with gpu_swarm(spec) as a, gpu_swarm(spec) as b:
+        a.run(25)
+        for _ in range(25):
+            b.step()
+        sa, sb = a.state(), b.state()
+    for k in ("x", "v", "p", "pf", "gpos"):
+        assert np.array_equal(sa[k], sb[k]), k
+    assert sa["gkey"] == sb["gkey"] and sa["giter"] == sb["giter"] and sa["t"] == sb["t"] == 25
+
+
+def test_stop_rule_matches_oracle():
+    spec = wl.SwarmSpec("sphere", 2048, 4, 600, seed=7)
+    announce("stop rule")
+    o = oracle_swarm(spec).run_f32(600, tol=1e-4, f_star=0.0)
+    assert o["iters"] < 600
+    with gpu_swarm(spec) as g:
+        r = g.run(600, tol=1e-4, f_star=0.0)
+        st = g.state()
+        # a second run with the rule already met runs nothing
+        r2 = g.run(50, tol=1e-4, f_star=0.0)
+    assert r["iters"] == o["iters"]
+    assert r["gbest_fit"] == o["gbest_fit"] and r["gbest_iter"] == o["giter"]
+    assert np.array_equal(r["gbest_pos"], o["gpos"])
+    assert_state_equal(st, o, spec.N, spec.D)
+    assert r2["iters"] == 0
+
+
+def test_checkpoint_resume_repeats_uninterrupted_run():
+    spec = wl.SwarmSpec("rastrigin", 5000, 12, 30, seed=11)
+    announce("checkpoint/resume")
+    with gpu_swarm(spec) as a:
+        a.run(30)
+        full = a.state()
+    with gpu_swarm(spec) as b:
+        b.run(17)
+        ck = b.state()
+    with gpu_swarm(wl.SwarmSpec("rastrigin", 5000, 12, 30, seed=11)) as c:
+        c.set_state(ck)
+        c.run(13)
+        res = c.state()
+    for k in ("x", "v", "p", "pf", "gpos"):
+        assert np.array_equal(res[k], full[k]), k
+    assert res["gkey"] == full["gkey"] and res["giter"] == full["giter"] and res["t"] == 30
+
+
+def test_reset_repeats_and_shift_reinitialises():
+    spec = wl.SwarmSpec("ackley", 1500, 6, 20, seed=2, shift_amplitude=4.0)
+    announce("reset/shift")
+    with gpu_swarm(spec) as g:
+        g.run(20)
+        a = g.state()
+        g.reset()
+        g.run(20)
+        b = g.state()
+        pso.pso_set_shift(g.h, None)
+        s0 = g.state()
+    for k in ("x", "v", "p", "pf", "gpos"):
+        assert np.array_equal(a[k], b[k]), k
+    assert s0["t"] == 0
+    o = oracle_swarm(wl.SwarmSpec("ackley", 1500, 6, 0, seed=2)).run_f32(0)
+    assert_state_equal(s0, o, 1500, 6)
+
+
+def test_caller_workspace_and_torch_stream():
+    import torch
+    spec = wl.SwarmSpec("rosenbrock", 3333, 5, 30, seed=4)
+    announce("pso_create_in with torch memory and stream")
+    nbytes = pso.pso_workspace_bytes(spec.N, spec.D)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    o = oracle_swarm(spec).run_f32(30)
+    g = pso.Swarm(spec.fitness, spec.N, spec.D, spec.box, spec.w, spec.c1, spec.c2, spec.vmax, spec.seed,
+                  workspace=ws, stream=stream)
+    try:
+        g.run(30)
+        st = g.state()
+    finally:
+        g.close()
+    assert st["gkey"] == o["gkey"]
+    assert_state_equal(st, o, spec.N, spec.D)
+
+
+def test_large_seed_and_single_particle():
+    spec = wl.SwarmSpec("cubic", 1, 1, 50, seed=(1 << 63) + 12345)
+    run_both(spec, 50)
+
+
+def test_history_window_errors():
+    spec = wl.SwarmSpec("sphere", 64, 2, 5, seed=0)
+    with gpu_swarm(spec) as g:
+        g.run(5)
+        with pytest.raises(pso.PsoError) as e:
+            g.history(0, 7)
+        assert e.value.code == pso.PSO_ESTATE
