@@ -73,7 +73,7 @@ size_t pso_workspace_bytes(int64_t N, int32_t D);
  * w inertia weight, c1 cognitive and c2 social coefficient, bounds = {min_pos,
  * max_pos} for every dimension, vmax = max_v with min_v = -vmax.
  * fitness_id is one of PSO_SPHERE..PSO_CUBIC; seed keys the Philox4x32-10
- * generator.  Requires 1 <= N < 2^32, 1 <= D <= 4096 (D >= 2 for
+ * generator.  Requires 1 <= N <= 2^30, 1 <= D <= 4096 (D >= 2 for
  * Rosenbrock), finite parameters, bounds[0] < bounds[1], vmax > 0.
  * The library allocates device memory and a stream; *out receives the handle.
  * Errors: PSO_EINVAL, PSO_ENOMEM, PSO_EDEVICE. */

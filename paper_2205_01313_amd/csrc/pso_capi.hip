@@ -11,7 +11,7 @@
 #include <new>
 #include <vector>
 
-#include "../../include/pso.h"
+#include "pso.h"
 #include "pso_device.hpp"
 #include "pso_kernels.hpp"
 
@@ -64,7 +64,7 @@ int check_params(int fitness_id, int64_t N, int32_t D, const float bounds[2], fl
                  float vmax)
 {
     if (fitness_id < PSO_SPHERE || fitness_id > PSO_CUBIC) return fail(PSO_EINVAL, "unknown fitness_id %d", fitness_id);
-    if (N < 1 || N >= (int64_t(1) << 32)) return fail(PSO_EINVAL, "N=%lld outside [1, 2^32)", (long long)N);
+    if (N < 1 || N > (int64_t(1) << 30)) return fail(PSO_EINVAL, "N=%lld outside [1, 2^30]", (long long)N);
     if (D < 1 || D > MAX_D) return fail(PSO_EINVAL, "D=%d outside [1, %d]", D, MAX_D);
     if (fitness_id == PSO_ROSENBROCK && D < 2) return fail(PSO_EINVAL, "Rosenbrock needs D >= 2");
     if (!bounds) return fail(PSO_EINVAL, "bounds is NULL");
@@ -163,7 +163,7 @@ const char *pso_last_error(void) { return g_err; }
 
 size_t pso_workspace_bytes(int64_t N, int32_t D)
 {
-    if (N < 1 || N >= (int64_t(1) << 32) || D < 1 || D > MAX_D) return 0;
+    if (N < 1 || N > (int64_t(1) << 30) || D < 1 || D > MAX_D) return 0;
     return pso::layout_of((uint64_t)N, D).total;
 }
 
@@ -316,11 +316,13 @@ int pso_get_state(pso_swarm *s, float *x_host, float *v_host, float *p_host, flo
                   float *gbest_pos_host, int64_t *gbest_iter, int64_t *iters_completed)
 {
     if (!s) return fail(PSO_EINVAL, "swarm is NULL");
+    HIP_TRY(pso::launch_flush(s->args, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
-    const size_t nd = sizeof(float) * s->N * (size_t)s->D;
-    if (x_host) HIP_TRY(hipMemcpy(x_host, s->args.x, nd, hipMemcpyDeviceToHost));
-    if (v_host) HIP_TRY(hipMemcpy(v_host, s->args.v, nd, hipMemcpyDeviceToHost));
-    if (p_host) HIP_TRY(hipMemcpy(p_host, s->args.p, nd, hipMemcpyDeviceToHost));
+    // device rows have pitch Np, host rows are dense (pitch N)
+    const size_t row = sizeof(float) * s->N, pitch = sizeof(float) * s->L.Np;
+    if (x_host) HIP_TRY(hipMemcpy2D(x_host, row, s->args.x, pitch, row, s->D, hipMemcpyDeviceToHost));
+    if (v_host) HIP_TRY(hipMemcpy2D(v_host, row, s->args.v, pitch, row, s->D, hipMemcpyDeviceToHost));
+    if (p_host) HIP_TRY(hipMemcpy2D(p_host, row, s->args.p, pitch, row, s->D, hipMemcpyDeviceToHost));
     if (pf_host) HIP_TRY(hipMemcpy(pf_host, s->args.pf, sizeof(float) * s->N, hipMemcpyDeviceToHost));
     int rc = fetch_ctrl(s, true);
     if (rc) return rc;
@@ -341,10 +343,10 @@ int pso_set_state(pso_swarm *s, const float *x_host, const float *v_host, const 
         return fail(PSO_EINVAL, "bad iteration counters");
     if ((gbest_key & 0xFFFFFFFFull) >= s->N) return fail(PSO_EINVAL, "gbest index out of range");
     HIP_TRY(hipStreamSynchronize(s->stream));
-    const size_t nd = sizeof(float) * s->N * (size_t)s->D;
-    HIP_TRY(hipMemcpy(s->args.x, x_host, nd, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(s->args.v, v_host, nd, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(s->args.p, p_host, nd, hipMemcpyHostToDevice));
+    const size_t row = sizeof(float) * s->N, pitch = sizeof(float) * s->L.Np;
+    HIP_TRY(hipMemcpy2D(s->args.x, pitch, x_host, row, row, s->D, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy2D(s->args.v, pitch, v_host, row, row, s->D, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy2D(s->args.p, pitch, p_host, row, row, s->D, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(s->args.pf, pf_host, sizeof(float) * s->N, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(s->args.gpos, gbest_pos_host, sizeof(float) * s->D, hipMemcpyHostToDevice));
     Ctrl c;
@@ -356,6 +358,8 @@ int pso_set_state(pso_swarm *s, const float *x_host, const float *v_host, const 
     c.t = iters_completed;
     c.t_run0 = iters_completed;
     HIP_TRY(hipMemcpy(s->args.ctrl, &c, sizeof c, hipMemcpyHostToDevice));
+    HIP_TRY(pso::launch_clear_pending(s->args, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
     return PSO_OK;
 }
 

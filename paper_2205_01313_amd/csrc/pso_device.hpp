@@ -25,14 +25,13 @@ __device__ __forceinline__ U4 philox4x32_10(uint32_t k0, uint32_t k1, uint32_t c
 {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = 0xD2511F53u * c0;
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo1 = 0xCD9E8D57u * c2;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
-        c0 = hi1 ^ c1 ^ k0;
-        c1 = lo1;
-        c2 = hi0 ^ c3 ^ k1;
-        c3 = lo0;
+        // one 32x32->64 product each (v_mad_u64_u32 on vector operands)
+        const uint64_t m0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t m1 = (uint64_t)0xCD9E8D57u * c2;
+        c0 = (uint32_t)(m1 >> 32) ^ c1 ^ k0;
+        c1 = (uint32_t)m1;
+        c2 = (uint32_t)(m0 >> 32) ^ c3 ^ k1;
+        c3 = (uint32_t)m0;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
@@ -80,7 +79,10 @@ __device__ __forceinline__ float cospi_f32(float y)
     if (!(__builtin_fabsf(y) < 0x1p24f)) return (y != y || __builtin_isinf(y)) ? __builtin_nanf("") : 1.0f;
     const float n = __builtin_rintf(y);
     const float a = __builtin_fabsf(y - n);
-    const float c = (a <= 0.25f) ? cos_pi_series(a) : sin_pi_series(0.5f - a);
+    // both series, then a select: no divergent branch
+    const float cc = cos_pi_series(a);
+    const float ss = sin_pi_series(0.5f - a);
+    const float c = (a <= 0.25f) ? cc : ss;
     return ((int)n & 1) ? -c : c;
 }
 

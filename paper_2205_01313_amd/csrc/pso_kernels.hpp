@@ -42,21 +42,27 @@ constexpr unsigned int ERR_SEQLOCK_SPIN = 1u; // a seqlock wait gave up
 // (the kernel-argument segment is read through the scalar cache, the role
 // constant memory plays in Sec. 4.2).
 struct SwarmArgs {
-    float *x, *v, *p, *pf;      // D*N, D*N, D*N, N
+    float *x, *v, *p, *pf;      // D*Np, D*Np, D*Np, Np; element (d, i) at d*Np + i
+    uint8_t *pend;              // Np: 1 = pbest position of i is x (not yet copied to p)
     float *gpos;                // D
     const float *shift;         // D
     unsigned long long *hist;   // HIST_CAP
     Ctrl *ctrl;
     uint32_t N;
+    uint32_t Np;                // row pitch: N rounded up to a multiple of 64
     int32_t D;
     float lo, hi, w, c1, c2, vmax;
     uint32_t k0, k1;            // Philox key = seed
 };
 
-// Byte layout of a swarm's workspace.
+// Byte layout of a swarm's workspace.  Each dimension's row of x, v, p holds
+// Np = N rounded up to 64 particles, so every row starts 256-byte aligned and
+// a lane can move four consecutive particles with one 16-byte access.
 struct Layout {
-    size_t ctrl, gpos, shift, hist, pf, x, v, p, total;
+    size_t ctrl, gpos, shift, hist, pf, pend, x, v, p, total;
+    uint64_t Np;
 };
+constexpr uint64_t ROW_ALIGN = 64;
 Layout layout_of(uint64_t N, int D);
 SwarmArgs bind(void *base, const Layout &L, uint64_t N, int D);
 
@@ -65,5 +71,9 @@ hipError_t launch_reset(const SwarmArgs &a, hipStream_t stream);
 hipError_t launch_init(int fitness, const SwarmArgs &a, hipStream_t stream);
 hipError_t launch_step(int fitness, int variant, const SwarmArgs &a, hipStream_t stream);
 hipError_t launch_arm(const SwarmArgs &a, float tol, float fstar, hipStream_t stream);
+// Copies every pending pbest position from x to p (before the state is read).
+hipError_t launch_flush(const SwarmArgs &a, hipStream_t stream);
+// Marks no pbest position pending (after the state is replaced).
+hipError_t launch_clear_pending(const SwarmArgs &a, hipStream_t stream);
 
 } // namespace pso
