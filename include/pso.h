@@ -145,6 +145,61 @@ int pso_sync(pso_swarm *s);
 /* Frees the library-owned memory and stream of the swarm.  NULL -> EINVAL. */
 int pso_destroy(pso_swarm *s);
 
+/* ------------------------------------------------------------------------ */
+/* Batches: many independent swarms (uneven N, D and fitness) run by one     */
+/* persistent launch; each swarm computes exactly what pso_create + pso_run  */
+/* (synchronous variant) computes for it alone.                              */
+/* ------------------------------------------------------------------------ */
+
+/* One swarm of a batch: the pso_create parameters, an optional shift (D
+ * floats, host, copied at pso_batch_create; NULL = 0) and the pso_run limits
+ * (max_iter iterations, stop once |gbest - f_star| < tol; tol <= 0: off). */
+typedef struct pso_desc {
+    int32_t fitness_id;
+    int32_t D;
+    int64_t N;
+    float bounds[2];
+    float w, c1, c2, vmax;
+    uint64_t seed;
+    const float *shift;
+    int64_t max_iter;
+    float tol;
+    float f_star;
+} pso_desc;
+
+/* Result of one batched swarm.  gbest_pos is caller memory (D floats, host)
+ * filled by pso_batch_results, or NULL to skip the position. */
+typedef struct pso_result {
+    float gbest_value;  /* gbest fitness */
+    int32_t status;     /* PSO_OK */
+    int64_t gbest_iter; /* iteration of the last gbest change (0 = init) */
+    int64_t iters;      /* iterations run */
+    float *gbest_pos;
+} pso_result;
+
+typedef struct pso_batch pso_batch;
+
+/* Validates count descriptors (each as pso_create, plus max_iter >= 0),
+ * allocates the device memory of all swarms and uploads their parameters.
+ * Work goes to hip_stream (a hipStream_t; NULL: a library-created stream).
+ * The descriptors are copied; the caller keeps ownership of them. */
+int pso_batch_create(const pso_desc *descs, int64_t count, void *hip_stream, pso_batch **out);
+
+/* Enqueues the whole batch -- Step 1 and every iteration of every swarm --
+ * as one persistent launch; returns without synchronising.  May be called
+ * again to rerun the batch from scratch. */
+int pso_batch_launch(pso_batch *b);
+
+/* Synchronises and writes results[i] for every swarm i (results[i].gbest_pos
+ * as described above). */
+int pso_batch_results(pso_batch *b, pso_result *results);
+
+/* Frees the batch's device memory (and its stream if the library made it). */
+int pso_batch_destroy(pso_batch *b);
+
+/* pso_batch_create + pso_batch_launch + pso_batch_results + destroy. */
+int pso_batch_run(const pso_desc *descs, int64_t count, pso_result *results);
+
 #ifdef __cplusplus
 }
 #endif

@@ -136,6 +136,80 @@ def pso_destroy(h):
     return _check(lib().pso_destroy(h), "pso_destroy")
 
 
+def _descs(specs):
+    """Array of pso_desc from objects with fitness, N, D, box, w, c1, c2, vmax,
+    seed, shift, T (max_iter), tol, f_star; keeps the shift arrays alive."""
+    arr = (_native.PsoDesc * len(specs))()
+    keep = []
+    for k, sp in enumerate(specs):
+        d = arr[k]
+        d.fitness_id = fitness_id(sp.fitness)
+        d.D, d.N = int(sp.D), int(sp.N)
+        d.bounds[0], d.bounds[1] = sp.box
+        d.w, d.c1, d.c2, d.vmax = sp.w, sp.c1, sp.c2, sp.vmax
+        d.seed = int(sp.seed)
+        if getattr(sp, "shift", None) is not None:
+            sh = np.ascontiguousarray(sp.shift, np.float32)
+            keep.append(sh)
+            d.shift = sh.ctypes.data
+        else:
+            d.shift = None
+        d.max_iter = int(sp.T)
+        d.tol = float(getattr(sp, "tol", 0.0) or 0.0)
+        d.f_star = float(getattr(sp, "f_star", 0.0) or 0.0)
+    return arr, keep
+
+
+class Batch:
+    """Many independent swarms run by one persistent launch (pso_batch_*)."""
+
+    def __init__(self, specs, stream=None):
+        self.specs = list(specs)
+        self._arr, self._keep = _descs(self.specs)
+        self.h = ctypes.c_void_p()
+        sp = None if stream is None else ctypes.c_void_p(int(stream.cuda_stream))
+        _check(lib().pso_batch_create(self._arr, len(self.specs), sp, ctypes.byref(self.h)), "pso_batch_create")
+
+    def launch(self):
+        _check(lib().pso_batch_launch(self.h), "pso_batch_launch")
+
+    def results(self, positions=True):
+        n = len(self.specs)
+        res = (_native.PsoResult * n)()
+        pos = [np.empty(int(sp.D), np.float32) for sp in self.specs] if positions else None
+        for k in range(n):
+            res[k].gbest_pos = pos[k].ctypes.data if positions else None
+        _check(lib().pso_batch_results(self.h, res), "pso_batch_results")
+        out = []
+        for k in range(n):
+            out.append(dict(gbest_fit=np.float32(res[k].gbest_value), gbest_iter=res[k].gbest_iter,
+                            iters=res[k].iters, gbest_pos=pos[k] if positions else None))
+        return out
+
+    def close(self):
+        if getattr(self, "h", None):
+            _check(lib().pso_batch_destroy(self.h), "pso_batch_destroy")
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pso_batch_run(specs):
+    with Batch(specs) as b:
+        b.launch()
+        return b.results()
+
+
 class Swarm:
     """One swarm on the GPU: owns its handle; parameters as in Table 1."""
 

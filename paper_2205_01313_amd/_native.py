@@ -16,6 +16,22 @@ c_int, c_i32, c_i64, c_u64, c_f, c_size, c_vp = (ctypes.c_int, ctypes.c_int32, c
                                                    ctypes.c_float, ctypes.c_size_t, ctypes.c_void_p)
 P = ctypes.POINTER
 
+
+class PsoDesc(ctypes.Structure):
+    """struct pso_desc of include/pso.h."""
+    _fields_ = [("fitness_id", ctypes.c_int32), ("D", ctypes.c_int32), ("N", ctypes.c_int64),
+                ("bounds", ctypes.c_float * 2), ("w", ctypes.c_float), ("c1", ctypes.c_float),
+                ("c2", ctypes.c_float), ("vmax", ctypes.c_float), ("seed", ctypes.c_uint64),
+                ("shift", ctypes.c_void_p), ("max_iter", ctypes.c_int64), ("tol", ctypes.c_float),
+                ("f_star", ctypes.c_float)]
+
+
+class PsoResult(ctypes.Structure):
+    """struct pso_result of include/pso.h."""
+    _fields_ = [("gbest_value", ctypes.c_float), ("status", ctypes.c_int32), ("gbest_iter", ctypes.c_int64),
+                ("iters", ctypes.c_int64), ("gbest_pos", ctypes.c_void_p)]
+
+
 # name -> (restype, argtypes), in the order of include/pso.h
 SIGNATURES = {
     "pso_last_error": (ctypes.c_char_p, []),
@@ -33,6 +49,11 @@ SIGNATURES = {
     "pso_set_state": (c_int, [c_vp, P(c_f), P(c_f), P(c_f), P(c_f), c_u64, P(c_f), c_i64, c_i64]),
     "pso_sync": (c_int, [c_vp]),
     "pso_destroy": (c_int, [c_vp]),
+    "pso_batch_create": (c_int, [P(PsoDesc), c_i64, c_vp, P(c_vp)]),
+    "pso_batch_launch": (c_int, [c_vp]),
+    "pso_batch_results": (c_int, [c_vp, P(PsoResult)]),
+    "pso_batch_destroy": (c_int, [c_vp]),
+    "pso_batch_run": (c_int, [P(PsoDesc), c_i64, P(PsoResult)]),
 }
 
 _lib = None

@@ -9,9 +9,11 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "pso.h"
+#include "pso_block.hpp"
 #include "pso_device.hpp"
 #include "pso_kernels.hpp"
 
@@ -39,6 +41,14 @@ int fail(int code, const char *fmt, ...)
     } while (0)
 
 constexpr int32_t MAX_D = 4096;
+
+// A synchronous swarm of at most this many particle-dimensions runs its
+// pso_run iterations in one workgroup (one launch for the whole run) instead
+// of one grid launch per iteration.
+#ifndef PSO_BLOCK_RUN_MAX_ND
+#define PSO_BLOCK_RUN_MAX_ND 65536
+#endif
+constexpr int64_t BLOCK_RUN_MAX_ND = PSO_BLOCK_RUN_MAX_ND;
 
 } // namespace
 
@@ -200,7 +210,6 @@ int pso_set_variant(pso_swarm *s, int variant)
 {
     if (!s) return fail(PSO_EINVAL, "swarm is NULL");
     if (variant != PSO_SYNC && variant != PSO_ASYNC) return fail(PSO_EINVAL, "unknown variant %d", variant);
-    if (variant == PSO_ASYNC) return fail(PSO_EINVAL, "asynchronous variant not available in this build");
     s->variant = variant;
     return PSO_OK;
 }
@@ -225,7 +234,10 @@ int pso_run(pso_swarm *s, int64_t max_iter, float tol, float f_star, float *gbes
     if (max_iter < 0) return fail(PSO_EINVAL, "max_iter < 0");
     if (std::isnan(tol) || std::isnan(f_star)) return fail(PSO_EINVAL, "tol and f_star must not be NaN");
     HIP_TRY(pso::launch_arm(s->args, tol, f_star, s->stream));
-    if (tol > 0.0f) {
+    const bool block_path = s->variant == PSO_SYNC && int64_t(s->N) * s->D <= BLOCK_RUN_MAX_ND;
+    if (block_path) {
+        if (max_iter > 0) HIP_TRY(pso::launch_block_run(s->fitness, s->args, max_iter, s->stream));
+    } else if (tol > 0.0f) {
         // Chunks of iterations with one chunk always queued ahead; the
         // device skips iterations once the stop rule holds, and the host
         // stops enqueueing when it sees the flag.
@@ -379,6 +391,185 @@ int pso_destroy(pso_swarm *s)
     (void)hipHostFree(s->host_gpos);
     delete s;
     return PSO_OK;
+}
+
+} // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batches.
+// ---------------------------------------------------------------------------
+struct pso_batch {
+    int64_t count = 0;
+    int maxD = 1;
+    int grid = 1;
+    void *slab = nullptr;            // every swarm's state
+    pso::BatchItem *d_items = nullptr;
+    uint32_t *d_order = nullptr;
+    pso::BatchResult *d_results = nullptr;
+    unsigned int *d_next = nullptr;
+    std::vector<pso::BatchItem> items; // host copy (device pointers inside)
+    hipStream_t stream = nullptr;
+    bool owns_stream = false;
+};
+
+namespace {
+
+void batch_free(pso_batch *b)
+{
+    if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    if (b->slab) (void)hipFree(b->slab);
+    if (b->d_items) (void)hipFree(b->d_items);
+    if (b->d_order) (void)hipFree(b->d_order);
+    if (b->d_results) (void)hipFree(b->d_results);
+    if (b->d_next) (void)hipFree(b->d_next);
+    if (b->owns_stream && b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+} // namespace
+
+extern "C" {
+
+int pso_batch_create(const pso_desc *descs, int64_t count, void *hip_stream, pso_batch **out)
+{
+    if (!out) return fail(PSO_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (count < 1 || count > (int64_t(1) << 31)) return fail(PSO_EINVAL, "count=%lld out of range", (long long)count);
+    if (!descs) return fail(PSO_EINVAL, "descs is NULL");
+    std::vector<pso::Layout> lay(count);
+    std::vector<size_t> off(count);
+    size_t total = 0;
+    int maxD = 1;
+    for (int64_t i = 0; i < count; ++i) {
+        const pso_desc &d = descs[i];
+        int rc = check_params(d.fitness_id, d.N, d.D, d.bounds, d.w, d.c1, d.c2, d.vmax);
+        if (rc) return fail(rc, "descriptor %lld: %s", (long long)i, std::string(g_err).c_str());
+        if (d.max_iter < 0 || d.max_iter >= (int64_t(1) << 32) - 1)
+            return fail(PSO_EINVAL, "descriptor %lld: max_iter out of range", (long long)i);
+        if (std::isnan(d.tol) || std::isnan(d.f_star)) return fail(PSO_EINVAL, "descriptor %lld: NaN tol/f_star", (long long)i);
+        if (d.shift)
+            for (int k = 0; k < d.D; ++k)
+                if (!std::isfinite(d.shift[k])) return fail(PSO_EINVAL, "descriptor %lld: shift not finite", (long long)i);
+        lay[i] = pso::layout_of((uint64_t)d.N, d.D, false);
+        off[i] = total;
+        total += lay[i].total;
+        maxD = std::max(maxD, (int)d.D);
+    }
+    pso_batch *b = new (std::nothrow) pso_batch();
+    if (!b) return fail(PSO_ENOMEM, "host allocation failed");
+    b->count = count;
+    b->maxD = maxD;
+    if (hip_stream) {
+        b->stream = static_cast<hipStream_t>(hip_stream);
+    } else {
+        if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+            batch_free(b);
+            return fail(PSO_EDEVICE, "hipStreamCreate failed");
+        }
+        b->owns_stream = true;
+    }
+    if (hipMalloc(&b->slab, total) != hipSuccess || hipMalloc(&b->d_items, sizeof(pso::BatchItem) * count) != hipSuccess ||
+        hipMalloc(&b->d_order, sizeof(uint32_t) * count) != hipSuccess ||
+        hipMalloc(&b->d_results, sizeof(pso::BatchResult) * count) != hipSuccess ||
+        hipMalloc(&b->d_next, sizeof(unsigned int)) != hipSuccess) {
+        batch_free(b);
+        return fail(PSO_ENOMEM, "hipMalloc of %zu bytes for the batch failed", total);
+    }
+    b->items.resize(count);
+    std::vector<float> shifts;
+    for (int64_t i = 0; i < count; ++i) {
+        const pso_desc &d = descs[i];
+        pso::BatchItem &it = b->items[i];
+        it.a = pso::bind(static_cast<char *>(b->slab) + off[i], lay[i], (uint64_t)d.N, d.D);
+        it.a.lo = d.bounds[0];
+        it.a.hi = d.bounds[1];
+        it.a.w = d.w;
+        it.a.c1 = d.c1;
+        it.a.c2 = d.c2;
+        it.a.vmax = d.vmax;
+        it.a.k0 = (uint32_t)d.seed;
+        it.a.k1 = (uint32_t)(d.seed >> 32);
+        it.fitness = d.fitness_id;
+        it.pad = 0;
+        it.max_iter = d.max_iter;
+        it.tol = d.tol;
+        it.fstar = d.f_star;
+        shifts.assign(d.D, 0.0f);
+        if (d.shift) std::memcpy(shifts.data(), d.shift, sizeof(float) * d.D);
+        if (hipMemcpy(const_cast<float *>(it.a.shift), shifts.data(), sizeof(float) * d.D, hipMemcpyHostToDevice) !=
+            hipSuccess) {
+            batch_free(b);
+            return fail(PSO_EDEVICE, "shift upload failed");
+        }
+    }
+    // largest work first: the persistent workgroups drain the queue in this order
+    std::vector<uint32_t> order(count);
+    for (int64_t i = 0; i < count; ++i) order[i] = (uint32_t)i;
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) {
+        const double wx = double(descs[x].N) * descs[x].D * double(descs[x].max_iter + 1);
+        const double wy = double(descs[y].N) * descs[y].D * double(descs[y].max_iter + 1);
+        return wx > wy;
+    });
+    if (hipMemcpy(b->d_items, b->items.data(), sizeof(pso::BatchItem) * count, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->d_order, order.data(), sizeof(uint32_t) * count, hipMemcpyHostToDevice) != hipSuccess) {
+        batch_free(b);
+        return fail(PSO_EDEVICE, "descriptor upload failed");
+    }
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        pso::batch_occupancy(maxD, &per_cu) != hipSuccess || cus < 1) {
+        batch_free(b);
+        return fail(PSO_EDEVICE, "device query failed");
+    }
+    b->grid = (int)std::min<int64_t>(count, int64_t(cus) * std::max(1, per_cu));
+    *out = b;
+    return PSO_OK;
+}
+
+int pso_batch_launch(pso_batch *b)
+{
+    if (!b) return fail(PSO_EINVAL, "batch is NULL");
+    HIP_TRY(pso::launch_batch(b->d_items, b->d_order, b->d_results, (uint32_t)b->count, b->d_next, b->maxD, b->grid,
+                              b->stream));
+    return PSO_OK;
+}
+
+int pso_batch_results(pso_batch *b, pso_result *results)
+{
+    if (!b) return fail(PSO_EINVAL, "batch is NULL");
+    if (!results) return fail(PSO_EINVAL, "results is NULL");
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    std::vector<pso::BatchResult> r(b->count);
+    HIP_TRY(hipMemcpy(r.data(), b->d_results, sizeof(pso::BatchResult) * b->count, hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < b->count; ++i) {
+        results[i].gbest_value = pso::key_fitness(r[i].gkey);
+        results[i].status = PSO_OK;
+        results[i].gbest_iter = r[i].giter;
+        results[i].iters = r[i].iters;
+        if (results[i].gbest_pos)
+            HIP_TRY(hipMemcpy(results[i].gbest_pos, b->items[i].a.gpos, sizeof(float) * b->items[i].a.D,
+                              hipMemcpyDeviceToHost));
+    }
+    return PSO_OK;
+}
+
+int pso_batch_destroy(pso_batch *b)
+{
+    if (!b) return fail(PSO_EINVAL, "batch is NULL");
+    batch_free(b);
+    return PSO_OK;
+}
+
+int pso_batch_run(const pso_desc *descs, int64_t count, pso_result *results)
+{
+    pso_batch *b = nullptr;
+    int rc = pso_batch_create(descs, count, nullptr, &b);
+    if (rc) return rc;
+    rc = pso_batch_launch(b);
+    if (!rc) rc = pso_batch_results(b, results);
+    batch_free(b);
+    return rc;
 }
 
 } // extern "C"

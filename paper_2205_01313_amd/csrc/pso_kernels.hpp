@@ -38,6 +38,10 @@ static_assert(sizeof(Ctrl) == 1024, "Ctrl layout");
 
 constexpr unsigned int ERR_SEQLOCK_SPIN = 1u; // a seqlock wait gave up
 
+// Aggregation variants (values of PSO_SYNC / PSO_ASYNC in pso.h).
+constexpr int VAR_SYNC = 0;
+constexpr int VAR_ASYNC = 1;
+
 // Device pointers and parameters of one swarm, passed by value to kernels
 // (the kernel-argument segment is read through the scalar cache, the role
 // constant memory plays in Sec. 4.2).
@@ -61,9 +65,11 @@ struct SwarmArgs {
 struct Layout {
     size_t ctrl, gpos, shift, hist, pf, pend, x, v, p, total;
     uint64_t Np;
+    bool control; // ctrl and hist present
 };
 constexpr uint64_t ROW_ALIGN = 64;
-Layout layout_of(uint64_t N, int D);
+// control = false leaves out the control block and history (batched swarms).
+Layout layout_of(uint64_t N, int D, bool control = true);
 SwarmArgs bind(void *base, const Layout &L, uint64_t N, int D);
 
 // Launchers; all enqueue on `stream` and return the launch status.

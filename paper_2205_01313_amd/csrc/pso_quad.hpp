@@ -1,0 +1,174 @@
+// pso_quad.hpp -- the per-particle work of Step 1 and Steps 2-4 (Alg. 1),
+// for the four consecutive particles a lane owns.  Every kernel (grid step,
+// per-swarm workgroup, batched) calls these, so all of them compute the same
+// bits for the same particle and iteration.
+#pragma once
+
+#include "pso_device.hpp"
+#include "pso_kernels.hpp"
+
+namespace pso {
+
+__device__ __forceinline__ float clampf(float v, float lo, float hi)
+{
+    v = (v < lo) ? lo : v;
+    return (v > hi) ? hi : v;
+}
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// 16-byte accesses of lane quad q within one dimension's row; the streamed
+// state carries non-temporal hints.
+__device__ __forceinline__ f4 ld_stream(const float *row, uint32_t q)
+{
+    return __builtin_nontemporal_load(reinterpret_cast<const f4 *>(row) + q);
+}
+
+__device__ __forceinline__ void st_stream(float *row, uint32_t q, f4 v)
+{
+    __builtin_nontemporal_store(v, reinterpret_cast<f4 *>(row) + q);
+}
+
+// Random words of dimension d = 2*pair + h: Philox output words 2h and 2h+1.
+__device__ __forceinline__ uint32_t word_r1(const U4 &u, int h) { return h ? u.c : u.a; }
+__device__ __forceinline__ uint32_t word_r2(const U4 &u, int h) { return h ? u.d : u.b; }
+
+// Step 1 for particles 4q .. 4q+3: x ~ U[lo, hi), v ~ U[-vmax, vmax), p = x,
+// pf = F(x), nothing pending.  Padding particles (index >= N, < Np) are
+// initialised too, so every stored element is finite.  Returns the smallest
+// key among the valid particles.
+template <int FIT>
+__device__ __forceinline__ unsigned long long init_quad(const SwarmArgs &a, int D, uint32_t q,
+                                                        const float *s_shift)
+{
+    const uint32_t i0 = 4 * q;
+    const size_t Np = a.Np;
+    const float span = a.hi - a.lo, vspan = a.vmax + a.vmax;
+    Fitness<FIT> fit[4];
+    for (int d = 0; d < D; d += 2) {
+        U4 u[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) u[k] = philox4x32_10(a.k0, a.k1, (uint32_t)d >> 1, i0 + k, 0u, TAG_INIT);
+        const int nd = (d + 1 < D) ? 2 : 1;
+        for (int h = 0; h < nd; ++h) {
+            f4 xs, vs;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                xs[k] = clampf(a.lo + span * unit_float(word_r1(u[k], h)), a.lo, a.hi);
+                vs[k] = clampf(-a.vmax + vspan * unit_float(word_r2(u[k], h)), -a.vmax, a.vmax);
+                fit[k].add(xs[k] - s_shift[d + h], d + h);
+            }
+            const size_t row = (size_t)(d + h) * Np;
+            st_stream(a.x + row, q, xs);
+            st_stream(a.v + row, q, vs);
+            st_stream(a.p + row, q, xs);
+        }
+    }
+    unsigned long long key = NO_KEY;
+    f4 fs;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        fs[k] = fit[k].value(D);
+        if (i0 + k < a.N) {
+            const unsigned long long kk = make_key(fs[k], i0 + k);
+            key = kk < key ? kk : key;
+        }
+    }
+    *reinterpret_cast<f4 *>(a.pf + i0) = fs;
+    *reinterpret_cast<uint32_t *>(a.pend + i0) = 0u;
+    return key;
+}
+
+// Steps 2-4 of iteration t for particles 4q .. 4q+3 (4q < N), with the gbest
+// position s_g and shift s_shift (D floats each, in LDS).  Returns the
+// smallest key among the particles whose pbest improved (NO_KEY if none).
+//
+// Deferred pbest positions: a particle whose pbest improves is marked in
+// pend and its new pbest position is left in x.  The next iteration reads x
+// anyway, so it uses x as the pbest position of marked particles and writes
+// it to p; every lane of a 128-byte line (8 lanes x 4 particles) holding a
+// marked particle rewrites its 16 bytes, so p is only written in whole lines.
+// Must be called by all active lanes of the wavefront together (it ballots).
+template <int FIT, int DC, int UNROLL>
+__device__ __forceinline__ unsigned long long iterate_quad(const SwarmArgs &a, int D, uint32_t q, uint32_t t,
+                                                           const float *s_g, const float *s_shift)
+{
+    const uint32_t i0 = 4 * q;
+    const size_t Np = a.Np;
+    const float w = a.w, c1 = a.c1, c2 = a.c2, vmax = a.vmax, lo = a.lo, hi = a.hi;
+    const f4 pf_old = *reinterpret_cast<const f4 *>(a.pf + i0);
+    const uint32_t pend = *reinterpret_cast<const uint32_t *>(a.pend + i0);
+    const unsigned long long dirty = __ballot(pend != 0u);
+    const bool line_dirty = ((dirty >> ((threadIdx.x & 63) & ~7u)) & 0xFFull) != 0;
+    Fitness<FIT> fit[4];
+#pragma unroll UNROLL
+    for (int d = 0; d < D; d += 2) {
+        U4 u[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) u[k] = philox4x32_10(a.k0, a.k1, (uint32_t)d >> 1, i0 + k, t, TAG_VEL);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (h == 1 && d + 1 >= D) break;
+            const size_t row = (size_t)(d + h) * Np;
+            const f4 xs = ld_stream(a.x + row, q);
+            const f4 vs = ld_stream(a.v + row, q);
+            f4 ps = ld_stream(a.p + row, q);
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (pend & (0xFFu << (8 * k))) ps[k] = xs[k];
+            const float g = s_g[d + h], sh = s_shift[d + h];
+            f4 xn, vn;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float r1 = unit_float(word_r1(u[k], h));
+                const float r2 = unit_float(word_r2(u[k], h));
+                // Eq. 1 left to right, clamp to [-vmax, vmax]; Eq. 2, clamp to [lo, hi]
+                float nv = ((w * vs[k]) + ((c1 * r1) * (ps[k] - xs[k]))) + ((c2 * r2) * (g - xs[k]));
+                nv = clampf(nv, -vmax, vmax);
+                xn[k] = clampf(xs[k] + nv, lo, hi);
+                vn[k] = nv;
+                fit[k].add(xn[k] - sh, d + h);
+            }
+            st_stream(a.x + row, q, xn);
+            st_stream(a.v + row, q, vn);
+            if (line_dirty) st_stream(a.p + row, q, ps);
+        }
+    }
+    // Step 4: strict improvement; NaN never improves.
+    unsigned long long key = NO_KEY;
+    f4 pf_new = pf_old;
+    uint32_t pend_new = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float f = fit[k].value(D);
+        if (i0 + k < a.N && f < pf_old[k]) {
+            pend_new |= 1u << (8 * k);
+            pf_new[k] = f;
+            const unsigned long long kk = make_key(f, i0 + k);
+            key = kk < key ? kk : key;
+        }
+    }
+    if (pend_new) *reinterpret_cast<f4 *>(a.pf + i0) = pf_new;
+    if (pend_new != pend) *reinterpret_cast<uint32_t *>(a.pend + i0) = pend_new;
+    return key;
+}
+
+// p <- x for the marked particles of quad q; clears the marks.
+__device__ __forceinline__ void flush_quad(const SwarmArgs &a, uint32_t q)
+{
+    const uint32_t i0 = 4 * q;
+    const uint32_t pend = *reinterpret_cast<const uint32_t *>(a.pend + i0);
+    if (!pend) return;
+    for (int d = 0; d < a.D; ++d) {
+        const size_t row = (size_t)d * a.Np;
+        const f4 xs = *(reinterpret_cast<const f4 *>(a.x + row) + q);
+        f4 ps = *(reinterpret_cast<const f4 *>(a.p + row) + q);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (pend & (0xFFu << (8 * k))) ps[k] = xs[k];
+        *(reinterpret_cast<f4 *>(a.p + row) + q) = ps;
+    }
+    *reinterpret_cast<uint32_t *>(a.pend + i0) = 0u;
+}
+
+} // namespace pso

@@ -1,0 +1,88 @@
+"""Asynchronous gbest variant (the lock-protected gbest of Sec. 3.2): a
+workgroup that improves the gbest publishes it at once, so later workgroups
+of the same iteration may use a newer gbest and the trajectory legitimately
+differs from the synchronous one.  It is judged by invariants that any
+correct run satisfies and by its final-fitness distribution over 32 seeds."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2205_01313_amd as pso
+from paper_2205_01313_amd import workloads as wl
+from tests.gpu_util import announce, gpu_swarm, oracle_swarm
+
+pytestmark = pytest.mark.gpu
+
+
+def check_invariants(spec, st, prev, osw):
+    N, D = spec.N, spec.D
+    x, v, p = (st[k].reshape(D, N) for k in ("x", "v", "p"))
+    pf = st["pf"]
+    assert np.all(x >= np.float32(spec.lo)) and np.all(x <= np.float32(spec.hi))
+    assert np.all(np.abs(v) <= np.float32(spec.vmax))
+    gi = st["gkey"] & 0xFFFFFFFF
+    gf = oracle.key_value(st["gkey"])
+    assert gf == pf.min() and gi == int(np.flatnonzero(pf == pf.min())[0])
+    # the published position is the gbest particle's pbest position
+    assert np.array_equal(st["gpos"], p[:, gi])
+    if osw is not None:
+        assert np.array_equal(osw.fitness_f32(p.T), pf)
+    if prev is not None:
+        assert st["gkey"] <= prev["gkey"]
+        assert np.all(pf <= prev["pf"])
+
+
+@pytest.mark.parametrize("fit,N,D", [("rastrigin", 20000, 8), ("ackley", 50000, 33), ("sphere", 9000, 300)])
+def test_invariants_every_iteration(fit, N, D):
+    spec = wl.SwarmSpec(fit, N, D, 25, seed=D, shift_amplitude=1.0)
+    announce(f"async invariants {fit} N={N} D={D}")
+    osw = oracle_swarm(spec, nthreads=16)
+    with gpu_swarm(spec, variant=pso.PSO_ASYNC) as g:
+        prev = g.state()
+        check_invariants(spec, prev, None, osw)
+        for _ in range(spec.T):
+            g.step()
+            st = g.state()
+            check_invariants(spec, st, prev, osw if _ % 8 == 0 else None)
+            prev = st
+        assert st["t"] == spec.T
+
+
+def test_async_history_is_monotone_and_giter_consistent():
+    spec = wl.SwarmSpec("rosenbrock", 100000, 16, 60, seed=5)
+    announce("async history")
+    with gpu_swarm(spec, variant=pso.PSO_ASYNC) as g:
+        r = g.run(60)
+        h = g.history(0, 61)
+    assert np.all(h[1:] <= h[:-1])
+    changes = np.flatnonzero(h[1:] != h[:-1]) + 1
+    assert r["gbest_iter"] == (changes[-1] if changes.size else 0)
+    assert oracle.key_value(h[-1]) == r["gbest_fit"]
+
+
+def test_async_stop_rule():
+    spec = wl.SwarmSpec("sphere", 300000, 4, 400, seed=2)
+    with gpu_swarm(spec, variant=pso.PSO_ASYNC) as g:
+        r = g.run(400, tol=1e-3, f_star=0.0)
+    assert r["gbest_fit"] < 1e-3 and r["iters"] < 400
+
+
+def test_final_fitness_distribution_32_seeds():
+    """Rastrigin D=32, N=2^20, 200 iterations, seeds 0..31: the asynchronous
+    variant reaches the same quality as the synchronous one (medians within a
+    factor of 1.5 either way); the quantiles and a two-sample KS statistic are
+    printed for the record."""
+    import scipy.stats
+    fs = {pso.PSO_SYNC: [], pso.PSO_ASYNC: []}
+    for variant in fs:
+        for seed in range(32):
+            spec = wl.large_rastrigin(seed=seed)
+            with gpu_swarm(spec, variant=variant) as g:
+                fs[variant].append(float(g.run(spec.T)["gbest_fit"]))
+    s, a = np.array(fs[pso.PSO_SYNC]), np.array(fs[pso.PSO_ASYNC])
+    ks = scipy.stats.ks_2samp(s, a)
+    print(f"\nsync  quantiles (0,25,50,75,100): {np.percentile(s, [0, 25, 50, 75, 100])}")
+    print(f"async quantiles (0,25,50,75,100): {np.percentile(a, [0, 25, 50, 75, 100])}")
+    print(f"KS statistic {ks.statistic:.3f}, p = {ks.pvalue:.3g}")
+    assert np.all(np.isfinite(s)) and np.all(np.isfinite(a))
+    assert np.median(a) <= 1.5 * np.median(s) and np.median(s) <= 1.5 * np.median(a)

@@ -1,0 +1,82 @@
+"""Batches: many swarms of uneven N, D and fitness in one persistent launch.
+Each swarm must compute exactly what it computes alone (pso_create +
+pso_run, synchronous) -- bit for bit -- and the oracle's result."""
+import numpy as np
+import pytest
+
+import paper_2205_01313_amd as pso
+from paper_2205_01313_amd import workloads as wl
+from tests.gpu_util import announce, gpu_swarm, oracle_swarm
+
+pytestmark = pytest.mark.gpu
+
+
+def mixed_specs(n, seed, max_iter=60):
+    rng = np.random.default_rng(seed)
+    specs = []
+    for k in range(n):
+        fit = wl.FITNESS_NAMES[int(rng.integers(0, 4))]
+        N = int(np.exp(rng.uniform(np.log(1), np.log(3000))))
+        D = int(rng.integers(1, 40))
+        if fit == "rosenbrock":
+            D = max(D, 2)
+        sp = wl.SwarmSpec(fit, N, D, int(rng.integers(0, max_iter)), seed=int(rng.integers(0, 2**40)),
+                          shift_amplitude=float(rng.uniform(0, 5)))
+        if k % 5 == 0:
+            sp.tol, sp.f_star = 1e-2, 0.0
+        specs.append(sp)
+    return specs
+
+
+def alone(sp):
+    with gpu_swarm(sp) as g:
+        r = g.run(sp.T, tol=getattr(sp, "tol", 0.0), f_star=getattr(sp, "f_star", 0.0))
+    return r
+
+
+def test_batch_equals_each_swarm_alone():
+    specs = mixed_specs(150, 1)
+    announce("batch of 150 vs alone")
+    res = pso.pso_batch_run(specs)
+    for sp, r in zip(specs, res):
+        a = alone(sp)
+        assert r["gbest_fit"] == a["gbest_fit"], sp
+        assert r["gbest_iter"] == a["gbest_iter"], sp
+        assert r["iters"] == a["iters"], sp
+        assert np.array_equal(r["gbest_pos"], a["gbest_pos"]), sp
+
+
+def test_batch_equals_oracle():
+    specs = mixed_specs(40, 2)
+    announce("batch of 40 vs oracle")
+    res = pso.pso_batch_run(specs)
+    for sp, r in zip(specs, res):
+        o = oracle_swarm(sp, nthreads=8).run_f32(sp.T, tol=getattr(sp, "tol", 0.0), f_star=getattr(sp, "f_star", 0.0))
+        assert r["gbest_fit"] == o["gbest_fit"], sp
+        assert r["gbest_iter"] == o["giter"] and r["iters"] == o["iters"], sp
+        assert np.array_equal(r["gbest_pos"], o["gpos"]), sp
+
+
+def test_batch_relaunch_repeats():
+    specs = mixed_specs(64, 3)
+    with pso.Batch(specs) as b:
+        b.launch()
+        r1 = b.results()
+        b.launch()
+        r2 = b.results()
+    for a, c in zip(r1, r2):
+        assert a["gbest_fit"] == c["gbest_fit"] and np.array_equal(a["gbest_pos"], c["gbest_pos"])
+
+
+def test_batch_single_and_tiny():
+    specs = [wl.SwarmSpec("sphere", 1, 1, 10, seed=3)]
+    r = pso.pso_batch_run(specs)[0]
+    o = oracle_swarm(specs[0]).run_f32(10)
+    assert r["gbest_fit"] == o["gbest_fit"] and r["iters"] == 10
+
+
+def test_batch_rejects_bad_descriptor():
+    specs = [wl.SwarmSpec("sphere", 16, 2, 5), wl.SwarmSpec("rosenbrock", 16, 1, 5)]
+    with pytest.raises(pso.PsoError) as e:
+        pso.pso_batch_run(specs)
+    assert e.value.code == pso.PSO_EINVAL and "descriptor 1" in str(e.value)
