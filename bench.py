@@ -23,6 +23,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+COPY_BYTES = 256 << 20  # calibration copy: reads and writes this many bytes
 
 
 def source_digest() -> str:
@@ -46,32 +47,6 @@ def traffic_from_profiles(kernel: str, launches_bytes_alg: float):
     if not ent or ent.get("source_digest") != source_digest():
         return None
     return ent["hbm_bytes_per_launch"]
-
-
-def improvement_rate(spec, pso, np) -> float:
-    """Mean fraction of particles whose pbest improves per iteration, from an
-    untimed run that reads pf after every iteration."""
-    sw = pso.Swarm(spec.fitness, spec.N, spec.D, spec.box, spec.w, spec.c1, spec.c2, spec.vmax, spec.seed)
-    try:
-        prev = sw_pf(sw, pso, np)
-        rates = []
-        for _ in range(spec.T):
-            sw.step()
-            cur = sw_pf(sw, pso, np)
-            rates.append(float(np.count_nonzero(cur < prev)) / spec.N)
-            prev = cur
-    finally:
-        sw.close()
-    return float(np.mean(rates))
-
-
-def sw_pf(sw, pso, np):
-    import ctypes
-    pf = np.empty(sw.N, np.float32)
-    fp = ctypes.POINTER(ctypes.c_float)
-    pso._check(pso.lib().pso_get_state(sw.h, None, None, None, pf.ctypes.data_as(fp), None, None, None, None),
-               "pso_get_state")
-    return pf
 
 
 def cpu_baseline(spec, iters: int):
@@ -99,7 +74,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--variant", choices=["sync", "async"], default="sync")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=8)
+    ap.add_argument("--cpu-iters", type=int, default=200)
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="for rocprofv3 counter runs: init + 20 step launches, then a 256 MiB torch copy "
+                         "(calibration kernel of known size); prints nothing else")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the path is single-GPU (--gpus {args.gpus} is not supported)",
@@ -121,6 +99,21 @@ def main():
     ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
     sw = pso.Swarm(spec.fitness, spec.N, spec.D, spec.box, spec.w, spec.c1, spec.c2, spec.vmax, spec.seed,
                    variant=variant, workspace=ws, stream=stream)
+
+    if args.pmc_probe:
+        sw.reset()
+        for _ in range(20):
+            pso.pso_step(sw.h)
+        torch.cuda.synchronize()
+        src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        sw.close()
+        print(json.dumps({"pmc_probe": True, "step_launches": 20, "copy_bytes": COPY_BYTES,
+                          "source_digest": source_digest()}), flush=True)
+        return
 
     def one_step(ev_a=None, ev_b=None):
         sw.reset()
@@ -147,6 +140,8 @@ def main():
     total_ms = start.elapsed_time(end)
     step_ms = sum(a.elapsed_time(b) for a, b in evs)
     best = sw.best()
+    # pbest improvements of the last timed solve (counted inside the step kernel)
+    rho = sw.counters()["pbest_improvements"] / (spec.N * spec.T)
     sw.close()
 
     ms_per_step = total_ms / args.steps
@@ -154,10 +149,9 @@ def main():
     value = updates * args.steps / (total_ms / 1e3)
     launch_us = step_ms * 1e3 / (args.steps * spec.T)
 
-    rho = improvement_rate(spec, pso, np)
     alg_bytes = spec.N * spec.D * (20.0 + 4.0 * rho) + spec.N * (4.0 + 4.0 * rho)
     achieved = alg_bytes / (launch_us * 1e-6) / 1e9
-    kernel = f"k_step_{args.variant}"
+    kernel = f"k_step<{spec.fitness}, D={spec.D}, {args.variant}>"
     traffic = traffic_from_profiles(kernel, alg_bytes)
 
     out = {

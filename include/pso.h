@@ -139,6 +139,10 @@ int pso_set_state(pso_swarm *s, const float *x_host, const float *v_host, const 
                   const float *pf_host, uint64_t gbest_key, const float *gbest_pos_host, int64_t gbest_iter,
                   int64_t iters_completed);
 
+/* Synchronises and reads the number of pbest improvements (Alg. 1 Step 4)
+ * since the last Step 1 -- the measured improvement rate of the run. */
+int pso_get_counters(pso_swarm *s, uint64_t *pbest_improvements);
+
 /* Blocks until the swarm's enqueued work is done; reports device errors. */
 int pso_sync(pso_swarm *s);
 
@@ -199,6 +203,44 @@ int pso_batch_destroy(pso_batch *b);
 
 /* pso_batch_create + pso_batch_launch + pso_batch_results + destroy. */
 int pso_batch_run(const pso_desc *descs, int64_t count, pso_result *results);
+
+/* ------------------------------------------------------------------------ */
+/* Request server: solves arrive over time (the real-time uses of Sec. 1).   */
+/* Requests are admitted in arrival order as device memory allows; admitted  */
+/* swarms stay resident and advance together, up to chunk_iters iterations   */
+/* per launch, with two launches in flight so that new arrivals start while  */
+/* others run.  A request's result is the same bits as pso_create + pso_run  */
+/* (synchronous) of the same descriptor alone.  Thread-safe: submit and poll */
+/* may be called from any host thread.                                       */
+/* ------------------------------------------------------------------------ */
+typedef struct pso_server pso_server;
+
+typedef struct pso_server_counters {
+    uint64_t submitted, completed, rejected, queued, launches;
+    size_t mem_budget, mem_used, mem_peak; /* device bytes of swarm state */
+    double p50_ms, p99_ms, max_ms;         /* submit-to-completion latency of completed requests */
+} pso_server_counters;
+
+/* Starts a server with mem_budget bytes of device memory for swarm state
+ * (allocated now) and chunk_iters iterations per launch (<= 0: 64). */
+int pso_server_create(size_t mem_budget, int64_t chunk_iters, pso_server **out);
+
+/* Queues one request (validated as a batch descriptor; the shift is copied)
+ * and returns its ticket. */
+int pso_server_submit(pso_server *srv, const pso_desc *desc, uint64_t *ticket);
+
+/* PSO_EAGAIN while the request is queued or running.  Once it is done, fills
+ * *result (result->gbest_pos as for batches) and the submit-to-completion
+ * latency, forgets the ticket and returns PSO_OK -- or PSO_ENOMEM if the
+ * request needs more memory than the whole budget.  Unknown ticket: EINVAL. */
+int pso_server_poll(pso_server *srv, uint64_t ticket, pso_result *result, double *latency_ms);
+
+/* Counters, memory use and latency percentiles since the server started. */
+int pso_server_stats(pso_server *srv, pso_server_counters *stats);
+
+/* Stops the scheduler (requests still queued or running are dropped) and
+ * frees the server. */
+int pso_server_destroy(pso_server *srv);
 
 #ifdef __cplusplus
 }

@@ -128,6 +128,12 @@ def pso_set_state(h, st):
                   "pso_set_state")
 
 
+def pso_get_counters(h):
+    n = ctypes.c_uint64()
+    _check(lib().pso_get_counters(h, ctypes.byref(n)), "pso_get_counters")
+    return dict(pbest_improvements=n.value)
+
+
 def pso_sync(h):
     return _check(lib().pso_sync(h), "pso_sync")
 
@@ -204,6 +210,59 @@ class Batch:
             pass
 
 
+class Server:
+    """Request server with continuous batching (pso_server_*)."""
+
+    def __init__(self, mem_budget: int, chunk_iters: int = 0):
+        self.h = ctypes.c_void_p()
+        _check(lib().pso_server_create(int(mem_budget), int(chunk_iters), ctypes.byref(self.h)), "pso_server_create")
+        self._D = {}
+
+    def submit(self, spec) -> int:
+        arr, keep = _descs([spec])
+        t = ctypes.c_uint64()
+        _check(lib().pso_server_submit(self.h, arr, ctypes.byref(t)), "pso_server_submit")
+        self._D[t.value] = int(spec.D)
+        return t.value
+
+    def poll(self, ticket):
+        """None while pending; else dict(gbest_fit, gbest_pos, gbest_iter, iters, latency_ms)."""
+        D = self._D.get(ticket, 0)
+        res = _native.PsoResult()
+        pos = np.empty(D, np.float32)
+        res.gbest_pos = pos.ctypes.data if D else None
+        lat = ctypes.c_double()
+        rc = lib().pso_server_poll(self.h, ticket, ctypes.byref(res), ctypes.byref(lat))
+        if rc == PSO_EAGAIN:
+            return None
+        self._D.pop(ticket, None)
+        _check(rc, "pso_server_poll")
+        return dict(gbest_fit=np.float32(res.gbest_value), gbest_pos=pos, gbest_iter=res.gbest_iter,
+                    iters=res.iters, latency_ms=lat.value)
+
+    def stats(self):
+        c = _native.PsoServerCounters()
+        _check(lib().pso_server_stats(self.h, ctypes.byref(c)), "pso_server_stats")
+        return {f: getattr(c, f) for f, _ in c._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            _check(lib().pso_server_destroy(self.h), "pso_server_destroy")
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def pso_batch_run(specs):
     with Batch(specs) as b:
         b.launch()
@@ -253,6 +312,9 @@ class Swarm:
 
     def sync(self):
         pso_sync(self.h)
+
+    def counters(self):
+        return pso_get_counters(self.h)
 
     def close(self):
         if getattr(self, "h", None):

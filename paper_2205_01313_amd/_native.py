@@ -32,6 +32,14 @@ class PsoResult(ctypes.Structure):
                 ("iters", ctypes.c_int64), ("gbest_pos", ctypes.c_void_p)]
 
 
+class PsoServerCounters(ctypes.Structure):
+    """struct pso_server_counters of include/pso.h."""
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("rejected", ctypes.c_uint64),
+                ("queued", ctypes.c_uint64), ("launches", ctypes.c_uint64), ("mem_budget", ctypes.c_size_t),
+                ("mem_used", ctypes.c_size_t), ("mem_peak", ctypes.c_size_t), ("p50_ms", ctypes.c_double),
+                ("p99_ms", ctypes.c_double), ("max_ms", ctypes.c_double)]
+
+
 # name -> (restype, argtypes), in the order of include/pso.h
 SIGNATURES = {
     "pso_last_error": (ctypes.c_char_p, []),
@@ -47,6 +55,7 @@ SIGNATURES = {
     "pso_get_history": (c_int, [c_vp, c_i64, c_i64, P(c_u64)]),
     "pso_get_state": (c_int, [c_vp, P(c_f), P(c_f), P(c_f), P(c_f), P(c_u64), P(c_f), P(c_i64), P(c_i64)]),
     "pso_set_state": (c_int, [c_vp, P(c_f), P(c_f), P(c_f), P(c_f), c_u64, P(c_f), c_i64, c_i64]),
+    "pso_get_counters": (c_int, [c_vp, P(c_u64)]),
     "pso_sync": (c_int, [c_vp]),
     "pso_destroy": (c_int, [c_vp]),
     "pso_batch_create": (c_int, [P(PsoDesc), c_i64, c_vp, P(c_vp)]),
@@ -54,6 +63,11 @@ SIGNATURES = {
     "pso_batch_results": (c_int, [c_vp, P(PsoResult)]),
     "pso_batch_destroy": (c_int, [c_vp]),
     "pso_batch_run": (c_int, [P(PsoDesc), c_i64, P(PsoResult)]),
+    "pso_server_create": (c_int, [c_size, c_i64, P(c_vp)]),
+    "pso_server_submit": (c_int, [c_vp, P(PsoDesc), P(c_u64)]),
+    "pso_server_poll": (c_int, [c_vp, c_u64, P(PsoResult), P(ctypes.c_double)]),
+    "pso_server_stats": (c_int, [c_vp, P(PsoServerCounters)]),
+    "pso_server_destroy": (c_int, [c_vp]),
 }
 
 _lib = None

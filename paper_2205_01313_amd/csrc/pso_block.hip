@@ -32,6 +32,7 @@ struct SwarmLoop {
     long long giter;         // iteration of the last gbest change
     long long t;             // iterations completed
     bool stop;
+    uint32_t improved;       // this lane's pbest improvements (block_iterate)
 };
 
 __device__ __forceinline__ bool meets_tol(unsigned long long key, float tol, float fstar)
@@ -89,14 +90,17 @@ template <int FIT>
 __device__ void block_iterate(const SwarmArgs &a, long long T, float tol, float fstar, const float *s_shift,
                               float *s_g, unsigned long long *s_min, unsigned long long *hist, SwarmLoop &L)
 {
+    uint32_t n_imp = 0; // this lane's pbest improvements over the run
     const int D = a.D;
     L.stop = L.stop || meets_tol(L.gkey, tol, fstar);
     for (long long it = 0; it < T && !L.stop; ++it) {
         const uint32_t t = (uint32_t)(L.t + 1);
         unsigned long long key = NO_KEY;
         for (uint32_t q = threadIdx.x; 4 * q < a.N; q += BLOCK_SWARM) {
-            const unsigned long long k = iterate_quad<FIT, 0, 1>(a, D, q, t, s_g, s_shift);
+            uint32_t n = 0;
+            const unsigned long long k = iterate_quad<FIT, 0, 1>(a, D, q, t, s_g, s_shift, &n);
             key = k < key ? k : key;
+            n_imp += n;
         }
         unsigned long long *slot = &s_min[t & 1];
         const unsigned long long m = block_min(key, L.gkey, slot);
@@ -111,6 +115,7 @@ __device__ void block_iterate(const SwarmArgs &a, long long T, float tol, float 
         L.stop = meets_tol(L.gkey, tol, fstar);
         __syncthreads();
     }
+    L.improved = n_imp;
 }
 
 // ---------------------------------------------------------------------------
@@ -141,6 +146,7 @@ __global__ void __launch_bounds__(BLOCK_SWARM) k_block_run(SwarmArgs a, long lon
     const float tol = c->tol, fstar = c->fstar;
     __syncthreads();
     block_iterate<FIT>(a, T, tol, fstar, s_shift, s_g, s_min, a.hist, L);
+    if (L.improved) atomicAdd(&c->improved, (unsigned long long)L.improved);
     for (int d = threadIdx.x; d < D; d += BLOCK_SWARM) a.gpos[d] = s_g[d];
     if (threadIdx.x == 0) {
         c->gkey = L.gkey;
@@ -153,15 +159,32 @@ __global__ void __launch_bounds__(BLOCK_SWARM) k_block_run(SwarmArgs a, long lon
 }
 
 // ---------------------------------------------------------------------------
-// Batched: many independent swarms in one persistent launch.
+// Batched: many independent swarms in one persistent launch.  Each launch
+// runs up to `chunk` iterations of every listed swarm and leaves its loop
+// state (BatchResult) and gbest position in device memory, so a later launch
+// resumes it exactly where it stopped: a swarm computes the same bits however
+// its iterations are split over launches.
 // ---------------------------------------------------------------------------
-__global__ void k_batch_reset(unsigned int *next)
+__global__ void k_batch_reset(BatchResult *results, uint32_t count, unsigned int *next)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *next = 0u;
+    if (i < count) {
+        results[i].gkey = NO_KEY;
+        results[i].giter = 0;
+        results[i].iters = 0;
+        results[i].started = 0;
+        results[i].stop = 0;
+    }
+}
+
+__global__ void k_counter_reset(unsigned int *next)
 {
     if (threadIdx.x == 0) *next = 0u;
 }
 
 template <int FIT>
-__device__ void batch_one(const BatchItem &it, BatchResult *res, float *s_g, float *s_shift,
+__device__ void batch_one(const BatchItem &it, BatchResult *res, long long chunk, float *s_g, float *s_shift,
                           unsigned long long *s_min)
 {
     const SwarmArgs &a = it.a;
@@ -171,21 +194,36 @@ __device__ void batch_one(const BatchItem &it, BatchResult *res, float *s_g, flo
         s_min[0] = NO_KEY;
         s_min[1] = NO_KEY;
     }
-    __syncthreads();
     SwarmLoop L;
-    L.stop = false;
-    block_init<FIT>(a, s_shift, s_g, s_min, L);
-    block_iterate<FIT>(a, it.max_iter, it.tol, it.fstar, s_shift, s_g, s_min, nullptr, L);
+    const bool started = res->started != 0u;
+    __syncthreads();
+    if (!started) {
+        L.stop = false;
+        block_init<FIT>(a, s_shift, s_g, s_min, L);
+    } else {
+        L.gkey = res->gkey;
+        L.giter = res->giter;
+        L.t = res->iters;
+        L.stop = res->stop != 0u;
+        for (int d = threadIdx.x; d < D; d += BLOCK_SWARM) s_g[d] = a.gpos[d];
+        __syncthreads();
+    }
+    const long long left = it.max_iter - L.t;
+    block_iterate<FIT>(a, left < chunk ? left : chunk, it.tol, it.fstar, s_shift, s_g, s_min, nullptr, L);
     for (int d = threadIdx.x; d < D; d += BLOCK_SWARM) a.gpos[d] = s_g[d];
     if (threadIdx.x == 0) {
         res->gkey = L.gkey;
         res->giter = L.giter;
         res->iters = L.t;
+        res->stop = L.stop ? 1u : 0u;
+        res->started = 1u;
     }
 }
 
 __global__ void __launch_bounds__(BLOCK_SWARM) k_batch(const BatchItem *items, const uint32_t *order,
-                                                       BatchResult *results, uint32_t count, unsigned int *next)
+                                                       BatchResult *results, uint32_t count, unsigned int *next,
+                                                       long long chunk, BatchResult *out_state, float *out_pos,
+                                                       int pos_stride)
 {
     __shared__ unsigned long long s_min[2];
     __shared__ uint32_t s_idx;
@@ -195,18 +233,21 @@ __global__ void __launch_bounds__(BLOCK_SWARM) k_batch(const BatchItem *items, c
         __syncthreads();
         const uint32_t j = s_idx;
         __syncthreads();
-        if (j >= count) break; // uniform: every workgroup leaves once the queue is empty
+        if (j >= count) break; // uniform: every workgroup leaves once the list is drained
         const uint32_t idx = order[j];
         const BatchItem &it = items[idx];
         float *s_g = s_dyn, *s_shift = s_dyn + it.a.D;
         switch (it.fitness) {
-        case F_SPHERE: batch_one<F_SPHERE>(it, &results[idx], s_g, s_shift, s_min); break;
-        case F_RASTRIGIN: batch_one<F_RASTRIGIN>(it, &results[idx], s_g, s_shift, s_min); break;
-        case F_ROSENBROCK: batch_one<F_ROSENBROCK>(it, &results[idx], s_g, s_shift, s_min); break;
-        case F_ACKLEY: batch_one<F_ACKLEY>(it, &results[idx], s_g, s_shift, s_min); break;
-        default: batch_one<F_CUBIC>(it, &results[idx], s_g, s_shift, s_min); break;
+        case F_SPHERE: batch_one<F_SPHERE>(it, &results[idx], chunk, s_g, s_shift, s_min); break;
+        case F_RASTRIGIN: batch_one<F_RASTRIGIN>(it, &results[idx], chunk, s_g, s_shift, s_min); break;
+        case F_ROSENBROCK: batch_one<F_ROSENBROCK>(it, &results[idx], chunk, s_g, s_shift, s_min); break;
+        case F_ACKLEY: batch_one<F_ACKLEY>(it, &results[idx], chunk, s_g, s_shift, s_min); break;
+        default: batch_one<F_CUBIC>(it, &results[idx], chunk, s_g, s_shift, s_min); break;
         }
         __syncthreads();
+        if (out_state && threadIdx.x == 0) out_state[j] = results[idx];
+        if (out_pos)
+            for (int d = threadIdx.x; d < it.a.D; d += BLOCK_SWARM) out_pos[(size_t)j * pos_stride + d] = s_g[d];
     }
 }
 
@@ -229,12 +270,20 @@ hipError_t launch_block_run(int fitness, const SwarmArgs &a, long long T, hipStr
 
 int batch_block_lanes() { return BLOCK_SWARM; }
 
-hipError_t launch_batch(const BatchItem *items, const uint32_t *order, BatchResult *results, uint32_t count,
-                        unsigned int *next, int maxD, int grid, hipStream_t stream)
+hipError_t launch_batch_reset(BatchResult *results, uint32_t count, unsigned int *next, hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, stream, next);
+    hipLaunchKernelGGL(k_batch_reset, dim3((count + 255) / 256), dim3(256), 0, stream, results, count, next);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch(const BatchItem *items, const uint32_t *order, BatchResult *results, uint32_t count,
+                        unsigned int *next, int maxD, int grid, long long chunk, hipStream_t stream,
+                        BatchResult *out_state, float *out_pos)
+{
+    hipLaunchKernelGGL(k_counter_reset, dim3(1), dim3(64), 0, stream, next);
     const size_t lds = 2 * sizeof(float) * maxD;
-    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(BLOCK_SWARM), lds, stream, items, order, results, count, next);
+    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(BLOCK_SWARM), lds, stream, items, order, results, count, next,
+                       chunk, out_state, out_pos, maxD);
     return hipGetLastError();
 }
 

@@ -52,6 +52,16 @@ constexpr int64_t BLOCK_RUN_MAX_ND = PSO_BLOCK_RUN_MAX_ND;
 
 } // namespace
 
+// Shared with pso_server.hip (C++ linkage, not part of the C ABI).
+int pso_internal_fail(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
 struct pso_swarm {
     int fitness = 0;
     int variant = PSO_SYNC;
@@ -86,6 +96,24 @@ int check_params(int fitness_id, int64_t N, int32_t D, const float bounds[2], fl
     if (!std::isfinite(bounds[1] - bounds[0])) return fail(PSO_EINVAL, "bounds span overflows");
     return PSO_OK;
 }
+
+} // namespace
+
+// Checks one request / batch descriptor (pso_create's rules plus the run
+// limits); shared with pso_server.hip.
+int pso_internal_check_desc(const pso_desc *d)
+{
+    int rc = check_params(d->fitness_id, d->N, d->D, d->bounds, d->w, d->c1, d->c2, d->vmax);
+    if (rc) return rc;
+    if (d->max_iter < 0 || d->max_iter >= (int64_t(1) << 32) - 1) return fail(PSO_EINVAL, "max_iter out of range");
+    if (std::isnan(d->tol) || std::isnan(d->f_star)) return fail(PSO_EINVAL, "tol and f_star must not be NaN");
+    if (d->shift)
+        for (int k = 0; k < d->D; ++k)
+            if (!std::isfinite(d->shift[k])) return fail(PSO_EINVAL, "shift[%d] is not finite", k);
+    return PSO_OK;
+}
+
+namespace {
 
 int enqueue_init(pso_swarm *s)
 {
@@ -375,6 +403,15 @@ int pso_set_state(pso_swarm *s, const float *x_host, const float *v_host, const 
     return PSO_OK;
 }
 
+int pso_get_counters(pso_swarm *s, uint64_t *pbest_improvements)
+{
+    if (!s) return fail(PSO_EINVAL, "swarm is NULL");
+    int rc = fetch_ctrl(s, false);
+    if (rc) return rc;
+    if (pbest_improvements) *pbest_improvements = s->host_ctrl->improved;
+    return PSO_OK;
+}
+
 int pso_sync(pso_swarm *s)
 {
     if (!s) return fail(PSO_EINVAL, "swarm is NULL");
@@ -443,14 +480,8 @@ int pso_batch_create(const pso_desc *descs, int64_t count, void *hip_stream, pso
     int maxD = 1;
     for (int64_t i = 0; i < count; ++i) {
         const pso_desc &d = descs[i];
-        int rc = check_params(d.fitness_id, d.N, d.D, d.bounds, d.w, d.c1, d.c2, d.vmax);
+        int rc = pso_internal_check_desc(&d);
         if (rc) return fail(rc, "descriptor %lld: %s", (long long)i, std::string(g_err).c_str());
-        if (d.max_iter < 0 || d.max_iter >= (int64_t(1) << 32) - 1)
-            return fail(PSO_EINVAL, "descriptor %lld: max_iter out of range", (long long)i);
-        if (std::isnan(d.tol) || std::isnan(d.f_star)) return fail(PSO_EINVAL, "descriptor %lld: NaN tol/f_star", (long long)i);
-        if (d.shift)
-            for (int k = 0; k < d.D; ++k)
-                if (!std::isfinite(d.shift[k])) return fail(PSO_EINVAL, "descriptor %lld: shift not finite", (long long)i);
         lay[i] = pso::layout_of((uint64_t)d.N, d.D, false);
         off[i] = total;
         total += lay[i].total;
@@ -530,8 +561,9 @@ int pso_batch_create(const pso_desc *descs, int64_t count, void *hip_stream, pso
 int pso_batch_launch(pso_batch *b)
 {
     if (!b) return fail(PSO_EINVAL, "batch is NULL");
+    HIP_TRY(pso::launch_batch_reset(b->d_results, (uint32_t)b->count, b->d_next, b->stream));
     HIP_TRY(pso::launch_batch(b->d_items, b->d_order, b->d_results, (uint32_t)b->count, b->d_next, b->maxD, b->grid,
-                              b->stream));
+                              (long long)1 << 62, b->stream));
     return PSO_OK;
 }
 

@@ -111,6 +111,22 @@ __device__ __forceinline__ unsigned long long workgroup_min(unsigned long long k
     return *wg_min;
 }
 
+// Adds the workgroup's pbest improvements to the control block's counter
+// (wavefront sums, one LDS add per wavefront, one device add per workgroup;
+// the device add happens after the barrier in workgroup_min).
+__device__ __forceinline__ void count_improvements(Ctrl *c, uint32_t n, unsigned int *wg_count)
+{
+    uint32_t s = n;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    if ((threadIdx.x & 63) == 0 && s) atomicAdd(wg_count, s);
+}
+
+__device__ __forceinline__ void flush_count(Ctrl *c, const unsigned int *wg_count)
+{
+    if (threadIdx.x == 0 && *wg_count) atomicAdd(&c->improved, (unsigned long long)*wg_count);
+}
+
 // Arrival count: true in every lane of the last workgroup of the launch,
 // after an acquire fence.
 __device__ __forceinline__ bool arrive_last(Ctrl *c, int *last_flag)
@@ -255,6 +271,7 @@ __global__ void k_reset(SwarmArgs a)
     if (threadIdx.x != 0) return;
     Ctrl *c = a.ctrl;
     c->gkey = NO_KEY;
+    c->improved = 0;
     c->arrive = 0;
     c->gkey_prev = NO_KEY;
     c->giter = 0;
@@ -312,6 +329,7 @@ __global__ void PSO_STEP_ATTR k_step(SwarmArgs a)
 {
     __shared__ unsigned long long wg_min;
     __shared__ unsigned long long snap_key;
+    __shared__ unsigned int wg_count;
     __shared__ int flag;
     extern __shared__ float s_dyn[]; // gbest position (D floats), then shift (D floats)
     Ctrl *c = a.ctrl;
@@ -323,7 +341,10 @@ __global__ void PSO_STEP_ATTR k_step(SwarmArgs a)
         if (VAR == VAR_SYNC) s_g[d] = a.gpos[d];
         s_shift[d] = a.shift[d];
     }
-    if (threadIdx.x == 0) wg_min = NO_KEY;
+    if (threadIdx.x == 0) {
+        wg_min = NO_KEY;
+        wg_count = 0;
+    }
     unsigned long long thr;
     if (VAR == VAR_SYNC) {
         thr = c->gkey_prev;
@@ -332,9 +353,12 @@ __global__ void PSO_STEP_ATTR k_step(SwarmArgs a)
         thr = snapshot_async(a, s_g, &snap_key); // ends with a barrier
     }
     const uint32_t q = blockIdx.x * BLOCK + threadIdx.x;
+    uint32_t n_imp = 0;
     const unsigned long long key =
-        (4 * q < a.N) ? iterate_quad<FIT, DC, PSO_STEP_UNROLL>(a, D, q, t, s_g, s_shift) : NO_KEY;
+        (4 * q < a.N) ? iterate_quad<FIT, DC, PSO_STEP_UNROLL>(a, D, q, t, s_g, s_shift, &n_imp) : NO_KEY;
+    count_improvements(c, n_imp, &wg_count);
     const unsigned long long m = workgroup_min(key, thr, &wg_min);
+    flush_count(c, &wg_count);
     if (VAR == VAR_SYNC) {
         publish_sync(c, m, thr);
     } else {

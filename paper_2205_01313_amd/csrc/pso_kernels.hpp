@@ -15,7 +15,8 @@ constexpr int HIST_CAP = 8192; // gbest keys kept per swarm (ring, power of two)
 struct alignas(256) Ctrl {
     // line 0: running minimum key of the current iteration (atomicMin target)
     unsigned long long gkey;
-    unsigned char pad0[248];
+    unsigned long long improved; // pbest improvements since Step 1 (one add per workgroup)
+    unsigned char pad0[240];
     // line 1: workgroups that finished the current launch
     unsigned int arrive;
     unsigned char pad1[252];

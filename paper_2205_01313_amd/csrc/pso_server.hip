@@ -1,0 +1,457 @@
+// pso_server.hip -- request server with continuous batching.
+//
+// Motivation: the paper targets real-time uses of PSO (object tracking,
+// posture estimation; Sec. 1), where solves arrive over time.  Requests
+// (pso_desc) are admitted in arrival order as device memory frees up (the
+// Arena/Admission bookkeeping of pso_arena.hpp), their swarm state stays
+// resident on the device, and a scheduler thread keeps up to two batched
+// launches in flight on two streams: each launch runs up to `chunk`
+// iterations of every swarm in its set (Step 1 first for new swarms), so
+// requests that arrive while a launch runs start on the other stream and
+// overlap on the device.  Between launches a swarm's loop state stays in
+// device memory, so its result is the same bits as running it alone.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "pso.h"
+#include "pso_arena.hpp"
+#include "pso_block.hpp"
+#include "pso_device.hpp"
+#include "pso_kernels.hpp"
+
+int pso_internal_fail(int code, const char *fmt, ...);
+int pso_internal_check_desc(const pso_desc *d);
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+double ms_since(Clock::time_point t0, Clock::time_point t1)
+{
+    return std::chrono::duration<double, std::milli>(t1 - t0).count();
+}
+
+struct Req {
+    uint64_t ticket = 0;
+    pso_desc d{};
+    std::vector<float> shift;
+    Clock::time_point t_submit, t_done;
+    int status = PSO_EAGAIN; // PSO_OK when done, PSO_ENOMEM when rejected
+    size_t off = 0;
+    int slot = -1;
+    pso::BatchResult res{};
+    std::vector<float> gpos;
+};
+
+constexpr int STREAMS = 2;
+
+} // namespace
+
+struct pso_server {
+    // configuration
+    size_t budget = 0;
+    long long chunk = 64;
+    int max_slots = 0;
+    int grid_cap = 1;
+    // device memory
+    void *base = nullptr;
+    pso::BatchItem *d_items = nullptr;
+    pso::BatchResult *d_state = nullptr;
+    uint32_t *d_order[STREAMS] = {};
+    unsigned int *d_next[STREAMS] = {};
+    pso::BatchResult *d_out[STREAMS] = {}; // compact state of a launch's items
+    float *d_opos[STREAMS] = {};           // compact gbest positions (cap_pos floats)
+    size_t cap_pos[STREAMS] = {};
+    int launch_maxD[STREAMS] = {};
+    // pinned staging
+    pso::BatchItem *h_items = nullptr;   // max_slots
+    pso::BatchResult *h_state = nullptr; // max_slots (fresh state for new swarms)
+    uint32_t *h_order[STREAMS] = {};
+    pso::BatchResult *h_out[STREAMS] = {};
+    std::vector<float> h_opos[STREAMS];
+    hipStream_t st[STREAMS] = {};
+    hipEvent_t ev[STREAMS] = {};
+    // bookkeeping (guarded by mu)
+    std::mutex mu;
+    std::condition_variable cv;
+    pso::Arena arena;
+    pso::Admission adm{&arena};
+    std::unordered_map<uint64_t, std::unique_ptr<Req>> reqs;
+    uint64_t next_ticket = 1;
+    std::vector<int> free_slots;
+    std::vector<Req *> slot_req;
+    // scheduler-thread state
+    std::vector<int> ready;              // started or new swarms not in flight
+    std::vector<int> fresh;              // slots whose item/state must be uploaded
+    std::vector<int> inflight[STREAMS];  // slots of each in-flight launch
+    bool busy[STREAMS] = {};
+    std::thread th;
+    std::atomic<bool> quit{false};
+    std::atomic<int> device_error{0};
+    // statistics (guarded by mu)
+    uint64_t submitted = 0, completed = 0, rejected = 0, launches = 0;
+    size_t peak_used = 0;
+    std::vector<double> latencies;
+};
+
+namespace {
+
+void server_loop(pso_server *s);
+
+void server_free(pso_server *s)
+{
+    if (!s) return;
+    for (int k = 0; k < STREAMS; ++k) {
+        if (s->st[k]) (void)hipStreamSynchronize(s->st[k]);
+    }
+    (void)hipFree(s->base);
+    (void)hipFree(s->d_items);
+    (void)hipFree(s->d_state);
+    for (int k = 0; k < STREAMS; ++k) {
+        (void)hipFree(s->d_order[k]);
+        (void)hipFree(s->d_next[k]);
+        (void)hipFree(s->d_out[k]);
+        (void)hipFree(s->d_opos[k]);
+        (void)hipHostFree(s->h_order[k]);
+        (void)hipHostFree(s->h_out[k]);
+        if (s->ev[k]) (void)hipEventDestroy(s->ev[k]);
+        if (s->st[k]) (void)hipStreamDestroy(s->st[k]);
+    }
+    (void)hipHostFree(s->h_items);
+    (void)hipHostFree(s->h_state);
+    delete s;
+}
+
+// Item of a newly admitted request, bound to its arena range.
+pso::BatchItem make_item(pso_server *s, const Req &r)
+{
+    const pso::Layout L = pso::layout_of((uint64_t)r.d.N, r.d.D, false);
+    pso::BatchItem it{};
+    it.a = pso::bind(static_cast<char *>(s->base) + r.off, L, (uint64_t)r.d.N, r.d.D);
+    it.a.lo = r.d.bounds[0];
+    it.a.hi = r.d.bounds[1];
+    it.a.w = r.d.w;
+    it.a.c1 = r.d.c1;
+    it.a.c2 = r.d.c2;
+    it.a.vmax = r.d.vmax;
+    it.a.k0 = (uint32_t)r.d.seed;
+    it.a.k1 = (uint32_t)(r.d.seed >> 32);
+    it.fitness = r.d.fitness_id;
+    it.max_iter = r.d.max_iter;
+    it.tol = r.d.tol;
+    it.fstar = r.d.f_star;
+    return it;
+}
+
+// Launches one chunk over every ready swarm on stream k.
+bool launch_ready(pso_server *s, int k)
+{
+    if (s->ready.empty()) return true;
+    hipStream_t st = s->st[k];
+    // upload the items, fresh loop states and shift vectors of new swarms
+    for (int slot : s->fresh) {
+        Req *r = s->slot_req[slot];
+        if (hipMemcpyAsync(&s->d_items[slot], &s->h_items[slot], sizeof(pso::BatchItem), hipMemcpyHostToDevice, st) !=
+                hipSuccess ||
+            hipMemcpyAsync(&s->d_state[slot], &s->h_state[slot], sizeof(pso::BatchResult), hipMemcpyHostToDevice, st) !=
+                hipSuccess ||
+            hipMemcpyAsync(const_cast<float *>(s->h_items[slot].a.shift), r->shift.data(), sizeof(float) * r->d.D,
+                           hipMemcpyHostToDevice, st) != hipSuccess)
+            return false;
+    }
+    s->fresh.clear();
+    const int n = (int)s->ready.size();
+    int maxD = 1;
+    for (int j = 0; j < n; ++j) {
+        s->h_order[k][j] = (uint32_t)s->ready[j];
+        maxD = std::max(maxD, (int)s->slot_req[s->ready[j]]->d.D);
+    }
+    if (hipMemcpyAsync(s->d_order[k], s->h_order[k], sizeof(uint32_t) * n, hipMemcpyHostToDevice, st) != hipSuccess)
+        return false;
+    const size_t need = (size_t)n * maxD;
+    if (need > s->cap_pos[k]) { // grow the compact position buffer
+        if (hipStreamSynchronize(st) != hipSuccess) return false;
+        (void)hipFree(s->d_opos[k]);
+        s->d_opos[k] = nullptr;
+        s->cap_pos[k] = std::max(need, 2 * s->cap_pos[k]);
+        if (hipMalloc(&s->d_opos[k], sizeof(float) * s->cap_pos[k]) != hipSuccess) return false;
+    }
+    const int grid = std::min(n, s->grid_cap);
+    if (pso::launch_batch(s->d_items, s->d_order[k], s->d_state, (uint32_t)n, s->d_next[k], maxD, grid, s->chunk, st,
+                          s->d_out[k], s->d_opos[k]) != hipSuccess)
+        return false;
+    if (hipMemcpyAsync(s->h_out[k], s->d_out[k], sizeof(pso::BatchResult) * n, hipMemcpyDeviceToHost, st) != hipSuccess)
+        return false;
+    if (hipEventRecord(s->ev[k], st) != hipSuccess) return false;
+    s->launch_maxD[k] = maxD;
+    s->inflight[k].swap(s->ready);
+    s->ready.clear();
+    s->busy[k] = true;
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        ++s->launches;
+    }
+    return true;
+}
+
+// Collects a finished launch (its compact states are already on the host):
+// completed swarms return their result and memory; the others become ready.
+bool collect(pso_server *s, int k)
+{
+    hipStream_t st = s->st[k];
+    const int n = (int)s->inflight[k].size();
+    const int maxD = s->launch_maxD[k];
+    std::vector<int> done_j;
+    for (int j = 0; j < n; ++j) {
+        const int slot = s->inflight[k][j];
+        Req *r = s->slot_req[slot];
+        r->res = s->h_out[k][j];
+        if (r->res.stop || r->res.iters >= r->d.max_iter)
+            done_j.push_back(j);
+        else
+            s->ready.push_back(slot);
+    }
+    if (!done_j.empty()) {
+        s->h_opos[k].resize((size_t)n * maxD);
+        if (hipMemcpyAsync(s->h_opos[k].data(), s->d_opos[k], sizeof(float) * n * maxD, hipMemcpyDeviceToHost, st) !=
+                hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return false;
+    }
+    const auto now = Clock::now();
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        for (int j : done_j) {
+            const int slot = s->inflight[k][j];
+            Req *r = s->slot_req[slot];
+            r->gpos.assign(s->h_opos[k].begin() + (size_t)j * maxD, s->h_opos[k].begin() + (size_t)j * maxD + r->d.D);
+            r->t_done = now;
+            r->status = PSO_OK;
+            s->latencies.push_back(ms_since(r->t_submit, now));
+            ++s->completed;
+            s->arena.release(r->off);
+            s->slot_req[slot] = nullptr;
+            s->free_slots.push_back(slot);
+        }
+        if (!done_j.empty()) s->cv.notify_all();
+    }
+    s->inflight[k].clear();
+    s->busy[k] = false;
+    return true;
+}
+
+void server_loop(pso_server *s)
+{
+    while (!s->quit.load()) {
+        bool progressed = false;
+        // admission
+        {
+            std::vector<std::pair<uint64_t, size_t>> admitted;
+            std::vector<uint64_t> rejected;
+            std::lock_guard<std::mutex> g(s->mu);
+            s->adm.admit(&admitted, &rejected, s->free_slots.size());
+            for (uint64_t t : rejected) {
+                Req *r = s->reqs[t].get();
+                r->status = PSO_ENOMEM;
+                r->t_done = Clock::now();
+                ++s->rejected;
+                progressed = true;
+            }
+            for (auto &ad : admitted) {
+                Req *r = s->reqs[ad.first].get();
+                r->off = ad.second;
+                r->slot = s->free_slots.back();
+                s->free_slots.pop_back();
+                s->slot_req[r->slot] = r;
+                s->h_items[r->slot] = make_item(s, *r);
+                s->h_state[r->slot] = pso::BatchResult{pso::NO_KEY, 0, 0, 0u, 0u};
+                s->fresh.push_back(r->slot);
+                s->ready.push_back(r->slot);
+                progressed = true;
+            }
+            s->peak_used = std::max(s->peak_used, s->arena.used());
+            if (!rejected.empty()) s->cv.notify_all();
+        }
+        // collect finished launches, then launch on free streams
+        for (int k = 0; k < STREAMS; ++k) {
+            if (s->busy[k]) {
+                const hipError_t q = hipEventQuery(s->ev[k]);
+                if (q == hipSuccess) {
+                    if (!collect(s, k)) s->device_error.store(1);
+                    progressed = true;
+                } else if (q != hipErrorNotReady) {
+                    s->device_error.store(1);
+                }
+            }
+        }
+        for (int k = 0; k < STREAMS; ++k) {
+            if (!s->busy[k] && !s->ready.empty()) {
+                if (!launch_ready(s, k)) s->device_error.store(1);
+                progressed = true;
+            }
+        }
+        if (s->device_error.load()) {
+            std::lock_guard<std::mutex> g(s->mu);
+            s->cv.notify_all();
+            break;
+        }
+        if (!progressed) {
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv.wait_for(lk, std::chrono::microseconds(50));
+        }
+    }
+}
+
+} // namespace
+
+extern "C" {
+
+int pso_server_create(size_t mem_budget, int64_t chunk_iters, pso_server **out)
+{
+    if (!out) return pso_internal_fail(PSO_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (mem_budget < 4096) return pso_internal_fail(PSO_EINVAL, "mem_budget too small");
+    pso_server *s = new (std::nothrow) pso_server();
+    if (!s) return pso_internal_fail(PSO_ENOMEM, "host allocation failed");
+    s->budget = mem_budget;
+    s->chunk = chunk_iters > 0 ? chunk_iters : 64;
+    s->arena = pso::Arena(mem_budget);
+    // at most one slot per 64 KiB of budget, within [64, 65536]
+    s->max_slots = (int)std::min<size_t>(65536, std::max<size_t>(64, mem_budget / 65536));
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                                hipSuccess) {
+        server_free(s);
+        return pso_internal_fail(PSO_EDEVICE, "device query failed");
+    }
+    if (pso::batch_occupancy(64, &per_cu) != hipSuccess) per_cu = 1;
+    s->grid_cap = std::max(1, cus * std::max(1, per_cu));
+    bool ok = hipMalloc(&s->base, mem_budget) == hipSuccess &&
+              hipMalloc(&s->d_items, sizeof(pso::BatchItem) * s->max_slots) == hipSuccess &&
+              hipMalloc(&s->d_state, sizeof(pso::BatchResult) * s->max_slots) == hipSuccess &&
+              hipHostMalloc(reinterpret_cast<void **>(&s->h_items), sizeof(pso::BatchItem) * s->max_slots,
+                            hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc(reinterpret_cast<void **>(&s->h_state), sizeof(pso::BatchResult) * s->max_slots,
+                            hipHostMallocDefault) == hipSuccess;
+    for (int k = 0; ok && k < STREAMS; ++k) {
+        ok = hipMalloc(&s->d_order[k], sizeof(uint32_t) * s->max_slots) == hipSuccess &&
+             hipMalloc(&s->d_next[k], sizeof(unsigned int)) == hipSuccess &&
+             hipMalloc(&s->d_out[k], sizeof(pso::BatchResult) * s->max_slots) == hipSuccess &&
+             hipHostMalloc(reinterpret_cast<void **>(&s->h_out[k]), sizeof(pso::BatchResult) * s->max_slots,
+                           hipHostMallocDefault) == hipSuccess &&
+             hipHostMalloc(reinterpret_cast<void **>(&s->h_order[k]), sizeof(uint32_t) * s->max_slots,
+                           hipHostMallocDefault) == hipSuccess &&
+             hipStreamCreateWithFlags(&s->st[k], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&s->ev[k], hipEventDisableTiming) == hipSuccess;
+    }
+    if (!ok) {
+        server_free(s);
+        return pso_internal_fail(PSO_ENOMEM, "device or pinned allocation for the server failed");
+    }
+    s->slot_req.assign(s->max_slots, nullptr);
+    for (int k = s->max_slots - 1; k >= 0; --k) s->free_slots.push_back(k);
+    s->th = std::thread(server_loop, s);
+    *out = s;
+    return PSO_OK;
+}
+
+int pso_server_submit(pso_server *s, const pso_desc *d, uint64_t *ticket)
+{
+    if (!s || !d || !ticket) return pso_internal_fail(PSO_EINVAL, "NULL argument");
+    int rc = pso_internal_check_desc(d);
+    if (rc) return rc;
+    if (s->device_error.load()) return pso_internal_fail(PSO_EDEVICE, "server stopped after a device error");
+    auto r = std::make_unique<Req>();
+    r->d = *d;
+    r->shift.assign(d->D, 0.0f);
+    if (d->shift) std::memcpy(r->shift.data(), d->shift, sizeof(float) * d->D);
+    r->d.shift = nullptr;
+    r->t_submit = Clock::now();
+    const size_t bytes = pso::layout_of((uint64_t)d->N, d->D, false).total;
+    std::lock_guard<std::mutex> g(s->mu);
+    r->ticket = s->next_ticket++;
+    *ticket = r->ticket;
+    s->adm.push(pso::Pending{r->ticket, bytes});
+    s->reqs[r->ticket] = std::move(r);
+    ++s->submitted;
+    s->cv.notify_all();
+    return PSO_OK;
+}
+
+int pso_server_poll(pso_server *s, uint64_t ticket, pso_result *result, double *latency_ms)
+{
+    if (!s) return pso_internal_fail(PSO_EINVAL, "server is NULL");
+    std::lock_guard<std::mutex> g(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return pso_internal_fail(PSO_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    Req *r = it->second.get();
+    if (r->status == PSO_EAGAIN) {
+        if (s->device_error.load()) return pso_internal_fail(PSO_EDEVICE, "server stopped after a device error");
+        return PSO_EAGAIN;
+    }
+    const int status = r->status;
+    if (result) {
+        result->status = status;
+        if (status == PSO_OK) {
+            result->gbest_value = pso::key_fitness(r->res.gkey);
+            result->gbest_iter = r->res.giter;
+            result->iters = r->res.iters;
+            if (result->gbest_pos) std::memcpy(result->gbest_pos, r->gpos.data(), sizeof(float) * r->d.D);
+        }
+    }
+    if (latency_ms) *latency_ms = ms_since(r->t_submit, r->t_done);
+    s->reqs.erase(it);
+    if (status != PSO_OK) return pso_internal_fail(status, "request %llu needs more device memory than the budget",
+                                                   (unsigned long long)ticket);
+    return PSO_OK;
+}
+
+int pso_server_stats(pso_server *s, pso_server_counters *out)
+{
+    if (!s || !out) return pso_internal_fail(PSO_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> g(s->mu);
+    out->submitted = s->submitted;
+    out->completed = s->completed;
+    out->rejected = s->rejected;
+    out->queued = s->adm.queued();
+    out->launches = s->launches;
+    out->mem_budget = s->budget;
+    out->mem_used = s->arena.used();
+    out->mem_peak = s->peak_used;
+    std::vector<double> l = s->latencies;
+    out->p50_ms = out->p99_ms = out->max_ms = 0.0;
+    if (!l.empty()) {
+        std::sort(l.begin(), l.end());
+        auto q = [&](double f) { return l[std::min(l.size() - 1, (size_t)(f * (l.size() - 1) + 0.5))]; };
+        out->p50_ms = q(0.50);
+        out->p99_ms = q(0.99);
+        out->max_ms = l.back();
+    }
+    return PSO_OK;
+}
+
+int pso_server_destroy(pso_server *s)
+{
+    if (!s) return pso_internal_fail(PSO_EINVAL, "server is NULL");
+    s->quit.store(true);
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        s->cv.notify_all();
+    }
+    if (s->th.joinable()) s->th.join();
+    server_free(s);
+    return PSO_OK;
+}
+
+} // extern "C"

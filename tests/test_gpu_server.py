@@ -1,0 +1,112 @@
+"""Request server (continuous batching): every request's result is the same
+bits as the same swarm run alone (pso_create + pso_run, synchronous), in any
+mix and arrival pattern; admission never exceeds the memory budget."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import paper_2205_01313_amd as pso
+from paper_2205_01313_amd import workloads as wl
+from tests.gpu_util import announce, gpu_swarm
+from tests.test_gpu_batch import mixed_specs
+
+pytestmark = pytest.mark.gpu
+
+
+def alone(sp):
+    with gpu_swarm(sp) as g:
+        return g.run(sp.T, tol=getattr(sp, "tol", 0.0), f_star=getattr(sp, "f_star", 0.0))
+
+
+def wait_all(srv, tickets, timeout=120.0):
+    out = {}
+    t0 = time.time()
+    while len(out) < len(tickets):
+        for t in tickets:
+            if t not in out:
+                r = srv.poll(t)
+                if r is not None:
+                    out[t] = r
+        assert time.time() - t0 < timeout, f"{len(out)}/{len(tickets)} done"
+        time.sleep(0.001)
+    return out
+
+
+def check_same(specs, tickets, res):
+    for sp, t in zip(specs, tickets):
+        a = alone(sp)
+        r = res[t]
+        assert r["gbest_fit"] == a["gbest_fit"], sp
+        assert r["gbest_iter"] == a["gbest_iter"] and r["iters"] == a["iters"], sp
+        assert np.array_equal(r["gbest_pos"], a["gbest_pos"]), sp
+
+
+def test_results_equal_alone_with_staggered_arrivals():
+    specs = mixed_specs(120, 11, max_iter=300)
+    announce("server: 120 staggered requests")
+    with pso.Server(1 << 30, chunk_iters=16) as srv:
+        tickets = []
+        for k, sp in enumerate(specs):
+            tickets.append(srv.submit(sp))
+            if k % 10 == 9:
+                time.sleep(0.002)  # let launches start between arrivals
+        res = wait_all(srv, tickets)
+        st = srv.stats()
+    assert st["completed"] == len(specs) and st["rejected"] == 0
+    assert st["launches"] > 1
+    check_same(specs, tickets, res)
+
+
+def test_small_budget_admits_in_stages_and_never_exceeds_it():
+    specs = [wl.SwarmSpec("rastrigin", 2000, 16, 120, seed=k) for k in range(30)]
+    need = pso.pso_workspace_bytes(2000, 16)
+    budget = 3 * need  # a few swarms at a time
+    announce("server: small budget")
+    with pso.Server(budget, chunk_iters=8) as srv:
+        tickets = [srv.submit(sp) for sp in specs]
+        res = wait_all(srv, tickets)
+        st = srv.stats()
+    assert st["completed"] == 30 and st["mem_peak"] <= budget and st["mem_used"] == 0
+    check_same(specs[:6], tickets[:6], res)
+
+
+def test_oversize_request_is_rejected_and_others_continue():
+    big = wl.SwarmSpec("sphere", 100000, 64, 10, seed=1)
+    small = wl.SwarmSpec("sphere", 64, 2, 10, seed=2)
+    with pso.Server(1 << 20) as srv:
+        tb = srv.submit(big)
+        ts = srv.submit(small)
+        t0 = time.time()
+        while True:
+            try:
+                r = srv.poll(tb)
+            except pso.PsoError as e:
+                assert e.code == pso.PSO_ENOMEM
+                break
+            assert r is None and time.time() - t0 < 30
+            time.sleep(0.001)
+        rs = wait_all(srv, [ts])[ts]
+        assert rs["iters"] == 10
+        with pytest.raises(pso.PsoError) as e:
+            srv.poll(987654)
+        assert e.value.code == pso.PSO_EINVAL
+
+
+def test_submit_from_two_threads():
+    specs = mixed_specs(60, 12, max_iter=80)
+    with pso.Server(1 << 30, chunk_iters=32) as srv:
+        tickets = [None] * len(specs)
+
+        def worker(lo):
+            for k in range(lo, len(specs), 2):
+                tickets[k] = srv.submit(specs[k])
+
+        th = [threading.Thread(target=worker, args=(i,)) for i in (0, 1)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        res = wait_all(srv, tickets)
+    check_same(specs[:10], tickets[:10], res)

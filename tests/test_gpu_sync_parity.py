@@ -170,3 +170,20 @@ def test_history_window_errors():
         with pytest.raises(pso.PsoError) as e:
             g.history(0, 7)
         assert e.value.code == pso.PSO_ESTATE
+
+
+def test_improvement_counter_matches_oracle():
+    """pso_get_counters counts Step 4 improvements; the oracle's count is the
+    number of pf decreases over the same iterations (grid and one-workgroup
+    paths)."""
+    for spec in (wl.SwarmSpec("rastrigin", 70000, 6, 15, seed=8), wl.SwarmSpec("ackley", 900, 5, 15, seed=8)):
+        osw = oracle_swarm(spec, nthreads=16)
+        st = osw.init_f32()
+        n = 0
+        for t in range(1, spec.T + 1):
+            prev = st["pf"].copy()
+            osw.step_f32(st, t)
+            n += int(np.count_nonzero(st["pf"] < prev))
+        with gpu_swarm(spec) as g:
+            g.run(spec.T)
+            assert g.counters()["pbest_improvements"] == n
