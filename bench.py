@@ -8,7 +8,11 @@ Step 1 (initialisation) plus 200 iterations, with all state resident in HBM.
 Prints one JSON line: throughput in particle-dimension updates per second
 (fitness included), the step kernel's roofline figures measured with HIP
 events on the stream the kernels run on, and the CPU oracle's rate on a
-bounded sample of the same workload.
+bounded sample of the same workload.  Extra legs (same line): the
+asynchronous variant on the same workload; a batch of 4096 uneven swarms in
+one persistent launch with its speedup over a plain per-swarm pso_run loop
+on a subset; and the request server under Poisson arrivals (p50/p99 latency
+and throughput per arrival rate).
 """
 from __future__ import annotations
 
@@ -26,25 +30,31 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 COPY_BYTES = 256 << 20  # calibration copy: reads and writes this many bytes
 
 
+# Sources that define the grid step kernel: a counter summary taken on other
+# sources is stale.
+STEP_SOURCES = ["pso_device.hpp", "pso_quad.hpp", "pso_kernels.hpp", "pso_kernels.hip"]
+
+
 def source_digest() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2205_01313_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
+    for name in STEP_SOURCES:
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(name.encode() + f.read())
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel: str, launches_bytes_alg: float):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel sources; else None."""
+def traffic_from_profiles(kernel: str):
+    """HBM bytes per launch (FETCH_SIZE and WRITE_SIZE, each scaled by what it
+    reads for a copy of known size) from the committed rocprofv3 counter
+    summary, if it was taken on the current step-kernel sources; else None."""
     path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    ent = rec.get(kernel)
-    if not ent or ent.get("source_digest") != source_digest():
+    ent = rec.get("kernels", {}).get(kernel)
+    if not ent or rec.get("source_digest") != source_digest():
         return None
     return ent["hbm_bytes_per_launch"]
 
@@ -67,6 +77,108 @@ def cpu_baseline(spec, iters: int):
                        f"{dt:.1f} s")
 
 
+def timed_events(torch, stream, fn):
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b)
+
+
+def async_leg(pso, torch, spec, ws, stream):
+    """Asynchronous variant on the same swarm: updates/s over one solve."""
+    sw = pso.Swarm(spec.fitness, spec.N, spec.D, spec.box, spec.w, spec.c1, spec.c2, spec.vmax, spec.seed,
+                   variant=pso.PSO_ASYNC, workspace=ws, stream=stream)
+
+    def solve():
+        sw.reset()
+        for _ in range(spec.T):
+            pso.pso_step(sw.h)
+    solve()
+    ms = timed_events(torch, stream, solve)
+    best = sw.best()
+    sw.close()
+    return dict(value=spec.N * spec.D * spec.T / (ms / 1e3), unit="particle·dim updates/s", ms_per_solve=ms,
+                gbest=float(best["gbest_fit"]))
+
+
+def batched_leg(pso, torch, wl, stream, subset=96):
+    """4096 swarms (N log-uniform in [32, 8192], D in {2..64}, four fitness
+    functions with shifts, 500 iterations) in one persistent launch; and a
+    spread subset run both as a batch and as a plain loop of pso_run calls
+    (one swarm after another, allocation outside the timed loop)."""
+    specs = wl.batch_specs()
+    with pso.Batch(specs, stream=stream) as b:
+        b.launch()
+        torch.cuda.synchronize()
+        ms = timed_events(torch, stream, b.launch)
+        res = b.results(positions=False)
+    updates = sum(sp.N * sp.D * r["iters"] for sp, r in zip(specs, res))
+    sub = specs[:: len(specs) // subset][:subset]
+    with pso.Batch(sub, stream=stream) as b:
+        b.launch()
+        torch.cuda.synchronize()
+        ms_sub = timed_events(torch, stream, b.launch)
+        rb = b.results()
+    swarms = [pso.Swarm(sp.fitness, sp.N, sp.D, sp.box, sp.w, sp.c1, sp.c2, sp.vmax, sp.seed, shift=sp.shift)
+              for sp in sub]
+    t0 = time.perf_counter()
+    rp = [sw.run(sp.T) for sw, sp in zip(swarms, sub)]
+    ms_plain = (time.perf_counter() - t0) * 1e3
+    for sw in swarms:
+        sw.close()
+    same = all(a["gbest_fit"] == c["gbest_fit"] and (a["gbest_pos"] == c["gbest_pos"]).all() for a, c in zip(rb, rp))
+    return dict(swarms=len(specs), iterations=500, ms=ms, value=updates / (ms / 1e3), unit="particle·dim updates/s",
+                subset=len(sub), subset_batched_ms=ms_sub, subset_plain_loop_ms=ms_plain,
+                batched_vs_plain_speedup=ms_plain / ms_sub, equal_results=bool(same))
+
+
+def serving_leg(pso, wl, rates=(2000, 10000, 50000), count=2000, budget=32 << 30, chunk=1 << 20):
+    """Poisson arrivals of solve requests (N lognormal median 512, D in
+    [2, 64], stop at |gbest| < 1e-4 or 1000 iterations) submitted at their
+    arrival times; latency is submit-to-completion inside the server."""
+    import ctypes
+    out = {}
+    for rate in rates:
+        specs = wl.serving_specs(count, seed=rate)
+        arr, keep = pso._descs(specs)
+        times = wl.poisson_arrivals(count, rate, seed=rate)
+        with pso.Server(budget, chunk_updates=chunk) as srv:
+            L = pso.lib()
+            tk = ctypes.c_uint64()
+            tickets = []
+            t0 = time.perf_counter()
+            for k in range(count):
+                while time.perf_counter() - t0 < times[k]:
+                    pass
+                pso._check(L.pso_server_submit(srv.h, ctypes.byref(arr[k]), ctypes.byref(tk)), "submit")
+                tickets.append(tk.value)
+            submit_s = time.perf_counter() - t0
+            pending = set(tickets)
+            res = {}
+            r = pso._native.PsoResult()
+            lat = ctypes.c_double()
+            while pending:
+                for t in list(pending):
+                    rc = L.pso_server_poll(srv.h, t, ctypes.byref(r), ctypes.byref(lat))
+                    if rc != pso.PSO_EAGAIN:
+                        pso._check(rc, "poll")
+                        res[t] = r.iters
+                        pending.discard(t)
+                if time.perf_counter() - t0 > 120:
+                    break
+            wall = time.perf_counter() - t0
+            st = srv.stats()
+        upd = sum(sp.N * sp.D * res.get(t, 0) for sp, t in zip(specs, tickets))
+        out[str(rate)] = dict(offered_per_s=rate, requests=count, completed=int(st["completed"]),
+                              p50_ms=st["p50_ms"], p99_ms=st["p99_ms"], max_ms=st["max_ms"],
+                              throughput_per_s=st["completed"] / wall, updates_per_s=upd / wall,
+                              submit_s=submit_s, wall_s=wall, launches=int(st["launches"]),
+                              mem_peak_bytes=int(st["mem_peak"]))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,6 +187,8 @@ def main():
     ap.add_argument("--variant", choices=["sync", "async"], default="sync")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=200)
+    ap.add_argument("--legs", default="main,async,batched,serving",
+                    help="comma list of legs beyond the main line: async, batched, serving")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="for rocprofv3 counter runs: init + 20 step launches, then a 256 MiB torch copy "
                          "(calibration kernel of known size); prints nothing else")
@@ -94,7 +208,10 @@ def main():
     variant = pso.PSO_SYNC if args.variant == "sync" else pso.PSO_ASYNC
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    stream = torch.cuda.current_stream()
+    # every kernel of the benchmark runs on this stream, so the HIP events
+    # recorded on it time exactly that work
+    stream = torch.cuda.Stream(device=dev)
+    torch.cuda.set_stream(stream)
     nbytes = pso.pso_workspace_bytes(spec.N, spec.D)
     ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
     sw = pso.Swarm(spec.fitness, spec.N, spec.D, spec.box, spec.w, spec.c1, spec.c2, spec.vmax, spec.seed,
@@ -152,7 +269,7 @@ def main():
     alg_bytes = spec.N * spec.D * (20.0 + 4.0 * rho) + spec.N * (4.0 + 4.0 * rho)
     achieved = alg_bytes / (launch_us * 1e-6) / 1e9
     kernel = f"k_step<{spec.fitness}, D={spec.D}, {args.variant}>"
-    traffic = traffic_from_profiles(kernel, alg_bytes)
+    traffic = traffic_from_profiles(kernel)
 
     out = {
         "metric": "particle·dim updates/s incl. fitness",
@@ -178,6 +295,13 @@ def main():
         "wall_s_timed": t_wall,
         "source_digest": source_digest(),
     }
+    legs = set(args.legs.split(","))
+    if "async" in legs:
+        out["async"] = async_leg(pso, torch, spec, ws, stream)
+    if "batched" in legs:
+        out["batched"] = batched_leg(pso, torch, wl, stream)
+    if "serving" in legs:
+        out["serving"] = serving_leg(pso, wl)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, args.cpu_iters)
     print(json.dumps(out), flush=True)

@@ -207,9 +207,10 @@ int pso_batch_run(const pso_desc *descs, int64_t count, pso_result *results);
 /* ------------------------------------------------------------------------ */
 /* Request server: solves arrive over time (the real-time uses of Sec. 1).   */
 /* Requests are admitted in arrival order as device memory allows; admitted  */
-/* swarms stay resident and advance together, up to chunk_iters iterations   */
-/* per launch, with two launches in flight so that new arrivals start while  */
-/* others run.  A request's result is the same bits as pso_create + pso_run  */
+/* swarms stay resident and advance together -- each launch runs about       */
+/* chunk_updates particle-dimension updates of every swarm (at least one     */
+/* iteration) -- with two launches in flight so that new arrivals start      */
+/* while others run.  A request's result is the same bits as pso_create + pso_run  */
 /* (synchronous) of the same descriptor alone.  Thread-safe: submit and poll */
 /* may be called from any host thread.                                       */
 /* ------------------------------------------------------------------------ */
@@ -222,8 +223,9 @@ typedef struct pso_server_counters {
 } pso_server_counters;
 
 /* Starts a server with mem_budget bytes of device memory for swarm state
- * (allocated now) and chunk_iters iterations per launch (<= 0: 64). */
-int pso_server_create(size_t mem_budget, int64_t chunk_iters, pso_server **out);
+ * (allocated now) and chunk_updates updates per swarm and launch (<= 0:
+ * 2^20). */
+int pso_server_create(size_t mem_budget, int64_t chunk_updates, pso_server **out);
 
 /* Queues one request (validated as a batch descriptor; the shift is copied)
  * and returns its ticket. */

@@ -213,9 +213,10 @@ class Batch:
 class Server:
     """Request server with continuous batching (pso_server_*)."""
 
-    def __init__(self, mem_budget: int, chunk_iters: int = 0):
+    def __init__(self, mem_budget: int, chunk_updates: int = 0):
         self.h = ctypes.c_void_p()
-        _check(lib().pso_server_create(int(mem_budget), int(chunk_iters), ctypes.byref(self.h)), "pso_server_create")
+        _check(lib().pso_server_create(int(mem_budget), int(chunk_updates), ctypes.byref(self.h)),
+               "pso_server_create")
         self._D = {}
 
     def submit(self, spec) -> int:

@@ -208,8 +208,13 @@ __device__ void batch_one(const BatchItem &it, BatchResult *res, long long chunk
         for (int d = threadIdx.x; d < D; d += BLOCK_SWARM) s_g[d] = a.gpos[d];
         __syncthreads();
     }
+    // iterations this launch: about `chunk` particle-dimension updates' worth
+    // (at least one), so every swarm of a launch takes a similar time
     const long long left = it.max_iter - L.t;
-    block_iterate<FIT>(a, left < chunk ? left : chunk, it.tol, it.fstar, s_shift, s_g, s_min, nullptr, L);
+    const long long nd = (long long)a.N * a.D;
+    long long iters = chunk / nd;
+    iters = iters < 1 ? 1 : iters;
+    block_iterate<FIT>(a, left < iters ? left : iters, it.tol, it.fstar, s_shift, s_g, s_min, nullptr, L);
     for (int d = threadIdx.x; d < D; d += BLOCK_SWARM) a.gpos[d] = s_g[d];
     if (threadIdx.x == 0) {
         res->gkey = L.gkey;

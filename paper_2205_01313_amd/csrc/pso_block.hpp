@@ -34,8 +34,9 @@ hipError_t launch_block_run(int fitness, const SwarmArgs &a, long long T, hipStr
 hipError_t launch_batch_reset(BatchResult *results, uint32_t count, unsigned int *next, hipStream_t stream);
 
 // One persistent launch of `grid` workgroups over the `count` items listed in
-// `order`: Step 1 for items not started, then up to `chunk` more iterations
-// of each (stop rule and max_iter respected).  `next` is a device work
+// `order`: Step 1 for items not started, then max(1, chunk / (N*D)) more
+// iterations of each -- `chunk` is a budget of particle-dimension updates
+// per swarm and launch -- within its max_iter and stop rule.  `next` is a device work
 // counter (cleared by the launch); maxD bounds every listed item's D.
 // Optionally the launch also writes, for the j-th listed item, its state to
 // out_state[j] and its gbest position to out_pos[j*maxD ..] (for one compact

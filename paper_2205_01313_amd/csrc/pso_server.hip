@@ -5,8 +5,9 @@
 // (pso_desc) are admitted in arrival order as device memory frees up (the
 // Arena/Admission bookkeeping of pso_arena.hpp), their swarm state stays
 // resident on the device, and a scheduler thread keeps up to two batched
-// launches in flight on two streams: each launch runs up to `chunk`
-// iterations of every swarm in its set (Step 1 first for new swarms), so
+// launches in flight on two streams: each launch advances every swarm in its
+// set by about `chunk` particle-dimension updates' worth of iterations (Step
+// 1 first for new swarms), so
 // requests that arrive while a launch runs start on the other stream and
 // overlap on the device.  Between launches a swarm's loop state stays in
 // device memory, so its result is the same bits as running it alone.
@@ -61,7 +62,7 @@ constexpr int STREAMS = 2;
 struct pso_server {
     // configuration
     size_t budget = 0;
-    long long chunk = 64;
+    long long chunk = 1 << 20; // particle-dimension updates per swarm and launch
     int max_slots = 0;
     int grid_cap = 1;
     // device memory
@@ -317,7 +318,7 @@ void server_loop(pso_server *s)
 
 extern "C" {
 
-int pso_server_create(size_t mem_budget, int64_t chunk_iters, pso_server **out)
+int pso_server_create(size_t mem_budget, int64_t chunk_updates, pso_server **out)
 {
     if (!out) return pso_internal_fail(PSO_EINVAL, "out is NULL");
     *out = nullptr;
@@ -325,7 +326,7 @@ int pso_server_create(size_t mem_budget, int64_t chunk_iters, pso_server **out)
     pso_server *s = new (std::nothrow) pso_server();
     if (!s) return pso_internal_fail(PSO_ENOMEM, "host allocation failed");
     s->budget = mem_budget;
-    s->chunk = chunk_iters > 0 ? chunk_iters : 64;
+    s->chunk = chunk_updates > 0 ? chunk_updates : (1 << 20);
     s->arena = pso::Arena(mem_budget);
     // at most one slot per 64 KiB of budget, within [64, 65536]
     s->max_slots = (int)std::min<size_t>(65536, std::max<size_t>(64, mem_budget / 65536));

@@ -86,3 +86,43 @@ def deep_ackley(seed=0):
     vmax 6.5536, shift U[-10,10] per seed."""
     return SwarmSpec("ackley", 65536, 128, 2000, seed=seed, box=(-32.768, 32.768), vmax=6.5536,
                      shift_amplitude=10.0)
+
+
+# Many independent swarms.
+def batch_specs(count=4096, seed=0, T=500, shift_amplitude=5.0):
+    """Swarms with N = round(exp(U[ln 32, ln 8192])), D uniform in
+    {2, 4, ..., 64}, fitness uniform over Sphere/Rastrigin/Rosenbrock/Ackley
+    on their standard boxes, shift U[-5, 5]^D, T iterations; swarm k uses
+    Philox seed k.  Drawn from PCG64(seed)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    specs = []
+    for k in range(count):
+        N = int(round(np.exp(rng.uniform(np.log(32), np.log(8192)))))
+        D = 2 * (1 + int(rng.integers(0, 32)))
+        fit = FITNESS_NAMES[int(rng.integers(0, 4))]
+        shift = rng.uniform(-shift_amplitude, shift_amplitude, D).astype(np.float32)
+        specs.append(SwarmSpec(fit, N, D, T, seed=k, shift=shift))
+    return specs
+
+
+def serving_specs(count, seed=0, max_iter=1000, tol=1e-4):
+    """Solve requests: N = lognormal(median 512, sigma 1) clipped to
+    [32, 16384], D uniform in [2, 64], fitness and shift as batch_specs, stop
+    at |gbest - 0| < tol or max_iter iterations.  Drawn from PCG64(seed)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    specs = []
+    for k in range(count):
+        N = int(np.clip(round(np.exp(rng.normal(np.log(512), 1.0))), 32, 16384))
+        D = int(rng.integers(2, 65))
+        fit = FITNESS_NAMES[int(rng.integers(0, 4))]
+        shift = rng.uniform(-5.0, 5.0, D).astype(np.float32)
+        sp = SwarmSpec(fit, N, D, max_iter, seed=k, shift=shift)
+        sp.tol, sp.f_star = tol, 0.0
+        specs.append(sp)
+    return specs
+
+
+def poisson_arrivals(count, rate, seed=0):
+    """Arrival times (s) of a Poisson process of the given rate (1/s)."""
+    rng = np.random.Generator(np.random.PCG64(seed + 1))
+    return np.cumsum(rng.exponential(1.0 / rate, count))

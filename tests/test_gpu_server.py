@@ -46,7 +46,7 @@ def check_same(specs, tickets, res):
 def test_results_equal_alone_with_staggered_arrivals():
     specs = mixed_specs(120, 11, max_iter=300)
     announce("server: 120 staggered requests")
-    with pso.Server(1 << 30, chunk_iters=16) as srv:
+    with pso.Server(1 << 30, chunk_updates=20000) as srv:
         tickets = []
         for k, sp in enumerate(specs):
             tickets.append(srv.submit(sp))
@@ -64,7 +64,7 @@ def test_small_budget_admits_in_stages_and_never_exceeds_it():
     need = pso.pso_workspace_bytes(2000, 16)
     budget = 3 * need  # a few swarms at a time
     announce("server: small budget")
-    with pso.Server(budget, chunk_iters=8) as srv:
+    with pso.Server(budget, chunk_updates=2000*16*8) as srv:
         tickets = [srv.submit(sp) for sp in specs]
         res = wait_all(srv, tickets)
         st = srv.stats()
@@ -96,7 +96,7 @@ def test_oversize_request_is_rejected_and_others_continue():
 
 def test_submit_from_two_threads():
     specs = mixed_specs(60, 12, max_iter=80)
-    with pso.Server(1 << 30, chunk_iters=32) as srv:
+    with pso.Server(1 << 30, chunk_updates=50000) as srv:
         tickets = [None] * len(specs)
 
         def worker(lo):
