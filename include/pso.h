@@ -57,6 +57,8 @@ extern "C" {
 /* Aggregation variants (pso_set_variant). */
 #define PSO_SYNC 0  /* gbest of iteration t-1 for every particle of iteration t (Sec. 2.2) */
 #define PSO_ASYNC 1 /* a workgroup publishes a better gbest at once (Sec. 3.2) */
+#define PSO_REDUCE 2 /* the paper's comparator: two kernels, tree reduction through auxiliary arrays (Sec. 2.2) */
+#define PSO_REDUCE_UNROLLED 3 /* the same with the last wavefront's reduction steps unrolled (Sec. 2.2) */
 
 typedef struct pso_swarm pso_swarm;
 
@@ -94,7 +96,10 @@ int pso_create_in(int fitness_id, int64_t N, int32_t D, const float bounds[2], f
  * NULL restores s = 0. */
 int pso_set_shift(pso_swarm *s, const float *shift_host);
 
-/* Selects PSO_SYNC (default) or PSO_ASYNC for the iterations that follow. */
+/* Selects the aggregation of the iterations that follow: PSO_SYNC
+ * (default), PSO_ASYNC, or the comparators PSO_REDUCE / PSO_REDUCE_UNROLLED
+ * (which compute exactly what PSO_SYNC computes, with two launches per
+ * iteration). */
 int pso_set_variant(pso_swarm *s, int variant);
 
 /* Re-runs Step 1 in place: the swarm returns to iteration 0 with the same

@@ -13,7 +13,8 @@ import numpy as np
 
 from . import _native
 from ._native import (PSO_ACKLEY, PSO_ASYNC, PSO_CUBIC, PSO_EAGAIN, PSO_EDEVICE, PSO_EINVAL,  # noqa: F401
-                      PSO_ENOMEM, PSO_ESTATE, PSO_OK, PSO_RASTRIGIN, PSO_ROSENBROCK, PSO_SPHERE, PSO_SYNC)
+                      PSO_ENOMEM, PSO_ESTATE, PSO_OK, PSO_RASTRIGIN, PSO_REDUCE, PSO_REDUCE_UNROLLED,
+                      PSO_ROSENBROCK, PSO_SPHERE, PSO_SYNC)
 
 FITNESS = {"sphere": PSO_SPHERE, "rastrigin": PSO_RASTRIGIN, "rosenbrock": PSO_ROSENBROCK,
            "ackley": PSO_ACKLEY, "cubic": PSO_CUBIC}

@@ -15,16 +15,25 @@
 // an atomic work counter (swarms are queued largest first), runs it to its
 // iteration limit or stop rule, writes the result, and takes the next; every
 // workgroup exits when the counter passes the swarm count.
+#include <algorithm>
+
 #include "pso_block.hpp"
 #include "pso_quad.hpp"
 
-#ifndef PSO_BLOCK_SWARM
-#define PSO_BLOCK_SWARM 256 // lanes of a swarm-owning workgroup
+#ifndef PSO_RUN_LANES
+#define PSO_RUN_LANES 256 // lanes of the workgroup running one small swarm (pso_run)
+#endif
+#ifndef PSO_BATCH_LANES
+#define PSO_BATCH_LANES 256 // lanes of a batched swarm's (part's) workgroup
+#endif
+#ifndef PSO_PART_WORK
+#define PSO_PART_WORK (1 << 17) // particle-dimension updates per part and iteration
 #endif
 
 namespace pso {
 
-constexpr int BLOCK_SWARM = PSO_BLOCK_SWARM;
+constexpr int RUN_LANES = PSO_RUN_LANES;
+constexpr int BATCH_LANES = PSO_BATCH_LANES;
 
 // Per-swarm loop state, identical in every lane.
 struct SwarmLoop {
@@ -54,41 +63,137 @@ __device__ __forceinline__ unsigned long long block_min(unsigned long long key, 
     return *slot;
 }
 
-// gbest position <- x of particle gi, stored by a lane of this workgroup
-// before the last barrier (one compute unit: its L1 serves every lane).
-__device__ __forceinline__ void gather_gbest(const SwarmArgs &a, int D, uint32_t gi, float *s_g)
+// The share of a swarm one workgroup runs: particle quads [q_lo, q_hi)
+// (4q < N), padded quads [qi_lo, qi_hi) initialised by it (4q < Np), and for
+// a swarm of several parts, their meeting point.
+struct Part {
+    uint32_t q_lo, q_hi, qi_lo, qi_hi;
+    uint32_t part, parts;
+    GangSync *gang;
+    unsigned long long *cand_key;
+    float *cand_pos;
+};
+
+__device__ __forceinline__ Part whole_swarm(const SwarmArgs &a)
 {
-    for (int d = threadIdx.x; d < D; d += BLOCK_SWARM) s_g[d] = a.x[(size_t)d * a.Np + gi];
+    Part P{};
+    P.q_lo = 0;
+    P.q_hi = (a.N + 3) / 4;
+    P.qi_lo = 0;
+    P.qi_hi = a.Np / 4;
+    P.part = 0;
+    P.parts = 1;
+    return P;
 }
 
-// Step 1 by one workgroup; leaves the gbest position in s_g.
-template <int FIT>
-__device__ void block_init(const SwarmArgs &a, const float *s_shift, float *s_g, unsigned long long *s_min,
+// Workgroup-shared scratch of the per-swarm loop.
+struct Scratch {
+    unsigned long long min[2]; // block_min slots, alternating by step
+    unsigned long long bkey;   // broadcast of the combined key
+    unsigned int owner;        // broadcast of the part owning it
+    unsigned int err;          // a wait gave up
+};
+
+constexpr unsigned long long GANG_WAIT_TICKS = 2000000000ull; // 20 s of the 100 MHz wall clock
+
+// Combines the workgroup minimum m of step tau (Step 1 = step 0, iteration t
+// = step t) over the swarm's parts.  Returns the swarm minimum; *owner is
+// the part that posted it (its candidate position is in cand_pos).
+template <int LANES>
+__device__ unsigned long long gang_min(const SwarmArgs &a, const Part &P, long long tau, unsigned long long m,
+                                       Scratch *sc, uint32_t *owner)
+{
+    if (P.parts == 1) { // uniform per swarm
+        *owner = 0;
+        return m;
+    }
+    const int b = (int)(tau & 1);
+    const int D = a.D;
+    if (m != NO_KEY) { // stage this part's candidate position (x just stored by this workgroup)
+        const size_t gi = (uint32_t)m;
+        float *dst = P.cand_pos + ((size_t)b * P.parts + P.part) * D;
+        for (int d = threadIdx.x; d < D; d += LANES) dst[d] = a.x[(size_t)d * a.Np + gi];
+    }
+    if (threadIdx.x == 0) P.cand_key[(size_t)b * P.parts + P.part] = m;
+    __threadfence(); // release the candidate before arriving
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        atomicAdd(&P.gang->arrive, 1ull);
+        const unsigned long long target = (unsigned long long)P.parts * (unsigned long long)(tau + 1);
+        const unsigned long long t0 = wall_clock64();
+        while (__hip_atomic_load(&P.gang->arrive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(4);
+            if (wall_clock64() - t0 > GANG_WAIT_TICKS) {
+                sc->err = 1u;
+                break;
+            }
+        }
+        __threadfence(); // acquire every part's candidate
+        unsigned long long g = NO_KEY;
+        unsigned int o = 0;
+        for (uint32_t p = 0; p < P.parts; ++p) {
+            const unsigned long long k = __hip_atomic_load(&P.cand_key[(size_t)b * P.parts + p], __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT);
+            if (k < g) {
+                g = k;
+                o = p;
+            }
+        }
+        sc->bkey = g;
+        sc->owner = o;
+    }
+    __syncthreads();
+    *owner = sc->owner;
+    return sc->bkey;
+}
+
+// gbest position <- the particle of key k: from x (one part: stored by this
+// workgroup before the last barrier) or from the owner part's staged copy.
+template <int LANES>
+__device__ __forceinline__ void gather_gbest(const SwarmArgs &a, const Part &P, long long tau, unsigned long long k,
+                                             uint32_t owner, float *s_g)
+{
+    const int D = a.D;
+    if (P.parts == 1) {
+        const size_t gi = (uint32_t)k;
+        for (int d = threadIdx.x; d < D; d += LANES) s_g[d] = a.x[(size_t)d * a.Np + gi];
+    } else {
+        const float *src = P.cand_pos + ((size_t)(tau & 1) * P.parts + owner) * D;
+        for (int d = threadIdx.x; d < D; d += LANES)
+            s_g[d] = __hip_atomic_load(&src[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Step 1 by one workgroup (its part); leaves the gbest position in s_g.
+template <int FIT, int LANES>
+__device__ void block_init(const SwarmArgs &a, const Part &P, const float *s_shift, float *s_g, Scratch *sc,
                            SwarmLoop &L)
 {
     const int D = a.D;
     unsigned long long key = NO_KEY;
-    for (uint32_t q = threadIdx.x; 4 * q < a.Np; q += BLOCK_SWARM) {
+    for (uint32_t q = P.qi_lo + threadIdx.x; q < P.qi_hi; q += LANES) {
         const unsigned long long k = init_quad<FIT>(a, D, q, s_shift);
         key = k < key ? k : key;
     }
-    const unsigned long long m = block_min(key, NO_KEY, &s_min[0]);
-    if (threadIdx.x == 0) s_min[1] = NO_KEY;
-    gather_gbest(a, D, (uint32_t)m, s_g);
-    L.gkey = m;
+    const unsigned long long m = block_min(key, NO_KEY, &sc->min[0]);
+    if (threadIdx.x == 0) sc->min[1] = NO_KEY;
+    uint32_t owner;
+    const unsigned long long g = gang_min<LANES>(a, P, 0, m, sc, &owner);
+    gather_gbest<LANES>(a, P, 0, g, owner, s_g);
+    L.gkey = g;
     L.giter = 0;
     L.t = 0;
     __syncthreads();
 }
 
 // Up to T iterations after L.t, stopping after the first iteration at which
-// the stop rule holds (it is tested before the first one too).  s_min[2]
+// the stop rule holds (it is tested before the first one too).  sc->min[2]
 // alternates between iterations: slot (t & 1) collects iteration t's
 // minimum, and the other slot is cleared for iteration t+1.  hist (may be
 // null) receives each iteration's gbest key.
-template <int FIT>
-__device__ void block_iterate(const SwarmArgs &a, long long T, float tol, float fstar, const float *s_shift,
-                              float *s_g, unsigned long long *s_min, unsigned long long *hist, SwarmLoop &L)
+template <int FIT, int LANES>
+__device__ void block_iterate(const SwarmArgs &a, const Part &P, long long T, float tol, float fstar,
+                              const float *s_shift, float *s_g, Scratch *sc, unsigned long long *hist, SwarmLoop &L)
 {
     uint32_t n_imp = 0; // this lane's pbest improvements over the run
     const int D = a.D;
@@ -96,19 +201,20 @@ __device__ void block_iterate(const SwarmArgs &a, long long T, float tol, float 
     for (long long it = 0; it < T && !L.stop; ++it) {
         const uint32_t t = (uint32_t)(L.t + 1);
         unsigned long long key = NO_KEY;
-        for (uint32_t q = threadIdx.x; 4 * q < a.N; q += BLOCK_SWARM) {
+        for (uint32_t q = P.q_lo + threadIdx.x; q < P.q_hi; q += LANES) {
             uint32_t n = 0;
             const unsigned long long k = iterate_quad<FIT, 0, 1>(a, D, q, t, s_g, s_shift, &n);
             key = k < key ? k : key;
             n_imp += n;
         }
-        unsigned long long *slot = &s_min[t & 1];
-        const unsigned long long m = block_min(key, L.gkey, slot);
-        if (threadIdx.x == 0) s_min[(t + 1) & 1] = NO_KEY;
-        if (m < L.gkey) {
-            L.gkey = m;
+        const unsigned long long m = block_min(key, L.gkey, &sc->min[t & 1]);
+        if (threadIdx.x == 0) sc->min[(t + 1) & 1] = NO_KEY;
+        uint32_t owner;
+        const unsigned long long g = gang_min<LANES>(a, P, t, m, sc, &owner);
+        if (g < L.gkey) {
+            L.gkey = g;
             L.giter = t;
-            gather_gbest(a, D, (uint32_t)m, s_g);
+            gather_gbest<LANES>(a, P, t, g, owner, s_g);
         }
         if (hist && threadIdx.x == 0) hist[t & (HIST_CAP - 1)] = L.gkey;
         L.t = t;
@@ -123,20 +229,21 @@ __device__ void block_iterate(const SwarmArgs &a, long long T, float tol, float 
 // control block's state for up to T iterations with its stop rule.
 // ---------------------------------------------------------------------------
 template <int FIT>
-__global__ void __launch_bounds__(BLOCK_SWARM) k_block_run(SwarmArgs a, long long T)
+__global__ void __launch_bounds__(RUN_LANES) k_block_run(SwarmArgs a, long long T)
 {
-    __shared__ unsigned long long s_min[2];
+    __shared__ Scratch sc;
     extern __shared__ float s_dyn[]; // gbest position (D), shift (D)
     Ctrl *c = a.ctrl;
     const int D = a.D;
     float *s_g = s_dyn, *s_shift = s_dyn + D;
-    for (int d = threadIdx.x; d < D; d += BLOCK_SWARM) {
+    for (int d = threadIdx.x; d < D; d += RUN_LANES) {
         s_g[d] = a.gpos[d];
         s_shift[d] = a.shift[d];
     }
     if (threadIdx.x == 0) {
-        s_min[0] = NO_KEY;
-        s_min[1] = NO_KEY;
+        sc.min[0] = NO_KEY;
+        sc.min[1] = NO_KEY;
+        sc.err = 0;
     }
     SwarmLoop L;
     L.gkey = c->gkey_prev;
@@ -145,9 +252,9 @@ __global__ void __launch_bounds__(BLOCK_SWARM) k_block_run(SwarmArgs a, long lon
     L.stop = c->stop != 0u;
     const float tol = c->tol, fstar = c->fstar;
     __syncthreads();
-    block_iterate<FIT>(a, T, tol, fstar, s_shift, s_g, s_min, a.hist, L);
+    block_iterate<FIT, RUN_LANES>(a, whole_swarm(a), T, tol, fstar, s_shift, s_g, &sc, a.hist, L);
     if (L.improved) atomicAdd(&c->improved, (unsigned long long)L.improved);
-    for (int d = threadIdx.x; d < D; d += BLOCK_SWARM) a.gpos[d] = s_g[d];
+    for (int d = threadIdx.x; d < D; d += RUN_LANES) a.gpos[d] = s_g[d];
     if (threadIdx.x == 0) {
         c->gkey = L.gkey;
         c->gkey_prev = L.gkey;
@@ -160,12 +267,19 @@ __global__ void __launch_bounds__(BLOCK_SWARM) k_block_run(SwarmArgs a, long lon
 
 // ---------------------------------------------------------------------------
 // Batched: many independent swarms in one persistent launch.  Each launch
-// runs up to `chunk` iterations of every listed swarm and leaves its loop
-// state (BatchResult) and gbest position in device memory, so a later launch
-// resumes it exactly where it stopped: a swarm computes the same bits however
-// its iterations are split over launches.
+// advances every listed swarm by about `chunk` updates' worth of iterations
+// and leaves its loop state (BatchResult) and gbest position in device
+// memory, so a later launch resumes it exactly where it stopped: a swarm
+// computes the same bits however its iterations are split over launches.
+//
+// A large swarm is split into parts run by different workgroups, which meet
+// once per step (gang_min).  Parts are consecutive in the work queue and the
+// grid is fully co-resident, so a part waiting for its siblings always has
+// them dequeued by workgroups that finish their own work: the first swarm in
+// queue order with a part not yet dequeued has all its earlier parts either
+// running or waiting for it, and every swarm before it has all its parts.
 // ---------------------------------------------------------------------------
-__global__ void k_batch_reset(BatchResult *results, uint32_t count, unsigned int *next)
+__global__ void k_batch_reset(const BatchItem *items, BatchResult *results, uint32_t count, unsigned int *next)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) *next = 0u;
@@ -175,6 +289,10 @@ __global__ void k_batch_reset(BatchResult *results, uint32_t count, unsigned int
         results[i].iters = 0;
         results[i].started = 0;
         results[i].stop = 0;
+        if (items[i].parts > 1) {
+            items[i].gang->arrive = 0ull;
+            items[i].gang->err = 0u;
+        }
     }
 }
 
@@ -183,77 +301,130 @@ __global__ void k_counter_reset(unsigned int *next)
     if (threadIdx.x == 0) *next = 0u;
 }
 
-template <int FIT>
-__device__ void batch_one(const BatchItem &it, BatchResult *res, long long chunk, float *s_g, float *s_shift,
-                          unsigned long long *s_min)
+template <int FIT, int LANES>
+__device__ void batch_part(const BatchItem &it, uint32_t part, BatchResult *res, long long chunk, long long iter_cap,
+                           float *s_g,
+                           float *s_shift, Scratch *sc, BatchResult *out_state, float *out_pos, uint32_t out,
+                           int pos_stride)
 {
     const SwarmArgs &a = it.a;
     const int D = a.D;
-    for (int d = threadIdx.x; d < D; d += BLOCK_SWARM) s_shift[d] = a.shift[d];
+    Part P;
+    const uint32_t nq = (a.N + 3) / 4, nqi = a.Np / 4;
+    P.parts = it.parts;
+    P.part = part;
+    P.q_lo = (uint32_t)((unsigned long long)nq * part / it.parts);
+    P.q_hi = (uint32_t)((unsigned long long)nq * (part + 1) / it.parts);
+    P.qi_lo = (uint32_t)((unsigned long long)nqi * part / it.parts);
+    P.qi_hi = (uint32_t)((unsigned long long)nqi * (part + 1) / it.parts);
+    P.gang = it.gang;
+    P.cand_key = it.cand_key;
+    P.cand_pos = it.cand_pos;
+    for (int d = threadIdx.x; d < D; d += LANES) s_shift[d] = a.shift[d];
     if (threadIdx.x == 0) {
-        s_min[0] = NO_KEY;
-        s_min[1] = NO_KEY;
+        sc->min[0] = NO_KEY;
+        sc->min[1] = NO_KEY;
     }
     SwarmLoop L;
     const bool started = res->started != 0u;
     __syncthreads();
     if (!started) {
         L.stop = false;
-        block_init<FIT>(a, s_shift, s_g, s_min, L);
+        block_init<FIT, LANES>(a, P, s_shift, s_g, sc, L);
     } else {
         L.gkey = res->gkey;
         L.giter = res->giter;
         L.t = res->iters;
         L.stop = res->stop != 0u;
-        for (int d = threadIdx.x; d < D; d += BLOCK_SWARM) s_g[d] = a.gpos[d];
+        for (int d = threadIdx.x; d < D; d += LANES) s_g[d] = a.gpos[d];
         __syncthreads();
     }
     // iterations this launch: about `chunk` particle-dimension updates' worth
-    // (at least one), so every swarm of a launch takes a similar time
+    // (at least one); the same number for every part of the swarm
     const long long left = it.max_iter - L.t;
     const long long nd = (long long)a.N * a.D;
     long long iters = chunk / nd;
-    iters = iters < 1 ? 1 : iters;
-    block_iterate<FIT>(a, left < iters ? left : iters, it.tol, it.fstar, s_shift, s_g, s_min, nullptr, L);
-    for (int d = threadIdx.x; d < D; d += BLOCK_SWARM) a.gpos[d] = s_g[d];
-    if (threadIdx.x == 0) {
-        res->gkey = L.gkey;
-        res->giter = L.giter;
-        res->iters = L.t;
-        res->stop = L.stop ? 1u : 0u;
-        res->started = 1u;
+    iters = iters < 1 ? 1 : (iters > iter_cap ? iter_cap : iters);
+    block_iterate<FIT, LANES>(a, P, left < iters ? left : iters, it.tol, it.fstar, s_shift, s_g, sc, nullptr, L);
+    if (part == 0) {
+        for (int d = threadIdx.x; d < D; d += LANES) {
+            a.gpos[d] = s_g[d];
+            if (out_pos) out_pos[(size_t)out * pos_stride + d] = s_g[d];
+        }
+        if (threadIdx.x == 0) {
+            res->gkey = L.gkey;
+            res->giter = L.giter;
+            res->iters = L.t;
+            res->stop = L.stop ? 1u : 0u;
+            res->started = 1u;
+            if (out_state) out_state[out] = *res;
+        }
     }
 }
 
-__global__ void __launch_bounds__(BLOCK_SWARM) k_batch(const BatchItem *items, const uint32_t *order,
+__global__ void __launch_bounds__(BATCH_LANES) k_batch(const BatchItem *items, const BatchEntry *entries,
                                                        BatchResult *results, uint32_t count, unsigned int *next,
-                                                       long long chunk, BatchResult *out_state, float *out_pos,
-                                                       int pos_stride)
+                                                       long long chunk, long long iter_cap, BatchResult *out_state,
+                                                       float *out_pos, int pos_stride, unsigned int *err)
 {
-    __shared__ unsigned long long s_min[2];
+    __shared__ Scratch sc;
     __shared__ uint32_t s_idx;
     extern __shared__ float s_dyn[]; // gbest position (maxD floats), then shift
+    if (threadIdx.x == 0) sc.err = 0;
     for (;;) {
         if (threadIdx.x == 0) s_idx = atomicAdd(next, 1u);
         __syncthreads();
         const uint32_t j = s_idx;
         __syncthreads();
         if (j >= count) break; // uniform: every workgroup leaves once the list is drained
-        const uint32_t idx = order[j];
-        const BatchItem &it = items[idx];
+        const BatchEntry e = entries[j];
+        const BatchItem &it = items[e.item];
         float *s_g = s_dyn, *s_shift = s_dyn + it.a.D;
+        BatchResult *res = &results[e.item];
         switch (it.fitness) {
-        case F_SPHERE: batch_one<F_SPHERE>(it, &results[idx], chunk, s_g, s_shift, s_min); break;
-        case F_RASTRIGIN: batch_one<F_RASTRIGIN>(it, &results[idx], chunk, s_g, s_shift, s_min); break;
-        case F_ROSENBROCK: batch_one<F_ROSENBROCK>(it, &results[idx], chunk, s_g, s_shift, s_min); break;
-        case F_ACKLEY: batch_one<F_ACKLEY>(it, &results[idx], chunk, s_g, s_shift, s_min); break;
-        default: batch_one<F_CUBIC>(it, &results[idx], chunk, s_g, s_shift, s_min); break;
+        case F_SPHERE: batch_part<F_SPHERE, BATCH_LANES>(it, e.part, res, chunk, iter_cap, s_g, s_shift, &sc, out_state, out_pos, e.out, pos_stride); break;
+        case F_RASTRIGIN: batch_part<F_RASTRIGIN, BATCH_LANES>(it, e.part, res, chunk, iter_cap, s_g, s_shift, &sc, out_state, out_pos, e.out, pos_stride); break;
+        case F_ROSENBROCK: batch_part<F_ROSENBROCK, BATCH_LANES>(it, e.part, res, chunk, iter_cap, s_g, s_shift, &sc, out_state, out_pos, e.out, pos_stride); break;
+        case F_ACKLEY: batch_part<F_ACKLEY, BATCH_LANES>(it, e.part, res, chunk, iter_cap, s_g, s_shift, &sc, out_state, out_pos, e.out, pos_stride); break;
+        default: batch_part<F_CUBIC, BATCH_LANES>(it, e.part, res, chunk, iter_cap, s_g, s_shift, &sc, out_state, out_pos, e.out, pos_stride); break;
         }
         __syncthreads();
-        if (out_state && threadIdx.x == 0) out_state[j] = results[idx];
-        if (out_pos)
-            for (int d = threadIdx.x; d < it.a.D; d += BLOCK_SWARM) out_pos[(size_t)j * pos_stride + d] = s_g[d];
     }
+    if (threadIdx.x == 0 && sc.err && err) atomicOr(err, 1u);
+}
+
+uint32_t parts_for(uint64_t N, int D, int grid_cap)
+{
+    const uint64_t work = N * (uint64_t)D;
+    uint64_t parts = (work + PSO_PART_WORK - 1) / PSO_PART_WORK;
+    const uint64_t by_quads = ((N + 3) / 4) / BATCH_LANES;
+    parts = std::min<uint64_t>(parts, by_quads);
+    parts = std::min<uint64_t>(parts, MAX_PARTS);
+    parts = std::min<uint64_t>(parts, (uint64_t)std::max(1, grid_cap));
+    return (uint32_t)std::max<uint64_t>(parts, 1);
+}
+
+size_t gang_bytes(uint32_t parts, int D)
+{
+    if (parts <= 1) return 0;
+    auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+    return al(sizeof(GangSync)) + al(sizeof(unsigned long long) * 2 * parts) + al(sizeof(float) * 2 * parts * (size_t)D);
+}
+
+void bind_gang(BatchItem *it, void *region, uint32_t parts)
+{
+    it->parts = parts < 1 ? 1 : parts;
+    if (it->parts == 1) {
+        it->gang = nullptr;
+        it->cand_key = nullptr;
+        it->cand_pos = nullptr;
+        return;
+    }
+    auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+    char *b = static_cast<char *>(region);
+    it->gang = reinterpret_cast<GangSync *>(b);
+    it->cand_key = reinterpret_cast<unsigned long long *>(b + al(sizeof(GangSync)));
+    it->cand_pos = reinterpret_cast<float *>(b + al(sizeof(GangSync)) + al(sizeof(unsigned long long) * 2 * parts));
 }
 
 // ---------------------------------------------------------------------------
@@ -263,39 +434,47 @@ hipError_t launch_block_run(int fitness, const SwarmArgs &a, long long T, hipStr
 {
     const size_t lds = 2 * sizeof(float) * a.D;
     switch (fitness) {
-    case F_SPHERE: hipLaunchKernelGGL(k_block_run<F_SPHERE>, dim3(1), dim3(BLOCK_SWARM), lds, stream, a, T); break;
-    case F_RASTRIGIN: hipLaunchKernelGGL(k_block_run<F_RASTRIGIN>, dim3(1), dim3(BLOCK_SWARM), lds, stream, a, T); break;
-    case F_ROSENBROCK: hipLaunchKernelGGL(k_block_run<F_ROSENBROCK>, dim3(1), dim3(BLOCK_SWARM), lds, stream, a, T); break;
-    case F_ACKLEY: hipLaunchKernelGGL(k_block_run<F_ACKLEY>, dim3(1), dim3(BLOCK_SWARM), lds, stream, a, T); break;
-    case F_CUBIC: hipLaunchKernelGGL(k_block_run<F_CUBIC>, dim3(1), dim3(BLOCK_SWARM), lds, stream, a, T); break;
+    case F_SPHERE: hipLaunchKernelGGL(k_block_run<F_SPHERE>, dim3(1), dim3(RUN_LANES), lds, stream, a, T); break;
+    case F_RASTRIGIN: hipLaunchKernelGGL(k_block_run<F_RASTRIGIN>, dim3(1), dim3(RUN_LANES), lds, stream, a, T); break;
+    case F_ROSENBROCK: hipLaunchKernelGGL(k_block_run<F_ROSENBROCK>, dim3(1), dim3(RUN_LANES), lds, stream, a, T); break;
+    case F_ACKLEY: hipLaunchKernelGGL(k_block_run<F_ACKLEY>, dim3(1), dim3(RUN_LANES), lds, stream, a, T); break;
+    case F_CUBIC: hipLaunchKernelGGL(k_block_run<F_CUBIC>, dim3(1), dim3(RUN_LANES), lds, stream, a, T); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-int batch_block_lanes() { return BLOCK_SWARM; }
 
-hipError_t launch_batch_reset(BatchResult *results, uint32_t count, unsigned int *next, hipStream_t stream)
+hipError_t launch_batch_reset(const BatchItem *items, BatchResult *results, uint32_t count, unsigned int *next,
+                              hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_batch_reset, dim3((count + 255) / 256), dim3(256), 0, stream, results, count, next);
+    hipLaunchKernelGGL(k_batch_reset, dim3((count + 255) / 256), dim3(256), 0, stream, items, results, count, next);
     return hipGetLastError();
 }
 
-hipError_t launch_batch(const BatchItem *items, const uint32_t *order, BatchResult *results, uint32_t count,
-                        unsigned int *next, int maxD, int grid, long long chunk, hipStream_t stream,
-                        BatchResult *out_state, float *out_pos)
+hipError_t launch_batch(const BatchItem *items, const BatchEntry *entries, BatchResult *results, uint32_t count,
+                        unsigned int *next, int maxD, int grid, long long chunk, long long iter_cap,
+                        hipStream_t stream, BatchResult *out_state, float *out_pos, unsigned int *err)
 {
     hipLaunchKernelGGL(k_counter_reset, dim3(1), dim3(64), 0, stream, next);
     const size_t lds = 2 * sizeof(float) * maxD;
-    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(BLOCK_SWARM), lds, stream, items, order, results, count, next,
-                       chunk, out_state, out_pos, maxD);
+    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(BATCH_LANES), lds, stream, items, entries, results, count, next,
+                       chunk, iter_cap, out_state, out_pos, maxD, err);
     return hipGetLastError();
 }
 
-hipError_t batch_occupancy(int maxD, int *blocks_per_cu)
+hipError_t batch_capacity(int maxD, int *workgroups)
 {
     const size_t lds = 2 * sizeof(float) * maxD;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch, BLOCK_SWARM, lds);
+    int per_cu = 0, dev = 0, cus = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch, BATCH_LANES, lds);
+    if (e != hipSuccess) return e;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+    // three quarters of the occupancy bound: a margin for anything else the
+    // device keeps resident, so every launched workgroup is co-resident
+    *workgroups = std::max(1, per_cu * cus * 3 / 4);
+    return hipSuccess;
 }
 
 } // namespace pso

@@ -237,7 +237,7 @@ int pso_set_shift(pso_swarm *s, const float *shift_host)
 int pso_set_variant(pso_swarm *s, int variant)
 {
     if (!s) return fail(PSO_EINVAL, "swarm is NULL");
-    if (variant != PSO_SYNC && variant != PSO_ASYNC) return fail(PSO_EINVAL, "unknown variant %d", variant);
+    if (variant < PSO_SYNC || variant > PSO_REDUCE_UNROLLED) return fail(PSO_EINVAL, "unknown variant %d", variant);
     s->variant = variant;
     return PSO_OK;
 }
@@ -441,9 +441,11 @@ struct pso_batch {
     int grid = 1;
     void *slab = nullptr;            // every swarm's state
     pso::BatchItem *d_items = nullptr;
-    uint32_t *d_order = nullptr;
+    pso::BatchEntry *d_entries = nullptr;
+    uint32_t n_entries = 0;
     pso::BatchResult *d_results = nullptr;
     unsigned int *d_next = nullptr;
+    unsigned int *d_err = nullptr;
     std::vector<pso::BatchItem> items; // host copy (device pointers inside)
     hipStream_t stream = nullptr;
     bool owns_stream = false;
@@ -457,7 +459,8 @@ void batch_free(pso_batch *b)
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     if (b->slab) (void)hipFree(b->slab);
     if (b->d_items) (void)hipFree(b->d_items);
-    if (b->d_order) (void)hipFree(b->d_order);
+    if (b->d_entries) (void)hipFree(b->d_entries);
+    if (b->d_err) (void)hipFree(b->d_err);
     if (b->d_results) (void)hipFree(b->d_results);
     if (b->d_next) (void)hipFree(b->d_next);
     if (b->owns_stream && b->stream) (void)hipStreamDestroy(b->stream);
@@ -474,23 +477,35 @@ int pso_batch_create(const pso_desc *descs, int64_t count, void *hip_stream, pso
     *out = nullptr;
     if (count < 1 || count > (int64_t(1) << 31)) return fail(PSO_EINVAL, "count=%lld out of range", (long long)count);
     if (!descs) return fail(PSO_EINVAL, "descs is NULL");
+    int capacity = 0;
+    {
+        int maxD0 = 1;
+        for (int64_t i = 0; i < count; ++i) maxD0 = std::max(maxD0, (int)descs[i].D);
+        if (pso::batch_capacity(maxD0, &capacity) != hipSuccess || capacity < 1)
+            return fail(PSO_EDEVICE, "device query failed");
+    }
     std::vector<pso::Layout> lay(count);
     std::vector<size_t> off(count);
+    std::vector<uint32_t> parts(count);
     size_t total = 0;
     int maxD = 1;
+    uint64_t n_entries = 0;
     for (int64_t i = 0; i < count; ++i) {
         const pso_desc &d = descs[i];
         int rc = pso_internal_check_desc(&d);
         if (rc) return fail(rc, "descriptor %lld: %s", (long long)i, std::string(g_err).c_str());
         lay[i] = pso::layout_of((uint64_t)d.N, d.D, false);
+        parts[i] = pso::parts_for((uint64_t)d.N, d.D, capacity);
         off[i] = total;
-        total += lay[i].total;
+        total += lay[i].total + pso::gang_bytes(parts[i], d.D);
         maxD = std::max(maxD, (int)d.D);
+        n_entries += parts[i];
     }
     pso_batch *b = new (std::nothrow) pso_batch();
     if (!b) return fail(PSO_ENOMEM, "host allocation failed");
     b->count = count;
     b->maxD = maxD;
+    b->n_entries = (uint32_t)n_entries;
     if (hip_stream) {
         b->stream = static_cast<hipStream_t>(hip_stream);
     } else {
@@ -501,9 +516,10 @@ int pso_batch_create(const pso_desc *descs, int64_t count, void *hip_stream, pso
         b->owns_stream = true;
     }
     if (hipMalloc(&b->slab, total) != hipSuccess || hipMalloc(&b->d_items, sizeof(pso::BatchItem) * count) != hipSuccess ||
-        hipMalloc(&b->d_order, sizeof(uint32_t) * count) != hipSuccess ||
+        hipMalloc(&b->d_entries, sizeof(pso::BatchEntry) * n_entries) != hipSuccess ||
         hipMalloc(&b->d_results, sizeof(pso::BatchResult) * count) != hipSuccess ||
-        hipMalloc(&b->d_next, sizeof(unsigned int)) != hipSuccess) {
+        hipMalloc(&b->d_next, sizeof(unsigned int)) != hipSuccess ||
+        hipMalloc(&b->d_err, sizeof(unsigned int)) != hipSuccess) {
         batch_free(b);
         return fail(PSO_ENOMEM, "hipMalloc of %zu bytes for the batch failed", total);
     }
@@ -512,7 +528,8 @@ int pso_batch_create(const pso_desc *descs, int64_t count, void *hip_stream, pso
     for (int64_t i = 0; i < count; ++i) {
         const pso_desc &d = descs[i];
         pso::BatchItem &it = b->items[i];
-        it.a = pso::bind(static_cast<char *>(b->slab) + off[i], lay[i], (uint64_t)d.N, d.D);
+        char *base = static_cast<char *>(b->slab) + off[i];
+        it.a = pso::bind(base, lay[i], (uint64_t)d.N, d.D);
         it.a.lo = d.bounds[0];
         it.a.hi = d.bounds[1];
         it.a.w = d.w;
@@ -522,10 +539,10 @@ int pso_batch_create(const pso_desc *descs, int64_t count, void *hip_stream, pso
         it.a.k0 = (uint32_t)d.seed;
         it.a.k1 = (uint32_t)(d.seed >> 32);
         it.fitness = d.fitness_id;
-        it.pad = 0;
         it.max_iter = d.max_iter;
         it.tol = d.tol;
         it.fstar = d.f_star;
+        pso::bind_gang(&it, base + lay[i].total, parts[i]);
         shifts.assign(d.D, 0.0f);
         if (d.shift) std::memcpy(shifts.data(), d.shift, sizeof(float) * d.D);
         if (hipMemcpy(const_cast<float *>(it.a.shift), shifts.data(), sizeof(float) * d.D, hipMemcpyHostToDevice) !=
@@ -534,26 +551,27 @@ int pso_batch_create(const pso_desc *descs, int64_t count, void *hip_stream, pso
             return fail(PSO_EDEVICE, "shift upload failed");
         }
     }
-    // largest work first: the persistent workgroups drain the queue in this order
+    // largest work first (the persistent workgroups drain the queue in this
+    // order); a swarm's parts are consecutive
     std::vector<uint32_t> order(count);
     for (int64_t i = 0; i < count; ++i) order[i] = (uint32_t)i;
     std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) {
-        const double wx = double(descs[x].N) * descs[x].D * double(descs[x].max_iter + 1);
-        const double wy = double(descs[y].N) * descs[y].D * double(descs[y].max_iter + 1);
+        const double wx = double(descs[x].N) * descs[x].D * double(descs[x].max_iter + 1) / parts[x];
+        const double wy = double(descs[y].N) * descs[y].D * double(descs[y].max_iter + 1) / parts[y];
         return wx > wy;
     });
+    std::vector<pso::BatchEntry> entries;
+    entries.reserve(n_entries);
+    for (uint32_t i : order)
+        for (uint32_t p = 0; p < parts[i]; ++p) entries.push_back(pso::BatchEntry{i, p, i, 0u});
     if (hipMemcpy(b->d_items, b->items.data(), sizeof(pso::BatchItem) * count, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(b->d_order, order.data(), sizeof(uint32_t) * count, hipMemcpyHostToDevice) != hipSuccess) {
+        hipMemcpy(b->d_entries, entries.data(), sizeof(pso::BatchEntry) * n_entries, hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        hipMemset(b->d_err, 0, sizeof(unsigned int)) != hipSuccess) {
         batch_free(b);
         return fail(PSO_EDEVICE, "descriptor upload failed");
     }
-    int dev = 0, cus = 0, per_cu = 0;
-    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        pso::batch_occupancy(maxD, &per_cu) != hipSuccess || cus < 1) {
-        batch_free(b);
-        return fail(PSO_EDEVICE, "device query failed");
-    }
-    b->grid = (int)std::min<int64_t>(count, int64_t(cus) * std::max(1, per_cu));
+    b->grid = (int)std::min<int64_t>(n_entries, capacity);
     *out = b;
     return PSO_OK;
 }
@@ -561,9 +579,9 @@ int pso_batch_create(const pso_desc *descs, int64_t count, void *hip_stream, pso
 int pso_batch_launch(pso_batch *b)
 {
     if (!b) return fail(PSO_EINVAL, "batch is NULL");
-    HIP_TRY(pso::launch_batch_reset(b->d_results, (uint32_t)b->count, b->d_next, b->stream));
-    HIP_TRY(pso::launch_batch(b->d_items, b->d_order, b->d_results, (uint32_t)b->count, b->d_next, b->maxD, b->grid,
-                              (long long)1 << 62, b->stream));
+    HIP_TRY(pso::launch_batch_reset(b->d_items, b->d_results, (uint32_t)b->count, b->d_next, b->stream));
+    HIP_TRY(pso::launch_batch(b->d_items, b->d_entries, b->d_results, b->n_entries, b->d_next, b->maxD, b->grid,
+                              (long long)1 << 62, (long long)1 << 62, b->stream, nullptr, nullptr, b->d_err));
     return PSO_OK;
 }
 
@@ -572,6 +590,9 @@ int pso_batch_results(pso_batch *b, pso_result *results)
     if (!b) return fail(PSO_EINVAL, "batch is NULL");
     if (!results) return fail(PSO_EINVAL, "results is NULL");
     HIP_TRY(hipStreamSynchronize(b->stream));
+    unsigned int err = 0;
+    HIP_TRY(hipMemcpy(&err, b->d_err, sizeof err, hipMemcpyDeviceToHost));
+    if (err) return fail(PSO_EDEVICE, "a batched swarm's parts timed out waiting for each other");
     std::vector<pso::BatchResult> r(b->count);
     HIP_TRY(hipMemcpy(r.data(), b->d_results, sizeof(pso::BatchResult) * b->count, hipMemcpyDeviceToHost));
     for (int64_t i = 0; i < b->count; ++i) {

@@ -66,6 +66,7 @@ Layout layout_of(uint64_t N, int D, bool control)
     L.gpos = o;  o += align256(sizeof(float) * D);
     L.shift = o; o += align256(sizeof(float) * D);
     L.hist = o;  o += control ? align256(sizeof(unsigned long long) * HIST_CAP) : 0;
+    L.aux = o;   o += control ? align256(sizeof(unsigned long long) * ((Np / 4 + BLOCK - 1) / BLOCK)) : 0;
     L.pf = o;    o += align256(sizeof(float) * Np);
     L.pend = o;  o += align256(Np);
     L.x = o;     o += align256(sizeof(float) * Np * (size_t)D);
@@ -83,6 +84,7 @@ SwarmArgs bind(void *base, const Layout &L, uint64_t N, int D)
     a.gpos = reinterpret_cast<float *>(b + L.gpos);
     a.shift = reinterpret_cast<const float *>(b + L.shift);
     a.hist = L.control ? reinterpret_cast<unsigned long long *>(b + L.hist) : nullptr;
+    a.aux = L.control ? reinterpret_cast<unsigned long long *>(b + L.aux) : nullptr;
     a.pf = reinterpret_cast<float *>(b + L.pf);
     a.pend = reinterpret_cast<uint8_t *>(b + L.pend);
     a.x = reinterpret_cast<float *>(b + L.x);
@@ -369,6 +371,88 @@ __global__ void PSO_STEP_ATTR k_step(SwarmArgs a)
 }
 
 // ---------------------------------------------------------------------------
+// The paper's comparator (Sec. 2.2, Fig. 1): a two-kernel parallel
+// reduction.  Kernel 1 updates the particles and reduces every particle's
+// pbest key over its block with a shared-memory tree (log2 of the block
+// size steps, a barrier each; UNROLLED ends with the last wavefront's steps
+// unrolled without barriers) into an auxiliary array; kernel 2, one block,
+// reduces the auxiliary array into the gbest.  Same results as the
+// synchronous variant; two launches per iteration.
+// ---------------------------------------------------------------------------
+template <bool UNROLLED>
+__device__ __forceinline__ unsigned long long tree_min(unsigned long long key, unsigned long long *sh)
+{
+    const int tid = threadIdx.x;
+    sh[tid] = key;
+    __syncthreads();
+    const int stop = UNROLLED ? 64 : 1;
+    for (int s = BLOCK / 2; s >= stop; s >>= 1) {
+        if (tid < s) sh[tid] = sh[tid] < sh[tid + s] ? sh[tid] : sh[tid + s];
+        __syncthreads();
+    }
+    if (UNROLLED && tid < 64) {
+        // the last 64 keys: one wavefront, lanes in lockstep
+        volatile unsigned long long *v = sh;
+        unsigned long long m = v[tid];
+#pragma unroll
+        for (int s = 32; s >= 1; s >>= 1) {
+            const unsigned long long o = __shfl_xor(m, s, 64);
+            m = o < m ? o : m;
+        }
+        if (tid == 0) v[0] = m;
+    }
+    __syncthreads();
+    return sh[0];
+}
+
+template <int FIT, int DC, bool UNROLLED>
+__global__ void PSO_STEP_ATTR k_step_reduce(SwarmArgs a)
+{
+    __shared__ unsigned long long sh[BLOCK];
+    extern __shared__ float s_dyn[];
+    Ctrl *c = a.ctrl;
+    if (c->stop) return;
+    const int D = DC > 0 ? DC : a.D;
+    float *s_g = s_dyn, *s_shift = s_dyn + D;
+    const uint32_t t = (uint32_t)(c->t + 1);
+    for (int d = threadIdx.x; d < D; d += BLOCK) {
+        s_g[d] = a.gpos[d];
+        s_shift[d] = a.shift[d];
+    }
+    __syncthreads();
+    const uint32_t q = blockIdx.x * BLOCK + threadIdx.x;
+    unsigned long long key = NO_KEY;
+    if (4 * q < a.N) {
+        iterate_quad<FIT, DC, PSO_STEP_UNROLL>(a, D, q, t, s_g, s_shift);
+        // every particle's pbest key, improved or not
+        const f4 pf = *reinterpret_cast<const f4 *>(a.pf + 4 * q);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (4 * q + k < a.N) {
+                const unsigned long long kk = make_key(pf[k], 4 * q + k);
+                key = kk < key ? kk : key;
+            }
+    }
+    const unsigned long long m = tree_min<UNROLLED>(key, sh);
+    if (threadIdx.x == 0) a.aux[blockIdx.x] = m;
+}
+
+template <bool UNROLLED>
+__global__ void __launch_bounds__(BLOCK) k_reduce_final(SwarmArgs a, uint32_t nblocks)
+{
+    __shared__ unsigned long long sh[BLOCK];
+    Ctrl *c = a.ctrl;
+    if (c->stop) return;
+    const uint32_t t = (uint32_t)(c->t + 1);
+    unsigned long long key = NO_KEY;
+    for (uint32_t b = threadIdx.x; b < nblocks; b += BLOCK) key = a.aux[b] < key ? a.aux[b] : key;
+    const unsigned long long m = tree_min<UNROLLED>(key, sh);
+    if (threadIdx.x == 0) c->gkey = m;
+    __syncthreads();
+    epilogue<VAR_SYNC>(a, t, false);
+}
+
+// ---------------------------------------------------------------------------
 // Pending pbest positions: complete them (before the state is read) or drop
 // the marks (after the state is replaced).
 // ---------------------------------------------------------------------------
@@ -440,18 +524,33 @@ static void launch_step_fv(const SwarmArgs &a, hipStream_t stream)
     }
 }
 
+template <int FIT, bool UNROLLED>
+static void launch_reduce(const SwarmArgs &a, hipStream_t stream)
+{
+    const size_t lds = 2 * sizeof(float) * a.D;
+    const dim3 g = grid_of(a);
+    switch (PSO_STEP_EXACT_D ? a.D : 0) {
+    case 2: hipLaunchKernelGGL((k_step_reduce<FIT, 2, UNROLLED>), g, dim3(BLOCK), lds, stream, a); break;
+    case 32: hipLaunchKernelGGL((k_step_reduce<FIT, 32, UNROLLED>), g, dim3(BLOCK), lds, stream, a); break;
+    default: hipLaunchKernelGGL((k_step_reduce<FIT, 0, UNROLLED>), g, dim3(BLOCK), lds, stream, a); break;
+    }
+    hipLaunchKernelGGL(k_reduce_final<UNROLLED>, dim3(1), dim3(BLOCK), 0, stream, a, g.x);
+}
+
 template <int FIT>
 static void launch_step_f(int variant, const SwarmArgs &a, hipStream_t stream)
 {
-    if (variant == VAR_SYNC)
-        launch_step_fv<FIT, VAR_SYNC>(a, stream);
-    else
-        launch_step_fv<FIT, VAR_ASYNC>(a, stream);
+    switch (variant) {
+    case VAR_SYNC: launch_step_fv<FIT, VAR_SYNC>(a, stream); break;
+    case VAR_ASYNC: launch_step_fv<FIT, VAR_ASYNC>(a, stream); break;
+    case VAR_REDUCE: launch_reduce<FIT, false>(a, stream); break;
+    default: launch_reduce<FIT, true>(a, stream); break;
+    }
 }
 
 hipError_t launch_step(int fitness, int variant, const SwarmArgs &a, hipStream_t stream)
 {
-    if (variant != VAR_SYNC && variant != VAR_ASYNC) return hipErrorInvalidValue;
+    if (variant < VAR_SYNC || variant > VAR_REDUCE_UNROLLED) return hipErrorInvalidValue;
     switch (fitness) {
     case F_SPHERE: launch_step_f<F_SPHERE>(variant, a, stream); break;
     case F_RASTRIGIN: launch_step_f<F_RASTRIGIN>(variant, a, stream); break;

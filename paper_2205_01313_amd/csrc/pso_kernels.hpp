@@ -39,9 +39,12 @@ static_assert(sizeof(Ctrl) == 1024, "Ctrl layout");
 
 constexpr unsigned int ERR_SEQLOCK_SPIN = 1u; // a seqlock wait gave up
 
-// Aggregation variants (values of PSO_SYNC / PSO_ASYNC in pso.h).
+// Aggregation variants (values of PSO_SYNC / PSO_ASYNC / PSO_REDUCE /
+// PSO_REDUCE_UNROLLED in pso.h).
 constexpr int VAR_SYNC = 0;
 constexpr int VAR_ASYNC = 1;
+constexpr int VAR_REDUCE = 2;
+constexpr int VAR_REDUCE_UNROLLED = 3;
 
 // Device pointers and parameters of one swarm, passed by value to kernels
 // (the kernel-argument segment is read through the scalar cache, the role
@@ -52,6 +55,7 @@ struct SwarmArgs {
     float *gpos;                // D
     const float *shift;         // D
     unsigned long long *hist;   // HIST_CAP
+    unsigned long long *aux;    // one key per step workgroup (two-kernel reduction)
     Ctrl *ctrl;
     uint32_t N;
     uint32_t Np;                // row pitch: N rounded up to a multiple of 64
@@ -64,7 +68,7 @@ struct SwarmArgs {
 // Np = N rounded up to 64 particles, so every row starts 256-byte aligned and
 // a lane can move four consecutive particles with one 16-byte access.
 struct Layout {
-    size_t ctrl, gpos, shift, hist, pf, pend, x, v, p, total;
+    size_t ctrl, gpos, shift, hist, aux, pf, pend, x, v, p, total;
     uint64_t Np;
     bool control; // ctrl and hist present
 };

@@ -51,11 +51,16 @@ struct Req {
     int status = PSO_EAGAIN; // PSO_OK when done, PSO_ENOMEM when rejected
     size_t off = 0;
     int slot = -1;
+    uint32_t parts = 1;
     pso::BatchResult res{};
     std::vector<float> gpos;
 };
 
 constexpr int STREAMS = 2;
+// At most this many iterations of a swarm per launch: a launch ends when its
+// slowest swarm's chunk does, so short, even chunks keep every swarm moving.
+constexpr long long ITER_CAP = 16;
+constexpr int MAX_SERVER_D = 4096; // LDS of a launch is sized for the largest D it lists
 
 } // namespace
 
@@ -69,8 +74,9 @@ struct pso_server {
     void *base = nullptr;
     pso::BatchItem *d_items = nullptr;
     pso::BatchResult *d_state = nullptr;
-    uint32_t *d_order[STREAMS] = {};
+    pso::BatchEntry *d_entries[STREAMS] = {};
     unsigned int *d_next[STREAMS] = {};
+    unsigned int *d_err = nullptr;
     pso::BatchResult *d_out[STREAMS] = {}; // compact state of a launch's items
     float *d_opos[STREAMS] = {};           // compact gbest positions (cap_pos floats)
     size_t cap_pos[STREAMS] = {};
@@ -78,7 +84,9 @@ struct pso_server {
     // pinned staging
     pso::BatchItem *h_items = nullptr;   // max_slots
     pso::BatchResult *h_state = nullptr; // max_slots (fresh state for new swarms)
-    uint32_t *h_order[STREAMS] = {};
+    pso::BatchEntry *h_entries[STREAMS] = {};
+    size_t cap_entries[STREAMS] = {};
+    unsigned int *h_err[STREAMS] = {};
     pso::BatchResult *h_out[STREAMS] = {};
     std::vector<float> h_opos[STREAMS];
     hipStream_t st[STREAMS] = {};
@@ -95,6 +103,8 @@ struct pso_server {
     // scheduler-thread state
     std::vector<int> ready;              // started or new swarms not in flight
     std::vector<int> fresh;              // slots whose item/state must be uploaded
+    std::vector<int> fresh_gang;         // of those, slots whose gang counter must be cleared
+    pso::GangSync *h_gang0 = nullptr;    // pinned zeroed GangSync
     std::vector<int> inflight[STREAMS];  // slots of each in-flight launch
     bool busy[STREAMS] = {};
     std::thread th;
@@ -119,18 +129,21 @@ void server_free(pso_server *s)
     (void)hipFree(s->base);
     (void)hipFree(s->d_items);
     (void)hipFree(s->d_state);
+    (void)hipFree(s->d_err);
     for (int k = 0; k < STREAMS; ++k) {
-        (void)hipFree(s->d_order[k]);
+        (void)hipFree(s->d_entries[k]);
         (void)hipFree(s->d_next[k]);
         (void)hipFree(s->d_out[k]);
         (void)hipFree(s->d_opos[k]);
-        (void)hipHostFree(s->h_order[k]);
+        (void)hipHostFree(s->h_entries[k]);
+        (void)hipHostFree(s->h_err[k]);
         (void)hipHostFree(s->h_out[k]);
         if (s->ev[k]) (void)hipEventDestroy(s->ev[k]);
         if (s->st[k]) (void)hipStreamDestroy(s->st[k]);
     }
     (void)hipHostFree(s->h_items);
     (void)hipHostFree(s->h_state);
+    (void)hipHostFree(s->h_gang0);
     delete s;
 }
 
@@ -152,6 +165,7 @@ pso::BatchItem make_item(pso_server *s, const Req &r)
     it.max_iter = r.d.max_iter;
     it.tol = r.d.tol;
     it.fstar = r.d.f_star;
+    pso::bind_gang(&it, static_cast<char *>(s->base) + r.off + L.total, r.parts);
     return it;
 }
 
@@ -171,14 +185,41 @@ bool launch_ready(pso_server *s, int k)
                            hipMemcpyHostToDevice, st) != hipSuccess)
             return false;
     }
+    for (int slot : s->fresh_gang)
+        if (hipMemcpyAsync(s->h_items[slot].gang, s->h_gang0, sizeof(pso::GangSync), hipMemcpyHostToDevice, st) !=
+            hipSuccess)
+            return false;
     s->fresh.clear();
+    s->fresh_gang.clear();
+    // largest per-part work first; a swarm's parts are consecutive
+    std::stable_sort(s->ready.begin(), s->ready.end(), [&](int x, int y) {
+        const Req *a = s->slot_req[x], *b = s->slot_req[y];
+        return double(a->d.N) * a->d.D / a->parts > double(b->d.N) * b->d.D / b->parts;
+    });
     const int n = (int)s->ready.size();
     int maxD = 1;
-    for (int j = 0; j < n; ++j) {
-        s->h_order[k][j] = (uint32_t)s->ready[j];
-        maxD = std::max(maxD, (int)s->slot_req[s->ready[j]]->d.D);
+    size_t need_entries = 0;
+    for (int j = 0; j < n; ++j) need_entries += s->slot_req[s->ready[j]]->parts;
+    if (need_entries > s->cap_entries[k]) { // grow the entry lists of this stream
+        if (hipStreamSynchronize(st) != hipSuccess) return false;
+        (void)hipFree(s->d_entries[k]);
+        (void)hipHostFree(s->h_entries[k]);
+        s->d_entries[k] = nullptr;
+        s->h_entries[k] = nullptr;
+        s->cap_entries[k] = std::max(need_entries, 2 * s->cap_entries[k]);
+        if (hipMalloc(&s->d_entries[k], sizeof(pso::BatchEntry) * s->cap_entries[k]) != hipSuccess ||
+            hipHostMalloc(reinterpret_cast<void **>(&s->h_entries[k]), sizeof(pso::BatchEntry) * s->cap_entries[k],
+                          hipHostMallocDefault) != hipSuccess)
+            return false;
     }
-    if (hipMemcpyAsync(s->d_order[k], s->h_order[k], sizeof(uint32_t) * n, hipMemcpyHostToDevice, st) != hipSuccess)
+    uint32_t ne = 0;
+    for (int j = 0; j < n; ++j) {
+        const Req *r = s->slot_req[s->ready[j]];
+        for (uint32_t p = 0; p < r->parts; ++p) s->h_entries[k][ne++] = pso::BatchEntry{(uint32_t)s->ready[j], p, (uint32_t)j, 0u};
+        maxD = std::max(maxD, (int)r->d.D);
+    }
+    if (hipMemcpyAsync(s->d_entries[k], s->h_entries[k], sizeof(pso::BatchEntry) * ne, hipMemcpyHostToDevice, st) !=
+        hipSuccess)
         return false;
     const size_t need = (size_t)n * maxD;
     if (need > s->cap_pos[k]) { // grow the compact position buffer
@@ -188,11 +229,12 @@ bool launch_ready(pso_server *s, int k)
         s->cap_pos[k] = std::max(need, 2 * s->cap_pos[k]);
         if (hipMalloc(&s->d_opos[k], sizeof(float) * s->cap_pos[k]) != hipSuccess) return false;
     }
-    const int grid = std::min(n, s->grid_cap);
-    if (pso::launch_batch(s->d_items, s->d_order[k], s->d_state, (uint32_t)n, s->d_next[k], maxD, grid, s->chunk, st,
-                          s->d_out[k], s->d_opos[k]) != hipSuccess)
+    const int grid = std::min<int>((int)ne, s->grid_cap);
+    if (pso::launch_batch(s->d_items, s->d_entries[k], s->d_state, ne, s->d_next[k], maxD, grid, s->chunk, ITER_CAP,
+                          st, s->d_out[k], s->d_opos[k], s->d_err) != hipSuccess)
         return false;
-    if (hipMemcpyAsync(s->h_out[k], s->d_out[k], sizeof(pso::BatchResult) * n, hipMemcpyDeviceToHost, st) != hipSuccess)
+    if (hipMemcpyAsync(s->h_out[k], s->d_out[k], sizeof(pso::BatchResult) * n, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(s->h_err[k], s->d_err, sizeof(unsigned int), hipMemcpyDeviceToHost, st) != hipSuccess)
         return false;
     if (hipEventRecord(s->ev[k], st) != hipSuccess) return false;
     s->launch_maxD[k] = maxD;
@@ -211,6 +253,7 @@ bool launch_ready(pso_server *s, int k)
 bool collect(pso_server *s, int k)
 {
     hipStream_t st = s->st[k];
+    if (*s->h_err[k]) return false; // parts of a swarm timed out waiting for each other
     const int n = (int)s->inflight[k].size();
     const int maxD = s->launch_maxD[k];
     std::vector<int> done_j;
@@ -278,6 +321,7 @@ void server_loop(pso_server *s)
                 s->h_items[r->slot] = make_item(s, *r);
                 s->h_state[r->slot] = pso::BatchResult{pso::NO_KEY, 0, 0, 0u, 0u};
                 s->fresh.push_back(r->slot);
+                if (r->parts > 1) s->fresh_gang.push_back(r->slot);
                 s->ready.push_back(r->slot);
                 progressed = true;
             }
@@ -330,29 +374,35 @@ int pso_server_create(size_t mem_budget, int64_t chunk_updates, pso_server **out
     s->arena = pso::Arena(mem_budget);
     // at most one slot per 64 KiB of budget, within [64, 65536]
     s->max_slots = (int)std::min<size_t>(65536, std::max<size_t>(64, mem_budget / 65536));
-    int dev = 0, cus = 0, per_cu = 0;
-    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
-                                                hipSuccess) {
+    // two launches may run at once: each gets half of the co-resident
+    // workgroups, so every launch's grid stays fully resident
+    int capacity = 0;
+    if (pso::batch_capacity(MAX_SERVER_D, &capacity) != hipSuccess || capacity < 2) {
         server_free(s);
         return pso_internal_fail(PSO_EDEVICE, "device query failed");
     }
-    if (pso::batch_occupancy(64, &per_cu) != hipSuccess) per_cu = 1;
-    s->grid_cap = std::max(1, cus * std::max(1, per_cu));
+    s->grid_cap = capacity / STREAMS;
     bool ok = hipMalloc(&s->base, mem_budget) == hipSuccess &&
               hipMalloc(&s->d_items, sizeof(pso::BatchItem) * s->max_slots) == hipSuccess &&
               hipMalloc(&s->d_state, sizeof(pso::BatchResult) * s->max_slots) == hipSuccess &&
+              hipMalloc(&s->d_err, sizeof(unsigned int)) == hipSuccess &&
+              hipMemset(s->d_err, 0, sizeof(unsigned int)) == hipSuccess &&
+              hipHostMalloc(reinterpret_cast<void **>(&s->h_gang0), sizeof(pso::GangSync), hipHostMallocDefault) ==
+                  hipSuccess &&
               hipHostMalloc(reinterpret_cast<void **>(&s->h_items), sizeof(pso::BatchItem) * s->max_slots,
                             hipHostMallocDefault) == hipSuccess &&
               hipHostMalloc(reinterpret_cast<void **>(&s->h_state), sizeof(pso::BatchResult) * s->max_slots,
                             hipHostMallocDefault) == hipSuccess;
     for (int k = 0; ok && k < STREAMS; ++k) {
-        ok = hipMalloc(&s->d_order[k], sizeof(uint32_t) * s->max_slots) == hipSuccess &&
+        ok = hipMalloc(&s->d_entries[k], sizeof(pso::BatchEntry) * s->max_slots) == hipSuccess &&
              hipMalloc(&s->d_next[k], sizeof(unsigned int)) == hipSuccess &&
              hipMalloc(&s->d_out[k], sizeof(pso::BatchResult) * s->max_slots) == hipSuccess &&
              hipHostMalloc(reinterpret_cast<void **>(&s->h_out[k]), sizeof(pso::BatchResult) * s->max_slots,
                            hipHostMallocDefault) == hipSuccess &&
-             hipHostMalloc(reinterpret_cast<void **>(&s->h_order[k]), sizeof(uint32_t) * s->max_slots,
+             hipHostMalloc(reinterpret_cast<void **>(&s->h_entries[k]), sizeof(pso::BatchEntry) * s->max_slots,
                            hipHostMallocDefault) == hipSuccess &&
+             hipHostMalloc(reinterpret_cast<void **>(&s->h_err[k]), sizeof(unsigned int), hipHostMallocDefault) ==
+                 hipSuccess &&
              hipStreamCreateWithFlags(&s->st[k], hipStreamNonBlocking) == hipSuccess &&
              hipEventCreateWithFlags(&s->ev[k], hipEventDisableTiming) == hipSuccess;
     }
@@ -360,6 +410,8 @@ int pso_server_create(size_t mem_budget, int64_t chunk_updates, pso_server **out
         server_free(s);
         return pso_internal_fail(PSO_ENOMEM, "device or pinned allocation for the server failed");
     }
+    std::memset(s->h_gang0, 0, sizeof(pso::GangSync));
+    for (int k = 0; k < STREAMS; ++k) s->cap_entries[k] = (size_t)s->max_slots;
     s->slot_req.assign(s->max_slots, nullptr);
     for (int k = s->max_slots - 1; k >= 0; --k) s->free_slots.push_back(k);
     s->th = std::thread(server_loop, s);
@@ -379,7 +431,8 @@ int pso_server_submit(pso_server *s, const pso_desc *d, uint64_t *ticket)
     if (d->shift) std::memcpy(r->shift.data(), d->shift, sizeof(float) * d->D);
     r->d.shift = nullptr;
     r->t_submit = Clock::now();
-    const size_t bytes = pso::layout_of((uint64_t)d->N, d->D, false).total;
+    r->parts = pso::parts_for((uint64_t)d->N, d->D, s->grid_cap);
+    const size_t bytes = pso::layout_of((uint64_t)d->N, d->D, false).total + pso::gang_bytes(r->parts, d->D);
     std::lock_guard<std::mutex> g(s->mu);
     r->ticket = s->next_ticket++;
     *ticket = r->ticket;

@@ -80,3 +80,21 @@ def test_batch_rejects_bad_descriptor():
     with pytest.raises(pso.PsoError) as e:
         pso.pso_batch_run(specs)
     assert e.value.code == pso.PSO_EINVAL and "descriptor 1" in str(e.value)
+
+
+def test_large_swarms_split_into_parts_equal_alone_and_oracle():
+    """Swarms large enough to be split over several workgroups (parts meet
+    once per iteration) compute the same bits as alone and as the oracle."""
+    specs = [wl.SwarmSpec("rastrigin", 50000, 16, 25, seed=1, shift_amplitude=1.0),
+             wl.SwarmSpec("ackley", 20000, 33, 20, seed=2, shift_amplitude=2.0),
+             wl.SwarmSpec("rosenbrock", 30001, 40, 15, seed=3),
+             wl.SwarmSpec("sphere", 300, 4, 25, seed=4)]
+    specs[1].tol, specs[1].f_star = 5.0, 0.0
+    announce("batch with multi-part swarms")
+    res = pso.pso_batch_run(specs)
+    for sp, r in zip(specs, res):
+        a = alone(sp)
+        assert r["gbest_fit"] == a["gbest_fit"] and r["iters"] == a["iters"], sp
+        assert r["gbest_iter"] == a["gbest_iter"] and np.array_equal(r["gbest_pos"], a["gbest_pos"]), sp
+        o = oracle_swarm(sp, nthreads=16).run_f32(sp.T, tol=getattr(sp, "tol", 0.0), f_star=getattr(sp, "f_star", 0.0))
+        assert r["gbest_fit"] == o["gbest_fit"] and np.array_equal(r["gbest_pos"], o["gpos"]), sp

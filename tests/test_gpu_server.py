@@ -110,3 +110,13 @@ def test_submit_from_two_threads():
             t.join()
         res = wait_all(srv, tickets)
     check_same(specs[:10], tickets[:10], res)
+
+
+def test_large_requests_split_into_parts():
+    specs = [wl.SwarmSpec("rastrigin", 40000, 24, 40, seed=k, shift_amplitude=1.0) for k in range(3)]
+    specs += mixed_specs(20, 13, max_iter=60)
+    announce("server with multi-part requests")
+    with pso.Server(1 << 30, chunk_updates=1 << 21) as srv:
+        tickets = [srv.submit(sp) for sp in specs]
+        res = wait_all(srv, tickets)
+    check_same(specs, tickets, res)

@@ -187,3 +187,20 @@ def test_improvement_counter_matches_oracle():
         with gpu_swarm(spec) as g:
             g.run(spec.T)
             assert g.counters()["pbest_improvements"] == n
+
+
+@pytest.mark.parametrize("variant", [pso.PSO_REDUCE, pso.PSO_REDUCE_UNROLLED])
+@pytest.mark.parametrize("fit,N,D", [("rastrigin", 70001, 32), ("cubic", 2048, 1), ("ackley", 5000, 7)])
+def test_two_kernel_reduction_comparator_equals_oracle(variant, fit, N, D):
+    """The paper's parallel-reduction comparator (two kernels per iteration)
+    computes exactly the synchronous gbest PSO."""
+    spec = wl.SwarmSpec(fit, N, D, 30, seed=N + D, shift_amplitude=1.0)
+    announce(f"reduction comparator variant={variant} {fit} N={N} D={D}")
+    o = oracle_swarm(spec, nthreads=16).run_f32(spec.T)
+    with gpu_swarm(spec, variant=variant) as g:
+        r = g.run(spec.T)
+        h = g.history(0, spec.T + 1)
+        st = g.state()
+    assert np.array_equal(h, o["hist"])
+    assert r["gbest_iter"] == o["giter"]
+    assert_state_equal(st, o, spec.N, spec.D)
