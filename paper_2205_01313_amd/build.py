@@ -6,6 +6,7 @@ import os
 import shutil
 import subprocess
 import sys
+import tempfile
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -30,11 +31,21 @@ def hipcc() -> str:
 
 
 def build(out: str = LIB, extra=()) -> str:
-    """Compile every source into `out`; raises on failure."""
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = out + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, *extra, "-I", os.path.join(ROOT, "include"), *srcs, "-o", tmp]
-    subprocess.run(cmd, check=True)
+    """Compile every source (in parallel, one object each) and link them into
+    `out`; raises on failure."""
+    inc = ["-I", os.path.join(ROOT, "include")]
+    with tempfile.TemporaryDirectory(prefix="pso_build_") as tmpdir:
+        objs, procs = [], []
+        for src in SOURCES:
+            obj = os.path.join(tmpdir, src.replace(".hip", ".o"))
+            cmd = [hipcc(), *HIPCC_FLAGS, *extra, *inc, "-c", os.path.join(CSRC, src), "-o", obj]
+            procs.append((cmd, subprocess.Popen(cmd)))
+            objs.append(obj)
+        failed = [cmd for cmd, p in procs if p.wait() != 0]
+        if failed:
+            raise subprocess.CalledProcessError(1, failed[0])
+        tmp = out + ".tmp"
+        subprocess.run([hipcc(), *HIPCC_FLAGS, *extra, *objs, "-o", tmp], check=True)
     os.replace(tmp, out)
     return out
 

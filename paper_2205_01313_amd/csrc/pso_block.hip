@@ -26,6 +26,11 @@
 #ifndef PSO_BATCH_LANES
 #define PSO_BATCH_LANES 256 // lanes of a batched swarm's (part's) workgroup
 #endif
+#ifndef PSO_SWARM_POLICY
+// cache policy of the per-swarm workgroup kernels: a workgroup re-reads its
+// swarm's (small) state every iteration, so all of it stays cacheable
+#define PSO_SWARM_POLICY POL_ALL
+#endif
 #ifndef PSO_PART_WORK
 #define PSO_PART_WORK (1 << 17) // particle-dimension updates per part and iteration
 #endif
@@ -115,9 +120,11 @@ __device__ unsigned long long gang_min(const SwarmArgs &a, const Part &P, long l
         for (int d = threadIdx.x; d < D; d += LANES) dst[d] = a.x[(size_t)d * a.Np + gi];
     }
     if (threadIdx.x == 0) P.cand_key[(size_t)b * P.parts + P.part] = m;
-    __threadfence(); // release the candidate before arriving
     __syncthreads();
     if (threadIdx.x == 0) {
+        // release the candidate before arriving: the barrier orders every
+        // lane's stores before this one fence
+        __threadfence();
         atomicAdd(&P.gang->arrive, 1ull);
         const unsigned long long target = (unsigned long long)P.parts * (unsigned long long)(tau + 1);
         const unsigned long long t0 = wall_clock64();
@@ -172,7 +179,7 @@ __device__ void block_init(const SwarmArgs &a, const Part &P, const float *s_shi
     const int D = a.D;
     unsigned long long key = NO_KEY;
     for (uint32_t q = P.qi_lo + threadIdx.x; q < P.qi_hi; q += LANES) {
-        const unsigned long long k = init_quad<FIT>(a, D, q, s_shift);
+        const unsigned long long k = init_quad<FIT, PSO_SWARM_POLICY>(a, D, q, s_shift);
         key = k < key ? k : key;
     }
     const unsigned long long m = block_min(key, NO_KEY, &sc->min[0]);
@@ -203,7 +210,7 @@ __device__ void block_iterate(const SwarmArgs &a, const Part &P, long long T, fl
         unsigned long long key = NO_KEY;
         for (uint32_t q = P.q_lo + threadIdx.x; q < P.q_hi; q += LANES) {
             uint32_t n = 0;
-            const unsigned long long k = iterate_quad<FIT, 0, 1>(a, D, q, t, s_g, s_shift, &n);
+            const unsigned long long k = iterate_quad<FIT, 0, 1, PSO_SWARM_POLICY>(a, D, q, t, s_g, s_shift, &n);
             key = k < key ? k : key;
             n_imp += n;
         }

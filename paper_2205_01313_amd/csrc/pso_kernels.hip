@@ -42,6 +42,22 @@
 #define PSO_BLOCK 256
 #endif
 
+// Bytes of the streamed state that may be kept resident in the memory-side
+// cache (MI355X: 256 MiB of Infinity Cache in front of HBM).  Three quarters
+// of it leaves room for pf, the pending marks and other traffic.  Up to twice
+// the cache, keeping x alone still pays (part of it stays resident); beyond
+// that everything streams.  Both limits are measured on gfx950.
+#ifndef PSO_KEEP_BUDGET_MIB
+#define PSO_KEEP_BUDGET_MIB 192
+#endif
+#ifndef PSO_KEEP_X_MAX_MIB
+#define PSO_KEEP_X_MAX_MIB 512
+#endif
+// -1 chooses the cache policy from the state size; 0..7 forces one.
+#ifndef PSO_CACHE_POLICY
+#define PSO_CACHE_POLICY -1
+#endif
+
 #if PSO_STEP_WAVES_PER_EU > 0
 #define PSO_STEP_ATTR __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(PSO_STEP_WAVES_PER_EU)))
 #else
@@ -74,6 +90,19 @@ Layout layout_of(uint64_t N, int D, bool control)
     L.p = o;     o += align256(sizeof(float) * Np * (size_t)D);
     L.total = o;
     return L;
+}
+
+int cache_policy(uint64_t Np, int D)
+{
+    if (PSO_CACHE_POLICY >= 0) return PSO_CACHE_POLICY == 0 ? POL_STREAM
+                                      : PSO_CACHE_POLICY == 1 ? POL_X
+                                      : PSO_CACHE_POLICY == 3 ? POL_XV
+                                                              : POL_ALL;
+    const uint64_t row = sizeof(float) * Np * (uint64_t)D, budget = (uint64_t)PSO_KEEP_BUDGET_MIB << 20;
+    if (3 * row <= budget) return POL_ALL;
+    if (2 * row <= budget) return POL_XV;
+    if (row <= ((uint64_t)PSO_KEEP_X_MAX_MIB << 20)) return POL_X;
+    return POL_STREAM;
 }
 
 SwarmArgs bind(void *base, const Layout &L, uint64_t N, int D)
@@ -131,30 +160,33 @@ __device__ __forceinline__ void flush_count(Ctrl *c, const unsigned int *wg_coun
 
 // Arrival count: true in every lane of the last workgroup of the launch,
 // after an acquire fence.
+// Lane 0 alone fences: the barrier orders the other lanes' later loads
+// after its acquire.
 __device__ __forceinline__ bool arrive_last(Ctrl *c, int *last_flag)
 {
     if (threadIdx.x == 0) {
         const unsigned int ticket = atomicAdd(&c->arrive, 1u);
-        *last_flag = (ticket == gridDim.x - 1);
+        const int last = (ticket == gridDim.x - 1);
+        if (last) __threadfence(); // acquire every workgroup's results
+        *last_flag = last;
     }
     __syncthreads();
-    if (*last_flag) {
-        __threadfence(); // acquire every workgroup's results
-        return true;
-    }
-    return false;
+    return *last_flag != 0;
 }
 
 // Synchronous aggregation: the workgroup minimum goes to the global key.
+// Called after the barrier that ends workgroup_min, so every lane's x stores
+// precede lane 0's release fence at workgroup scope; one agent-scope fence
+// per workgroup then publishes them all (a fence per wavefront costs ~5 us
+// per iteration at 1024 workgroups).  A candidate already beaten by the
+// running global key cannot win and is not published (keys are unique).
 __device__ __forceinline__ void publish_sync(Ctrl *c, unsigned long long m, unsigned long long thr)
 {
-    if (m < thr) {
+    if (m < thr && threadIdx.x == 0 &&
+        m < __hip_atomic_load(&c->gkey, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
         __threadfence(); // release this workgroup's stores (the winner's x)
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            atomicMin(&c->gkey, m);
-            __threadfence(); // the minimum precedes the arrival
-        }
+        atomicMin(&c->gkey, m);
+        __threadfence(); // the minimum precedes the arrival
     }
 }
 
@@ -304,7 +336,7 @@ __global__ void k_arm(SwarmArgs a, float tol, float fstar)
 // Step 1 (Alg. 1) over the whole grid; lane q initialises particles 4q..4q+3
 // (the padding past N included).
 // ---------------------------------------------------------------------------
-template <int FIT>
+template <int FIT, int POL>
 __global__ void __launch_bounds__(BLOCK) k_init(SwarmArgs a)
 {
     __shared__ unsigned long long wg_min;
@@ -315,7 +347,7 @@ __global__ void __launch_bounds__(BLOCK) k_init(SwarmArgs a)
     if (threadIdx.x == 0) wg_min = NO_KEY;
     __syncthreads();
     const uint32_t q = blockIdx.x * BLOCK + threadIdx.x;
-    const unsigned long long key = (4 * q < a.Np) ? init_quad<FIT>(a, D, q, s_shift) : NO_KEY;
+    const unsigned long long key = (4 * q < a.Np) ? init_quad<FIT, POL>(a, D, q, s_shift) : NO_KEY;
     const unsigned long long m = workgroup_min(key, NO_KEY, &wg_min);
     publish_sync(a.ctrl, m, NO_KEY);
     if (arrive_last(a.ctrl, &last)) epilogue<VAR_SYNC>(a, 0u, true);
@@ -326,7 +358,7 @@ __global__ void __launch_bounds__(BLOCK) k_init(SwarmArgs a)
 // gbest position and the shift vector are staged in LDS (each dimension's
 // value is one broadcast read).  DC > 0 fixes D at compile time.
 // ---------------------------------------------------------------------------
-template <int FIT, int DC, int VAR>
+template <int FIT, int DC, int VAR, int POL>
 __global__ void PSO_STEP_ATTR k_step(SwarmArgs a)
 {
     __shared__ unsigned long long wg_min;
@@ -357,7 +389,7 @@ __global__ void PSO_STEP_ATTR k_step(SwarmArgs a)
     const uint32_t q = blockIdx.x * BLOCK + threadIdx.x;
     uint32_t n_imp = 0;
     const unsigned long long key =
-        (4 * q < a.N) ? iterate_quad<FIT, DC, PSO_STEP_UNROLL>(a, D, q, t, s_g, s_shift, &n_imp) : NO_KEY;
+        (4 * q < a.N) ? iterate_quad<FIT, DC, PSO_STEP_UNROLL, POL>(a, D, q, t, s_g, s_shift, &n_imp) : NO_KEY;
     count_improvements(c, n_imp, &wg_count);
     const unsigned long long m = workgroup_min(key, thr, &wg_min);
     flush_count(c, &wg_count);
@@ -405,7 +437,7 @@ __device__ __forceinline__ unsigned long long tree_min(unsigned long long key, u
     return sh[0];
 }
 
-template <int FIT, int DC, bool UNROLLED>
+template <int FIT, int DC, bool UNROLLED, int POL>
 __global__ void PSO_STEP_ATTR k_step_reduce(SwarmArgs a)
 {
     __shared__ unsigned long long sh[BLOCK];
@@ -423,7 +455,7 @@ __global__ void PSO_STEP_ATTR k_step_reduce(SwarmArgs a)
     const uint32_t q = blockIdx.x * BLOCK + threadIdx.x;
     unsigned long long key = NO_KEY;
     if (4 * q < a.N) {
-        iterate_quad<FIT, DC, PSO_STEP_UNROLL>(a, D, q, t, s_g, s_shift);
+        iterate_quad<FIT, DC, PSO_STEP_UNROLL, POL>(a, D, q, t, s_g, s_shift);
         // every particle's pbest key, improved or not
         const f4 pf = *reinterpret_cast<const f4 *>(a.pf + 4 * q);
 #pragma unroll
@@ -498,43 +530,74 @@ hipError_t launch_clear_pending(const SwarmArgs &a, hipStream_t stream)
     return hipGetLastError();
 }
 
-hipError_t launch_init(int fitness, const SwarmArgs &a, hipStream_t stream)
+template <int FIT>
+static void launch_init_f(const SwarmArgs &a, hipStream_t stream)
 {
     const size_t lds = sizeof(float) * a.D;
+    switch (cache_policy(a.Np, a.D)) {
+    case POL_STREAM: hipLaunchKernelGGL((k_init<FIT, POL_STREAM>), grid_all(a), dim3(BLOCK), lds, stream, a); break;
+    case POL_X: hipLaunchKernelGGL((k_init<FIT, POL_X>), grid_all(a), dim3(BLOCK), lds, stream, a); break;
+    case POL_XV: hipLaunchKernelGGL((k_init<FIT, POL_XV>), grid_all(a), dim3(BLOCK), lds, stream, a); break;
+    default: hipLaunchKernelGGL((k_init<FIT, POL_ALL>), grid_all(a), dim3(BLOCK), lds, stream, a); break;
+    }
+}
+
+hipError_t launch_init(int fitness, const SwarmArgs &a, hipStream_t stream)
+{
     switch (fitness) {
-    case F_SPHERE: hipLaunchKernelGGL(k_init<F_SPHERE>, grid_all(a), dim3(BLOCK), lds, stream, a); break;
-    case F_RASTRIGIN: hipLaunchKernelGGL(k_init<F_RASTRIGIN>, grid_all(a), dim3(BLOCK), lds, stream, a); break;
-    case F_ROSENBROCK: hipLaunchKernelGGL(k_init<F_ROSENBROCK>, grid_all(a), dim3(BLOCK), lds, stream, a); break;
-    case F_ACKLEY: hipLaunchKernelGGL(k_init<F_ACKLEY>, grid_all(a), dim3(BLOCK), lds, stream, a); break;
-    case F_CUBIC: hipLaunchKernelGGL(k_init<F_CUBIC>, grid_all(a), dim3(BLOCK), lds, stream, a); break;
+    case F_SPHERE: launch_init_f<F_SPHERE>(a, stream); break;
+    case F_RASTRIGIN: launch_init_f<F_RASTRIGIN>(a, stream); break;
+    case F_ROSENBROCK: launch_init_f<F_ROSENBROCK>(a, stream); break;
+    case F_ACKLEY: launch_init_f<F_ACKLEY>(a, stream); break;
+    case F_CUBIC: launch_init_f<F_CUBIC>(a, stream); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-template <int FIT, int VAR>
-static void launch_step_fv(const SwarmArgs &a, hipStream_t stream)
+template <int FIT, int VAR, int POL>
+static void launch_step_fvp(const SwarmArgs &a, hipStream_t stream)
 {
     const size_t lds = 2 * sizeof(float) * a.D;
     switch (PSO_STEP_EXACT_D ? a.D : 0) {
-    case 2: hipLaunchKernelGGL((k_step<FIT, 2, VAR>), grid_of(a), dim3(BLOCK), lds, stream, a); break;
-    case 32: hipLaunchKernelGGL((k_step<FIT, 32, VAR>), grid_of(a), dim3(BLOCK), lds, stream, a); break;
-    case 128: hipLaunchKernelGGL((k_step<FIT, 128, VAR>), grid_of(a), dim3(BLOCK), lds, stream, a); break;
-    default: hipLaunchKernelGGL((k_step<FIT, 0, VAR>), grid_of(a), dim3(BLOCK), lds, stream, a); break;
+    case 32: hipLaunchKernelGGL((k_step<FIT, 32, VAR, POL>), grid_of(a), dim3(BLOCK), lds, stream, a); break;
+    case 128: hipLaunchKernelGGL((k_step<FIT, 128, VAR, POL>), grid_of(a), dim3(BLOCK), lds, stream, a); break;
+    default: hipLaunchKernelGGL((k_step<FIT, 0, VAR, POL>), grid_of(a), dim3(BLOCK), lds, stream, a); break;
     }
+}
+
+template <int FIT, int VAR>
+static void launch_step_fv(const SwarmArgs &a, hipStream_t stream)
+{
+    switch (cache_policy(a.Np, a.D)) {
+    case POL_STREAM: launch_step_fvp<FIT, VAR, POL_STREAM>(a, stream); break;
+    case POL_X: launch_step_fvp<FIT, VAR, POL_X>(a, stream); break;
+    case POL_XV: launch_step_fvp<FIT, VAR, POL_XV>(a, stream); break;
+    default: launch_step_fvp<FIT, VAR, POL_ALL>(a, stream); break;
+    }
+}
+
+template <int FIT, bool UNROLLED, int POL>
+static void launch_reduce_p(const SwarmArgs &a, hipStream_t stream)
+{
+    const size_t lds = 2 * sizeof(float) * a.D;
+    const dim3 g = grid_of(a);
+    switch (PSO_STEP_EXACT_D ? a.D : 0) {
+    case 32: hipLaunchKernelGGL((k_step_reduce<FIT, 32, UNROLLED, POL>), g, dim3(BLOCK), lds, stream, a); break;
+    default: hipLaunchKernelGGL((k_step_reduce<FIT, 0, UNROLLED, POL>), g, dim3(BLOCK), lds, stream, a); break;
+    }
+    hipLaunchKernelGGL(k_reduce_final<UNROLLED>, dim3(1), dim3(BLOCK), 0, stream, a, g.x);
 }
 
 template <int FIT, bool UNROLLED>
 static void launch_reduce(const SwarmArgs &a, hipStream_t stream)
 {
-    const size_t lds = 2 * sizeof(float) * a.D;
-    const dim3 g = grid_of(a);
-    switch (PSO_STEP_EXACT_D ? a.D : 0) {
-    case 2: hipLaunchKernelGGL((k_step_reduce<FIT, 2, UNROLLED>), g, dim3(BLOCK), lds, stream, a); break;
-    case 32: hipLaunchKernelGGL((k_step_reduce<FIT, 32, UNROLLED>), g, dim3(BLOCK), lds, stream, a); break;
-    default: hipLaunchKernelGGL((k_step_reduce<FIT, 0, UNROLLED>), g, dim3(BLOCK), lds, stream, a); break;
+    switch (cache_policy(a.Np, a.D)) {
+    case POL_STREAM: launch_reduce_p<FIT, UNROLLED, POL_STREAM>(a, stream); break;
+    case POL_X: launch_reduce_p<FIT, UNROLLED, POL_X>(a, stream); break;
+    case POL_XV: launch_reduce_p<FIT, UNROLLED, POL_XV>(a, stream); break;
+    default: launch_reduce_p<FIT, UNROLLED, POL_ALL>(a, stream); break;
     }
-    hipLaunchKernelGGL(k_reduce_final<UNROLLED>, dim3(1), dim3(BLOCK), 0, stream, a, g.x);
 }
 
 template <int FIT>

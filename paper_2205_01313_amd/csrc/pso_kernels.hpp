@@ -64,6 +64,18 @@ struct SwarmArgs {
     uint32_t k0, k1;            // Philox key = seed
 };
 
+// Cache policy of the streamed state x, v, p: a set bit gives that array
+// ordinary (cache-allocating) accesses so it can stay resident in the
+// memory-side last-level cache across iterations; clear bits stream it with
+// non-temporal hints.  Kept arrays must fit in that cache together, or they
+// evict each other and gain nothing.
+constexpr int KEEP_X = 1, KEEP_V = 2, KEEP_P = 4;
+constexpr int POL_STREAM = 0, POL_X = KEEP_X, POL_XV = KEEP_X | KEEP_V, POL_ALL = KEEP_X | KEEP_V | KEEP_P;
+// The policy for rows of Np particles and D dimensions: as many of x, v, p
+// (in that order) as fit together in the cache budget; x alone also for
+// rows up to twice the cache.
+int cache_policy(uint64_t Np, int D);
+
 // Byte layout of a swarm's workspace.  Each dimension's row of x, v, p holds
 // Np = N rounded up to 64 particles, so every row starts 256-byte aligned and
 // a lane can move four consecutive particles with one 16-byte access.
