@@ -28,6 +28,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 COPY_BYTES = 256 << 20  # calibration copy: reads and writes this many bytes
+SIMDS = 1024  # MI355X: 256 compute units x 4 SIMDs
+CLOCK_MHZ = 2400.0
 
 
 # Sources that define the grid step kernel: a counter summary taken on other
@@ -44,10 +46,11 @@ def source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel: str):
-    """HBM bytes per launch (FETCH_SIZE and WRITE_SIZE, each scaled by what it
-    reads for a copy of known size) from the committed rocprofv3 counter
-    summary, if it was taken on the current step-kernel sources; else None."""
+def counters_from_profiles(kernel: str):
+    """Per-launch counter figures of the step kernel from the committed
+    rocprofv3 summary, if it was taken on the current step-kernel sources
+    (else None): HBM bytes (FETCH_SIZE and WRITE_SIZE, each scaled by what it
+    reads for a copy of known size) and VALU instructions (SQ_INSTS_VALU)."""
     path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     if not os.path.exists(path):
         return None
@@ -56,7 +59,7 @@ def traffic_from_profiles(kernel: str):
     ent = rec.get("kernels", {}).get(kernel)
     if not ent or rec.get("source_digest") != source_digest():
         return None
-    return ent["hbm_bytes_per_launch"]
+    return ent
 
 
 def cpu_baseline(spec, iters: int):
@@ -269,7 +272,12 @@ def main():
     alg_bytes = spec.N * spec.D * (20.0 + 4.0 * rho) + spec.N * (4.0 + 4.0 * rho)
     achieved = alg_bytes / (launch_us * 1e-6) / 1e9
     kernel = f"k_step<{spec.fitness}, D={spec.D}, {args.variant}>"
-    traffic = traffic_from_profiles(kernel)
+    counters = counters_from_profiles(kernel)
+    traffic = counters["hbm_bytes_per_launch"] if counters else None
+    # share of SIMD cycles issuing VALU work: a wave64 VALU instruction
+    # occupies its SIMD for 4 cycles; 1024 SIMDs at 2.4 GHz
+    valu_busy = (counters["valu_insts_per_dispatch"] * 4 / SIMDS / (launch_us * CLOCK_MHZ)
+                 if counters and "valu_insts_per_dispatch" in counters else None)
 
     out = {
         "metric": "particle·dim updates/s incl. fitness",
@@ -290,7 +298,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": kernel, "avg_launch_us": launch_us, "alg_bytes_per_launch": alg_bytes,
-                     "pbest_improvement_rate": rho},
+                     "pbest_improvement_rate": rho, "valu_busy_frac": valu_busy},
         "gbest": {"value": float(best["gbest_fit"]), "iteration": int(best["gbest_iter"])},
         "wall_s_timed": t_wall,
         "source_digest": source_digest(),

@@ -74,16 +74,20 @@ __device__ __forceinline__ float sin_pi_series(float b)
 
 // cos(pi y): y = n + r, n = rint(y), r exact in [-1/2, 1/2]; |r| <= 1/4 uses the
 // cos series, otherwise sin(pi (1/2 - |r|)) (1/2 - |r| is exact); odd n negates.
+// |y| >= 2^24 (every such binary32 is an even integer) gives 1, NaN and
+// infinities the canonical NaN.  Every case is computed and selected, so the
+// function has no branch.
 __device__ __forceinline__ float cospi_f32(float y)
 {
-    if (!(__builtin_fabsf(y) < 0x1p24f)) return (y != y || __builtin_isinf(y)) ? __builtin_nanf("") : 1.0f;
     const float n = __builtin_rintf(y);
     const float a = __builtin_fabsf(y - n);
-    // both series, then a select: no divergent branch
     const float cc = cos_pi_series(a);
     const float ss = sin_pi_series(0.5f - a);
     const float c = (a <= 0.25f) ? cc : ss;
-    return ((int)n & 1) ? -c : c;
+    const float h = 0.5f * n; // exact; an integer iff n is even (|n| < 2^24)
+    const float r = (h != __builtin_rintf(h)) ? -c : c;
+    const float big = (y != y || __builtin_isinf(y)) ? __builtin_nanf("") : 1.0f;
+    return (__builtin_fabsf(y) < 0x1p24f) ? r : big;
 }
 
 // exp(x): k = rint(x log2 e), r = x - k ln2 in two fused steps (ln 2 split in
