@@ -106,6 +106,62 @@ def async_leg(pso, torch, spec, ws, stream):
                 gbest=float(best["gbest_fit"]))
 
 
+def small_leg(pso, torch, wl, stream):
+    """Small Sphere (D=2, N=1024, 1000 iterations): microseconds per
+    iteration, (a) as one pso_run (the whole run inside one workgroup) and
+    (b) as one pso_step launch per iteration; median of 5 solves each."""
+    spec = wl.small_sphere()
+    ws = torch.empty(pso.pso_workspace_bytes(spec.N, spec.D), dtype=torch.uint8, device="cuda")
+    sw = pso.Swarm(spec.fitness, spec.N, spec.D, spec.box, spec.w, spec.c1, spec.c2, spec.vmax, spec.seed,
+                   workspace=ws, stream=stream)
+
+    def run():
+        sw.reset()
+        sw.run(spec.T)
+
+    def steps():
+        sw.reset()
+        for _ in range(spec.T):
+            pso.pso_step(sw.h)
+    run()
+    steps()
+    us_run = sorted(timed_events(torch, stream, run) * 1e3 / spec.T for _ in range(5))
+    us_step = sorted(timed_events(torch, stream, steps) * 1e3 / spec.T for _ in range(5))
+    best = sw.best()
+    sw.close()
+    return dict(workload="Sphere D=2 N=1024, 1000 iterations", us_per_iteration_run=us_run[2],
+                us_per_iteration_step_launches=us_step[2], gbest=float(best["gbest_fit"]),
+                updates_per_s_run=spec.N * spec.D / (us_run[2] * 1e-6))
+
+
+def deep_leg(pso, torch, wl, stream):
+    """Deep workloads (D=128, N=65536, 2000 iterations): Rosenbrock, and
+    Ackley with a shift; updates/s and the step kernel's share of the HBM
+    roofline on algorithmic bytes.  Their 100 MB state fits the 256 MiB
+    Infinity Cache, so the fraction can exceed what HBM alone would allow."""
+    out = {}
+    for spec in (wl.deep_rosenbrock(0), wl.deep_ackley(0)):
+        ws = torch.empty(pso.pso_workspace_bytes(spec.N, spec.D), dtype=torch.uint8, device="cuda")
+        sw = pso.Swarm(spec.fitness, spec.N, spec.D, spec.box, spec.w, spec.c1, spec.c2, spec.vmax, spec.seed,
+                       shift=spec.shift, workspace=ws, stream=stream)
+
+        def solve():
+            sw.reset()
+            for _ in range(spec.T):
+                pso.pso_step(sw.h)
+        solve()
+        ms = timed_events(torch, stream, solve)
+        rho = sw.counters()["pbest_improvements"] / (spec.N * spec.T)
+        best = sw.best()
+        sw.close()
+        us = ms * 1e3 / spec.T
+        alg = spec.N * spec.D * (20.0 + 4.0 * rho) + spec.N * (4.0 + 4.0 * rho)
+        out[spec.fitness] = dict(value=spec.N * spec.D * spec.T / (ms / 1e3), unit="particle·dim updates/s",
+                                 us_per_iteration=us, hbm_frac=alg / (us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+                                 pbest_improvement_rate=rho, gbest=float(best["gbest_fit"]))
+    return out
+
+
 def batched_leg(pso, torch, wl, stream, subset=96):
     """4096 swarms (N log-uniform in [32, 8192], D in {2..64}, four fitness
     functions with shifts, 500 iterations) in one persistent launch; and a
@@ -185,13 +241,13 @@ def serving_leg(pso, wl, rates=(2000, 10000, 50000), count=2000, budget=32 << 30
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--variant", choices=["sync", "async"], default="sync")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=200)
-    ap.add_argument("--legs", default="main,async,batched,serving",
-                    help="comma list of legs beyond the main line: async, batched, serving")
+    ap.add_argument("--legs", default="main,async,small,deep,batched,serving",
+                    help="comma list of legs beyond the main line: async, small, deep, batched, serving")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="for rocprofv3 counter runs: init + 20 step launches, then a 256 MiB torch copy "
                          "(calibration kernel of known size); prints nothing else")
@@ -265,6 +321,8 @@ def main():
     sw.close()
 
     ms_per_step = total_ms / args.steps
+    solve_ms = sorted(a.elapsed_time(b) for a, b in evs)
+    trimmed = solve_ms[1:-1] if len(solve_ms) >= 3 else solve_ms
     updates = spec.N * spec.D * spec.T
     value = updates * args.steps / (total_ms / 1e3)
     launch_us = step_ms * 1e3 / (args.steps * spec.T)
@@ -300,12 +358,18 @@ def main():
                      "kernel": kernel, "avg_launch_us": launch_us, "alg_bytes_per_launch": alg_bytes,
                      "pbest_improvement_rate": rho, "valu_busy_frac": valu_busy},
         "gbest": {"value": float(best["gbest_fit"]), "iteration": int(best["gbest_iter"])},
+        "solve_ms": {"median": solve_ms[len(solve_ms) // 2], "trimmed_mean": sum(trimmed) / len(trimmed),
+                     "min": solve_ms[0], "max": solve_ms[-1]},
         "wall_s_timed": t_wall,
         "source_digest": source_digest(),
     }
     legs = set(args.legs.split(","))
     if "async" in legs:
         out["async"] = async_leg(pso, torch, spec, ws, stream)
+    if "small" in legs:
+        out["small"] = small_leg(pso, torch, wl, stream)
+    if "deep" in legs:
+        out["deep"] = deep_leg(pso, torch, wl, stream)
     if "batched" in legs:
         out["batched"] = batched_leg(pso, torch, wl, stream)
     if "serving" in legs:

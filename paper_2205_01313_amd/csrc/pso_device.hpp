@@ -146,6 +146,38 @@ struct Fitness {
         }
     }
 
+    // The same sum split in two: stage(z) computes a dimension's terms
+    // independently of the others (STAGE_WORDS floats), fold() adds staged
+    // terms in dimension order.  stage then fold gives exactly add(z, d).
+    static constexpr int STAGE_WORDS = FIT == F_ACKLEY ? 2 : 1;
+
+    __device__ __forceinline__ static void stage(float z, float *s0, float *s1)
+    {
+        if constexpr (FIT == F_RASTRIGIN) {
+            *s0 = z * z - 10.0f * cospi_f32(2.0f * z);
+        } else if constexpr (FIT == F_ACKLEY) {
+            *s0 = z * z;
+            *s1 = cospi_f32(2.0f * z);
+        } else if constexpr (FIT == F_CUBIC) {
+            const float z2 = z * z;
+            *s0 = ((z2 * z - 0.8f * z2) - 1000.0f * z) + 8000.0f;
+        } else { // Sphere, Rosenbrock: z itself
+            *s0 = z;
+        }
+    }
+
+    __device__ __forceinline__ void fold(float s0, float s1, int d)
+    {
+        if constexpr (FIT == F_RASTRIGIN || FIT == F_CUBIC) {
+            acc = acc + s0;
+        } else if constexpr (FIT == F_ACKLEY) {
+            acc = acc + s0;
+            aux = aux + s1;
+        } else {
+            add(s0, d);
+        }
+    }
+
     __device__ __forceinline__ float value(int D) const
     {
         if constexpr (FIT == F_RASTRIGIN) {

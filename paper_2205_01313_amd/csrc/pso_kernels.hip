@@ -25,6 +25,8 @@
 //   - Asynchronous variant (the lock-protected gbest of Sec. 3.2): a
 //     workgroup that lowers the gbest publishes its position at once under a
 //     seqlock, and workgroups that start later in the same iteration use it.
+#include <cstdlib>
+
 #include "pso_quad.hpp"
 
 // Launch-shape knobs of the step kernel (build-time; the defaults are the
@@ -403,6 +405,102 @@ __global__ void PSO_STEP_ATTR k_step(SwarmArgs a)
 }
 
 // ---------------------------------------------------------------------------
+// Split step, for swarms too small to fill the GPU at four particles per
+// lane (at N = 65 536 the plain step has a quarter of a wavefront per SIMD).
+// L lanes share a particle quad and each walks C consecutive dimensions of
+// it (C even, so a chunk holds whole Philox pairs).  Lane t of the
+// workgroup takes chunk t / Q of quad t % Q (Q = BLOCK / L quads per
+// workgroup): the lanes of one chunk are consecutive, so a wavefront moves
+// 256-byte row segments, and a 64-byte pbest group is four lanes of one
+// chunk, as in the plain step.  Each lane stages its dimensions' fitness
+// terms in LDS ([word][d][particle], one 16-byte store per quad); after a
+// barrier one lane per particle folds them in dimension order, so the
+// fitness is the same sequential sum as in the plain step, bit for bit.
+// ---------------------------------------------------------------------------
+template <int FIT, int POL>
+__global__ void PSO_STEP_ATTR k_step_split(SwarmArgs a, uint32_t L, uint32_t C)
+{
+    __shared__ unsigned long long wg_min;
+    __shared__ unsigned int wg_count;
+    __shared__ int flag;
+    extern __shared__ float s_dyn[]; // gbest position (D), shift (D), staged terms
+    Ctrl *c = a.ctrl;
+    if (c->stop) return;
+    constexpr int W = Fitness<FIT>::STAGE_WORDS;
+    constexpr bool KX = (POL & KEEP_X) != 0, KV = (POL & KEEP_V) != 0, KP = (POL & KEEP_P) != 0;
+    const int D = a.D;
+    const uint32_t Q = BLOCK / L, P = 4 * Q;
+    float *s_g = s_dyn, *s_shift = s_dyn + D, *s_t0 = s_dyn + 2 * D, *s_t1 = s_t0 + (size_t)D * P;
+    const uint32_t t = (uint32_t)(c->t + 1);
+    for (int d = threadIdx.x; d < D; d += BLOCK) {
+        s_g[d] = a.gpos[d];
+        s_shift[d] = a.shift[d];
+    }
+    if (threadIdx.x == 0) {
+        wg_min = NO_KEY;
+        wg_count = 0;
+    }
+    const unsigned long long thr = c->gkey_prev;
+    __syncthreads();
+    const uint32_t k = threadIdx.x / Q, qq = threadIdx.x % Q;
+    const uint32_t q = blockIdx.x * Q + qq, i0 = 4 * q;
+    const bool active = i0 < a.N;
+    const uint32_t pend = active ? *reinterpret_cast<const uint32_t *>(a.pend + i0) : 0u;
+    const bool line_dirty = group_dirty(pend);
+    if (active) {
+        const size_t Np = a.Np;
+        const int d_end = min(D, (int)((k + 1) * C));
+        for (int d = (int)(k * C); d < d_end; d += 2) {
+            U4 u[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) u[j] = philox4x32_10(a.k0, a.k1, (uint32_t)d >> 1, i0 + j, t, TAG_VEL);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                if (h == 1 && d + 1 >= d_end) break;
+                const size_t row = (size_t)(d + h) * Np;
+                const f4 xn = update_row<POL>(a, row, q, ld_state<KX>(a.x + row, q), ld_state<KV>(a.v + row, q),
+                                              ld_state<KP>(a.p + row, q), pend, line_dirty, u, h, s_g[d + h]);
+                const float sh = s_shift[d + h];
+                f4 w0, w1;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    float t0 = 0.0f, t1 = 0.0f;
+                    Fitness<FIT>::stage(xn[j] - sh, &t0, &t1);
+                    w0[j] = t0;
+                    w1[j] = t1;
+                }
+                *reinterpret_cast<f4 *>(s_t0 + (size_t)(d + h) * P + 4 * qq) = w0;
+                if constexpr (W == 2) *reinterpret_cast<f4 *>(s_t1 + (size_t)(d + h) * P + 4 * qq) = w1;
+            }
+        }
+    }
+    __syncthreads();
+    // Step 4 for particle s of the workgroup: fold, strict improvement
+    unsigned long long key = NO_KEY;
+    uint32_t n_imp = 0;
+    for (uint32_t sidx = threadIdx.x; sidx < P; sidx += BLOCK) {
+        const uint32_t i = blockIdx.x * P + sidx;
+        if (i >= a.N) break;
+        Fitness<FIT> fit;
+        for (int d = 0; d < D; ++d) fit.fold(s_t0[(size_t)d * P + sidx], W == 2 ? s_t1[(size_t)d * P + sidx] : 0.0f, d);
+        const float f = fit.value(D);
+        const bool imp = f < a.pf[i];
+        if (imp) {
+            a.pf[i] = f;
+            const unsigned long long kk = make_key(f, i);
+            key = kk < key ? kk : key;
+            ++n_imp;
+        }
+        a.pend[i] = imp ? 1 : 0;
+    }
+    count_improvements(c, n_imp, &wg_count);
+    const unsigned long long m = workgroup_min(key, thr, &wg_min);
+    flush_count(c, &wg_count);
+    publish_sync(c, m, thr);
+    if (arrive_last(c, &flag)) epilogue<VAR_SYNC>(a, t, false);
+}
+
+// ---------------------------------------------------------------------------
 // The paper's comparator (Sec. 2.2, Fig. 1): a two-kernel parallel
 // reduction.  Kernel 1 updates the particles and reduces every particle's
 // pbest key over its block with a shared-memory tree (log2 of the block
@@ -555,9 +653,51 @@ hipError_t launch_init(int fitness, const SwarmArgs &a, hipStream_t stream)
     return hipGetLastError();
 }
 
+// Split shape (lanes per quad L, dimensions per lane C) for the step of a
+// swarm, or false for the plain step.  The split step runs with C <= 8 (4
+// for Ackley's two staged words, keeping its LDS at 32 KiB) and L a power of
+// two <= 64, for D >= 16.  It is chosen for N <= 2^17 (at most 512 plain
+// wavefronts, half a wavefront per SIMD) and, with two staged words, N*D <=
+// 2^24: measured on gfx950 over N = 2^14..2^19, D = 16..256 for Rastrigin,
+// Rosenbrock and Ackley, it is 1.1-8.9x faster there and slower beyond.
+// PSO_STEP_SPLIT=0 in the environment disables it, =1 uses it whenever the
+// shape allows (tests of both paths).
+static bool split_shape(const SwarmArgs &a, int words, uint32_t *L, uint32_t *C)
+{
+    const char *env = getenv("PSO_STEP_SPLIT");
+    const int mode = env ? atoi(env) : -1;
+    if (mode == 0 || a.D < 16) return false;
+    if (mode < 0 && (a.N > (1u << 17) || (words == 2 && (uint64_t)a.N * (uint64_t)a.D > (1ull << 24)))) return false;
+    const uint32_t cmax = 8 / (uint32_t)words;
+    uint32_t l = 2;
+    while (l * cmax < (uint32_t)a.D) l *= 2;
+    if (l > 64) return false;
+    uint32_t c = ((uint32_t)a.D + l - 1) / l;
+    c += c & 1u;
+    *L = l;
+    *C = c;
+    return true;
+}
+
+template <int FIT, int POL>
+static void launch_split(const SwarmArgs &a, uint32_t L, uint32_t C, hipStream_t stream)
+{
+    constexpr int W = Fitness<FIT>::STAGE_WORDS;
+    const uint32_t Q = BLOCK / L, P = 4 * Q;
+    const uint64_t quads = ((uint64_t)a.N + 3) / 4;
+    const dim3 grid((unsigned)((quads + Q - 1) / Q));
+    const size_t lds = sizeof(float) * (2 * (size_t)a.D + (size_t)W * a.D * P);
+    hipLaunchKernelGGL((k_step_split<FIT, POL>), grid, dim3(BLOCK), lds, stream, a, L, C);
+}
+
 template <int FIT, int VAR, int POL>
 static void launch_step_fvp(const SwarmArgs &a, hipStream_t stream)
 {
+    uint32_t L = 0, C = 0;
+    if (VAR == VAR_SYNC && split_shape(a, Fitness<FIT>::STAGE_WORDS, &L, &C)) {
+        launch_split<FIT, POL>(a, L, C, stream);
+        return;
+    }
     const size_t lds = 2 * sizeof(float) * a.D;
     switch (PSO_STEP_EXACT_D ? a.D : 0) {
     case 32: hipLaunchKernelGGL((k_step<FIT, 32, VAR, POL>), grid_of(a), dim3(BLOCK), lds, stream, a); break;

@@ -112,12 +112,11 @@ __device__ __forceinline__ unsigned long long init_quad(const SwarmArgs &a, int 
 #define PSO_PREFETCH (FIT == F_ACKLEY)
 #endif
 // Eq. 1 and Eq. 2 for one dimension row of the four particles (x, v, p as
-// loaded; p replaced by x where the pbest position is pending), the fitness
-// term, and the stores of x, v and (for a dirty group) p.
-template <int FIT, int POL>
-__device__ __forceinline__ void update_row(const SwarmArgs &a, size_t row, uint32_t q, int d, f4 xs, f4 vs, f4 ps,
-                                           uint32_t pend, bool line_dirty, const U4 *u, int h, float g, float sh,
-                                           Fitness<FIT> *fit)
+// loaded; p replaced by x where the pbest position is pending) and the stores
+// of x, v and (for a dirty group) p.  Returns the new positions.
+template <int POL>
+__device__ __forceinline__ f4 update_row(const SwarmArgs &a, size_t row, uint32_t q, f4 xs, f4 vs, f4 ps,
+                                         uint32_t pend, bool line_dirty, const U4 *u, int h, float g)
 {
     const float w = a.w, c1 = a.c1, c2 = a.c2, vmax = a.vmax, lo = a.lo, hi = a.hi;
 #pragma unroll
@@ -133,11 +132,21 @@ __device__ __forceinline__ void update_row(const SwarmArgs &a, size_t row, uint3
         nv = clampf(nv, -vmax, vmax);
         xn[k] = clampf(xs[k] + nv, lo, hi);
         vn[k] = nv;
-        fit[k].add(xn[k] - sh, d);
     }
     st_state<(POL & KEEP_X) != 0>(a.x + row, q, xn);
     st_state<(POL & KEEP_V) != 0>(a.v + row, q, vn);
     if (line_dirty) st_state<(POL & KEEP_P) != 0>(a.p + row, q, ps);
+    return xn;
+}
+
+// The pending marks of quad q and whether its 64-byte group of PSO_PBEST_GROUP
+// lanes (consecutive in the wavefront) holds any: such a group rewrites p.
+// Must be called by all active lanes of the wavefront together (it ballots).
+__device__ __forceinline__ bool group_dirty(uint32_t pend)
+{
+    constexpr unsigned G = PSO_PBEST_GROUP;
+    const unsigned long long dirty = __ballot(pend != 0u);
+    return ((dirty >> ((threadIdx.x & 63) & ~(G - 1))) & ((1ull << G) - 1)) != 0;
 }
 
 template <int FIT, int DC, int UNROLL, int POL>
@@ -149,9 +158,7 @@ __device__ __forceinline__ unsigned long long iterate_quad(const SwarmArgs &a, i
     const size_t Np = a.Np;
     const f4 pf_old = *reinterpret_cast<const f4 *>(a.pf + i0);
     const uint32_t pend = *reinterpret_cast<const uint32_t *>(a.pend + i0);
-    const unsigned long long dirty = __ballot(pend != 0u);
-    constexpr unsigned G = PSO_PBEST_GROUP;
-    const bool line_dirty = ((dirty >> ((threadIdx.x & 63) & ~(G - 1))) & ((1ull << G) - 1)) != 0;
+    const bool line_dirty = group_dirty(pend);
     constexpr bool KX = (POL & KEEP_X) != 0, KV = (POL & KEEP_V) != 0, KP = (POL & KEEP_P) != 0;
     Fitness<FIT> fit[4];
     if constexpr (PSO_PREFETCH) {
@@ -191,8 +198,11 @@ __device__ __forceinline__ unsigned long long iterate_quad(const SwarmArgs &a, i
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 if (h == 1 && d + 1 >= D) break;
-                update_row<FIT, POL>(a, (size_t)(d + h) * Np, q, d + h, cx[h], cv[h], cp[h], pend, line_dirty, u, h,
-                                     s_g[d + h], s_shift[d + h], fit);
+                const f4 xn = update_row<POL>(a, (size_t)(d + h) * Np, q, cx[h], cv[h], cp[h], pend, line_dirty, u,
+                                              h, s_g[d + h]);
+                const float sh = s_shift[d + h];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) fit[k].add(xn[k] - sh, d + h);
             }
         }
     } else {
@@ -205,9 +215,11 @@ __device__ __forceinline__ unsigned long long iterate_quad(const SwarmArgs &a, i
             for (int h = 0; h < 2; ++h) {
                 if (h == 1 && d + 1 >= D) break;
                 const size_t row = (size_t)(d + h) * Np;
-                update_row<FIT, POL>(a, row, q, d + h, ld_state<KX>(a.x + row, q), ld_state<KV>(a.v + row, q),
-                                     ld_state<KP>(a.p + row, q), pend, line_dirty, u, h, s_g[d + h],
-                                     s_shift[d + h], fit);
+                const f4 xn = update_row<POL>(a, row, q, ld_state<KX>(a.x + row, q), ld_state<KV>(a.v + row, q),
+                                              ld_state<KP>(a.p + row, q), pend, line_dirty, u, h, s_g[d + h]);
+                const float sh = s_shift[d + h];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) fit[k].add(xn[k] - sh, d + h);
             }
         }
     }

@@ -73,6 +73,30 @@ def test_deep_d128_full_size_first_iterations(mk):
     run_both(spec, 4, nthreads=16)
 
 
+@pytest.mark.parametrize("split", ["0", "1"])
+@pytest.mark.parametrize("fit", wl.FITNESS_NAMES)
+@pytest.mark.parametrize("N,D", [(4099, 16), (2050, 17), (3001, 33), (1025, 130), (701, 200), (129, 512)])
+def test_split_and_plain_steps_equal_oracle(monkeypatch, split, fit, N, D):
+    """The step launched per iteration, forced onto the plain kernel (four
+    particles per lane) or the split kernel (lanes share a particle's
+    dimensions, terms folded in order from LDS): both bit-exact against the
+    oracle, over ragged particle counts, odd D, one to 64 chunks per quad."""
+    monkeypatch.setenv("PSO_STEP_SPLIT", split)
+    T = 30
+    spec = wl.SwarmSpec(fit, N, D, T, seed=N + 7 * D, shift_amplitude=2.0)
+    announce(f"split={split} {fit} N={N} D={D} T={T}")
+    o = oracle_swarm(spec, 8).run_f32(T)
+    with gpu_swarm(spec) as g:
+        g.step(T)
+        hist = g.history(0, T + 1)
+        st = g.state()
+        b = g.best()
+    bad = np.flatnonzero(hist != o["hist"])
+    assert bad.size == 0, f"gbest key differs first at iteration {bad[0]}"
+    assert b["gbest_iter"] == o["giter"] and st["t"] == T
+    assert_state_equal(st, o, N, D)
+
+
 def test_step_by_step_equals_run():
     spec = wl.SwarmSpec("ackley", 3000, 9, 25, seed=5, shift_amplitude=3.0)
     announce("step vs run")
