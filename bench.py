@@ -164,11 +164,15 @@ def deep_leg(pso, torch, wl, stream):
 
 def batched_leg(pso, torch, wl, stream, subset=96):
     """4096 swarms (N log-uniform in [32, 8192], D in {2..64}, four fitness
-    functions with shifts, 500 iterations) in one persistent launch; and a
+    functions with shifts, 500 iterations) in one persistent launch, its
+    shape (lanes, workgroups, part size) picked by the autotuner; and a
     spread subset run both as a batch and as a plain loop of pso_run calls
     (one swarm after another, allocation outside the timed loop)."""
     specs = wl.batch_specs()
     with pso.Batch(specs, stream=stream) as b:
+        t0 = time.perf_counter()
+        shape = b.autotune(probe_iters=8)
+        tune_s = time.perf_counter() - t0
         b.launch()
         torch.cuda.synchronize()
         ms = timed_events(torch, stream, b.launch)
@@ -189,6 +193,7 @@ def batched_leg(pso, torch, wl, stream, subset=96):
         sw.close()
     same = all(a["gbest_fit"] == c["gbest_fit"] and (a["gbest_pos"] == c["gbest_pos"]).all() for a, c in zip(rb, rp))
     return dict(swarms=len(specs), iterations=500, ms=ms, value=updates / (ms / 1e3), unit="particle·dim updates/s",
+                autotuned_shape=shape, autotune_s=tune_s,
                 subset=len(sub), subset_batched_ms=ms_sub, subset_plain_loop_ms=ms_plain,
                 batched_vs_plain_speedup=ms_plain / ms_sub, equal_results=bool(same))
 

@@ -180,6 +180,24 @@ class Batch:
     def launch(self):
         _check(lib().pso_batch_launch(self.h), "pso_batch_launch")
 
+    @property
+    def shape(self):
+        """Current tiles and schedule: dict(lanes, grid, part_work)."""
+        sh = _native.PsoBatchShape()
+        _check(lib().pso_batch_get_shape(self.h, ctypes.byref(sh)), "pso_batch_get_shape")
+        return dict(lanes=sh.lanes, grid=sh.grid, part_work=sh.part_work)
+
+    def set_shape(self, lanes, grid=0, part_work=1 << 17):
+        sh = _native.PsoBatchShape(int(lanes), int(grid), int(part_work))
+        _check(lib().pso_batch_set_shape(self.h, ctypes.byref(sh)), "pso_batch_set_shape")
+
+    def autotune(self, probe_iters=8):
+        """Times every candidate shape on probe_iters iterations and keeps
+        the fastest (pso_batch_autotune); returns it."""
+        sh = _native.PsoBatchShape()
+        _check(lib().pso_batch_autotune(self.h, int(probe_iters), ctypes.byref(sh)), "pso_batch_autotune")
+        return dict(lanes=sh.lanes, grid=sh.grid, part_work=sh.part_work)
+
     def results(self, positions=True):
         n = len(self.specs)
         res = (_native.PsoResult * n)()

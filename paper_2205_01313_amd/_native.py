@@ -26,6 +26,10 @@ class PsoDesc(ctypes.Structure):
                 ("f_star", ctypes.c_float)]
 
 
+class PsoBatchShape(ctypes.Structure):
+    _fields_ = [("lanes", ctypes.c_int32), ("grid", ctypes.c_int32), ("part_work", ctypes.c_int64)]
+
+
 class PsoResult(ctypes.Structure):
     """struct pso_result of include/pso.h."""
     _fields_ = [("gbest_value", ctypes.c_float), ("status", ctypes.c_int32), ("gbest_iter", ctypes.c_int64),
@@ -63,6 +67,9 @@ SIGNATURES = {
     "pso_batch_results": (c_int, [c_vp, P(PsoResult)]),
     "pso_batch_destroy": (c_int, [c_vp]),
     "pso_batch_run": (c_int, [P(PsoDesc), c_i64, P(PsoResult)]),
+    "pso_batch_get_shape": (c_int, [c_vp, P(PsoBatchShape)]),
+    "pso_batch_set_shape": (c_int, [c_vp, P(PsoBatchShape)]),
+    "pso_batch_autotune": (c_int, [c_vp, c_i64, P(PsoBatchShape)]),
     "pso_server_create": (c_int, [c_size, c_i64, P(c_vp)]),
     "pso_server_submit": (c_int, [c_vp, P(PsoDesc), P(c_u64)]),
     "pso_server_poll": (c_int, [c_vp, c_u64, P(PsoResult), P(ctypes.c_double)]),

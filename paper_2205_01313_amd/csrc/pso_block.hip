@@ -23,22 +23,15 @@
 #ifndef PSO_RUN_LANES
 #define PSO_RUN_LANES 256 // lanes of the workgroup running one small swarm (pso_run)
 #endif
-#ifndef PSO_BATCH_LANES
-#define PSO_BATCH_LANES 256 // lanes of a batched swarm's (part's) workgroup
-#endif
 #ifndef PSO_SWARM_POLICY
 // cache policy of the per-swarm workgroup kernels: a workgroup re-reads its
 // swarm's (small) state every iteration, so all of it stays cacheable
 #define PSO_SWARM_POLICY POL_ALL
 #endif
-#ifndef PSO_PART_WORK
-#define PSO_PART_WORK (1 << 17) // particle-dimension updates per part and iteration
-#endif
 
 namespace pso {
 
 constexpr int RUN_LANES = PSO_RUN_LANES;
-constexpr int BATCH_LANES = PSO_BATCH_LANES;
 
 // Per-swarm loop state, identical in every lane.
 struct SwarmLoop {
@@ -369,10 +362,11 @@ __device__ void batch_part(const BatchItem &it, uint32_t part, BatchResult *res,
     }
 }
 
-__global__ void __launch_bounds__(BATCH_LANES) k_batch(const BatchItem *items, const BatchEntry *entries,
-                                                       BatchResult *results, uint32_t count, unsigned int *next,
-                                                       long long chunk, long long iter_cap, BatchResult *out_state,
-                                                       float *out_pos, int pos_stride, unsigned int *err)
+template <int LANES>
+__global__ void __launch_bounds__(LANES) k_batch(const BatchItem *items, const BatchEntry *entries,
+                                                 BatchResult *results, uint32_t count, unsigned int *next,
+                                                 long long chunk, long long iter_cap, BatchResult *out_state,
+                                                 float *out_pos, int pos_stride, unsigned int *err)
 {
     __shared__ Scratch sc;
     __shared__ uint32_t s_idx;
@@ -389,27 +383,30 @@ __global__ void __launch_bounds__(BATCH_LANES) k_batch(const BatchItem *items, c
         float *s_g = s_dyn, *s_shift = s_dyn + it.a.D;
         BatchResult *res = &results[e.item];
         switch (it.fitness) {
-        case F_SPHERE: batch_part<F_SPHERE, BATCH_LANES>(it, e.part, res, chunk, iter_cap, s_g, s_shift, &sc, out_state, out_pos, e.out, pos_stride); break;
-        case F_RASTRIGIN: batch_part<F_RASTRIGIN, BATCH_LANES>(it, e.part, res, chunk, iter_cap, s_g, s_shift, &sc, out_state, out_pos, e.out, pos_stride); break;
-        case F_ROSENBROCK: batch_part<F_ROSENBROCK, BATCH_LANES>(it, e.part, res, chunk, iter_cap, s_g, s_shift, &sc, out_state, out_pos, e.out, pos_stride); break;
-        case F_ACKLEY: batch_part<F_ACKLEY, BATCH_LANES>(it, e.part, res, chunk, iter_cap, s_g, s_shift, &sc, out_state, out_pos, e.out, pos_stride); break;
-        default: batch_part<F_CUBIC, BATCH_LANES>(it, e.part, res, chunk, iter_cap, s_g, s_shift, &sc, out_state, out_pos, e.out, pos_stride); break;
+        case F_SPHERE: batch_part<F_SPHERE, LANES>(it, e.part, res, chunk, iter_cap, s_g, s_shift, &sc, out_state, out_pos, e.out, pos_stride); break;
+        case F_RASTRIGIN: batch_part<F_RASTRIGIN, LANES>(it, e.part, res, chunk, iter_cap, s_g, s_shift, &sc, out_state, out_pos, e.out, pos_stride); break;
+        case F_ROSENBROCK: batch_part<F_ROSENBROCK, LANES>(it, e.part, res, chunk, iter_cap, s_g, s_shift, &sc, out_state, out_pos, e.out, pos_stride); break;
+        case F_ACKLEY: batch_part<F_ACKLEY, LANES>(it, e.part, res, chunk, iter_cap, s_g, s_shift, &sc, out_state, out_pos, e.out, pos_stride); break;
+        default: batch_part<F_CUBIC, LANES>(it, e.part, res, chunk, iter_cap, s_g, s_shift, &sc, out_state, out_pos, e.out, pos_stride); break;
         }
         __syncthreads();
     }
     if (threadIdx.x == 0 && sc.err && err) atomicOr(err, 1u);
 }
 
-uint32_t parts_for(uint64_t N, int D, int grid_cap)
+uint32_t parts_for(uint64_t N, int D, int grid_cap, const BatchShape &shape)
 {
     const uint64_t work = N * (uint64_t)D;
-    uint64_t parts = (work + PSO_PART_WORK - 1) / PSO_PART_WORK;
-    const uint64_t by_quads = ((N + 3) / 4) / BATCH_LANES;
+    const uint64_t pw = (uint64_t)std::max<long long>(1, shape.part_work);
+    uint64_t parts = (work + pw - 1) / pw;
+    const uint64_t by_quads = ((N + 3) / 4) / (uint64_t)std::max(1, shape.lanes);
     parts = std::min<uint64_t>(parts, by_quads);
     parts = std::min<uint64_t>(parts, MAX_PARTS);
     parts = std::min<uint64_t>(parts, (uint64_t)std::max(1, grid_cap));
     return (uint32_t)std::max<uint64_t>(parts, 1);
 }
+
+bool batch_lanes_supported(int lanes) { return lanes == 64 || lanes == 128 || lanes == 256; }
 
 size_t gang_bytes(uint32_t parts, int D)
 {
@@ -460,21 +457,37 @@ hipError_t launch_batch_reset(const BatchItem *items, BatchResult *results, uint
 }
 
 hipError_t launch_batch(const BatchItem *items, const BatchEntry *entries, BatchResult *results, uint32_t count,
-                        unsigned int *next, int maxD, int grid, long long chunk, long long iter_cap,
+                        unsigned int *next, int maxD, int grid, int lanes, long long chunk, long long iter_cap,
                         hipStream_t stream, BatchResult *out_state, float *out_pos, unsigned int *err)
 {
+    if (!batch_lanes_supported(lanes)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_counter_reset, dim3(1), dim3(64), 0, stream, next);
     const size_t lds = 2 * sizeof(float) * maxD;
-    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(BATCH_LANES), lds, stream, items, entries, results, count, next,
-                       chunk, iter_cap, out_state, out_pos, maxD, err);
+    switch (lanes) {
+    case 64:
+        hipLaunchKernelGGL(k_batch<64>, dim3(grid), dim3(64), lds, stream, items, entries, results, count, next, chunk,
+                           iter_cap, out_state, out_pos, maxD, err);
+        break;
+    case 128:
+        hipLaunchKernelGGL(k_batch<128>, dim3(grid), dim3(128), lds, stream, items, entries, results, count, next,
+                           chunk, iter_cap, out_state, out_pos, maxD, err);
+        break;
+    default:
+        hipLaunchKernelGGL(k_batch<256>, dim3(grid), dim3(256), lds, stream, items, entries, results, count, next,
+                           chunk, iter_cap, out_state, out_pos, maxD, err);
+        break;
+    }
     return hipGetLastError();
 }
 
-hipError_t batch_capacity(int maxD, int *workgroups)
+hipError_t batch_capacity(int maxD, int lanes, int *workgroups)
 {
+    if (!batch_lanes_supported(lanes)) return hipErrorInvalidValue;
     const size_t lds = 2 * sizeof(float) * maxD;
     int per_cu = 0, dev = 0, cus = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch, BATCH_LANES, lds);
+    hipError_t e = lanes == 64    ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<64>, 64, lds)
+                   : lanes == 128 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<128>, 128, lds)
+                                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<256>, 256, lds);
     if (e != hipSuccess) return e;
     if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
     if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;

@@ -32,11 +32,24 @@ struct BatchItem {
     float *cand_pos;
 };
 
-// Parts for a batched swarm: about one part per PSO_PART_WORK (2^17)
+// Tiles and schedule of a batched launch: lanes per workgroup (64, 128 or
+// 256), co-resident workgroups, and particle-dimension updates per part and
+// iteration when a large swarm is split into parts.  Every shape computes the
+// same bits; only the time differs.
+struct BatchShape {
+    int lanes;
+    int grid;
+    long long part_work;
+};
+constexpr BatchShape DEFAULT_BATCH_SHAPE = {256, 0, 1 << 17}; // grid 0: three quarters of occupancy
+
+bool batch_lanes_supported(int lanes);
+
+// Parts for a batched swarm: about one part per shape.part_work
 // particle-dimension updates of an iteration, at least one particle quad per
 // lane of a part, at most MAX_PARTS and at most grid_cap (the workgroups of
 // the launches it joins).
-uint32_t parts_for(uint64_t N, int D, int grid_cap);
+uint32_t parts_for(uint64_t N, int D, int grid_cap, const BatchShape &shape);
 
 // Bytes of a swarm's gang region for `parts` parts (0 when parts == 1).
 size_t gang_bytes(uint32_t parts, int D);
@@ -78,10 +91,10 @@ hipError_t launch_batch_reset(const BatchItem *items, BatchResult *results, uint
 // Optionally writes each swarm's state to out_state[out] and its gbest
 // position to out_pos[out*maxD ..]; device errors set *err.
 hipError_t launch_batch(const BatchItem *items, const BatchEntry *entries, BatchResult *results, uint32_t count,
-                        unsigned int *next, int maxD, int grid, long long chunk, long long iter_cap,
+                        unsigned int *next, int maxD, int grid, int lanes, long long chunk, long long iter_cap,
                         hipStream_t stream, BatchResult *out_state, float *out_pos, unsigned int *err);
-// Workgroups of the batched kernel that are safely co-resident (three
-// quarters of the occupancy bound).
-hipError_t batch_capacity(int maxD, int *workgroups);
+// Workgroups of `lanes` lanes of the batched kernel that are safely
+// co-resident (three quarters of the occupancy bound).
+hipError_t batch_capacity(int maxD, int lanes, int *workgroups);
 
 } // namespace pso

@@ -8,6 +8,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -439,7 +441,8 @@ struct pso_batch {
     int64_t count = 0;
     int maxD = 1;
     int grid = 1;
-    void *slab = nullptr;            // every swarm's state
+    pso::BatchShape shape = pso::DEFAULT_BATCH_SHAPE;
+    void *slab = nullptr;            // every swarm's state and gang region
     pso::BatchItem *d_items = nullptr;
     pso::BatchEntry *d_entries = nullptr;
     uint32_t n_entries = 0;
@@ -447,6 +450,12 @@ struct pso_batch {
     unsigned int *d_next = nullptr;
     unsigned int *d_err = nullptr;
     std::vector<pso::BatchItem> items; // host copy (device pointers inside)
+    std::vector<char *> gang;          // each swarm's gang region (sized for max_parts)
+    std::vector<uint32_t> max_parts;
+    std::vector<uint64_t> N;
+    std::vector<int> D;
+    std::vector<long long> max_iter;
+    uint64_t signature = 0;
     hipStream_t stream = nullptr;
     bool owns_stream = false;
 };
@@ -467,6 +476,75 @@ void batch_free(pso_batch *b)
     delete b;
 }
 
+// The shapes the autotuner tries: lanes per workgroup x part size x
+// co-resident workgroups (all of them, or half: a smaller working set).
+std::vector<pso::BatchShape> tuner_candidates()
+{
+    std::vector<pso::BatchShape> c;
+    for (int lanes : {64, 128, 256})
+        for (long long pw : {1LL << 15, 1LL << 17})
+            for (int half : {0, 1}) c.push_back(pso::BatchShape{lanes, half ? -2 : 0, pw});
+    return c;
+}
+
+// Workgroups of a shape: grid > 0 as given (at most the capacity), 0 the
+// capacity, -k the capacity / k.
+hipError_t shape_grid(int maxD, const pso::BatchShape &sh, int *grid)
+{
+    int cap = 0;
+    hipError_t e = pso::batch_capacity(maxD, sh.lanes, &cap);
+    if (e != hipSuccess) return e;
+    *grid = sh.grid > 0 ? std::min(sh.grid, cap) : sh.grid < 0 ? std::max(1, cap / -sh.grid) : cap;
+    return hipSuccess;
+}
+
+// Process-wide choices of the autotuner, by batch signature and device.
+std::mutex g_tuned_mu;
+std::map<std::pair<uint64_t, int>, pso::BatchShape> g_tuned;
+
+// Applies a shape: parts per swarm, gang bindings, the work queue (largest
+// per-part work first, a swarm's parts consecutive) and the grid.
+int batch_configure(pso_batch *b, const pso::BatchShape &sh)
+{
+    if (!pso::batch_lanes_supported(sh.lanes) || sh.part_work < 1)
+        return fail(PSO_EINVAL, "batch shape: lanes must be 64, 128 or 256 and part_work >= 1");
+    int grid = 0;
+    HIP_TRY(shape_grid(b->maxD, sh, &grid));
+    std::vector<uint32_t> parts(b->count);
+    uint64_t n_entries = 0;
+    for (int64_t i = 0; i < b->count; ++i) {
+        parts[i] = std::min(pso::parts_for(b->N[i], b->D[i], grid, sh), b->max_parts[i]);
+        pso::bind_gang(&b->items[i], b->gang[i], parts[i]);
+        n_entries += parts[i];
+    }
+    std::vector<uint32_t> order(b->count);
+    for (int64_t i = 0; i < b->count; ++i) order[i] = (uint32_t)i;
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) {
+        const double wx = double(b->N[x]) * b->D[x] * double(b->max_iter[x] + 1) / parts[x];
+        const double wy = double(b->N[y]) * b->D[y] * double(b->max_iter[y] + 1) / parts[y];
+        return wx > wy;
+    });
+    std::vector<pso::BatchEntry> entries;
+    entries.reserve(n_entries);
+    for (uint32_t i : order)
+        for (uint32_t p = 0; p < parts[i]; ++p) entries.push_back(pso::BatchEntry{i, p, i, 0u});
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    HIP_TRY(hipMemcpy(b->d_items, b->items.data(), sizeof(pso::BatchItem) * b->count, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(b->d_entries, entries.data(), sizeof(pso::BatchEntry) * n_entries, hipMemcpyHostToDevice));
+    b->n_entries = (uint32_t)n_entries;
+    b->grid = (int)std::min<uint64_t>(n_entries, (uint64_t)grid);
+    b->shape = sh;
+    return PSO_OK;
+}
+
+int batch_launch_iters(pso_batch *b, long long iter_cap, bool reset)
+{
+    if (reset) HIP_TRY(pso::launch_batch_reset(b->d_items, b->d_results, (uint32_t)b->count, b->d_next, b->stream));
+    HIP_TRY(pso::launch_batch(b->d_items, b->d_entries, b->d_results, b->n_entries, b->d_next, b->maxD, b->grid,
+                              b->shape.lanes, (long long)1 << 62, iter_cap, b->stream, nullptr, nullptr, b->d_err));
+    return PSO_OK;
+}
+
 } // namespace
 
 extern "C" {
@@ -477,35 +555,47 @@ int pso_batch_create(const pso_desc *descs, int64_t count, void *hip_stream, pso
     *out = nullptr;
     if (count < 1 || count > (int64_t(1) << 31)) return fail(PSO_EINVAL, "count=%lld out of range", (long long)count);
     if (!descs) return fail(PSO_EINVAL, "descs is NULL");
-    int capacity = 0;
-    {
-        int maxD0 = 1;
-        for (int64_t i = 0; i < count; ++i) maxD0 = std::max(maxD0, (int)descs[i].D);
-        if (pso::batch_capacity(maxD0, &capacity) != hipSuccess || capacity < 1)
-            return fail(PSO_EDEVICE, "device query failed");
-    }
-    std::vector<pso::Layout> lay(count);
-    std::vector<size_t> off(count);
-    std::vector<uint32_t> parts(count);
-    size_t total = 0;
     int maxD = 1;
-    uint64_t n_entries = 0;
+    for (int64_t i = 0; i < count; ++i) {
+        int rc = pso_internal_check_desc(&descs[i]);
+        if (rc) return fail(rc, "descriptor %lld: %s", (long long)i, std::string(g_err).c_str());
+        maxD = std::max(maxD, (int)descs[i].D);
+    }
+    // gang regions are sized for the most parts any tuner shape gives
+    const std::vector<pso::BatchShape> cands = tuner_candidates();
+    std::vector<int> cand_grid(cands.size());
+    for (size_t c = 0; c < cands.size(); ++c)
+        if (shape_grid(maxD, cands[c], &cand_grid[c]) != hipSuccess) return fail(PSO_EDEVICE, "device query failed");
+    int def_grid = 0;
+    if (shape_grid(maxD, pso::DEFAULT_BATCH_SHAPE, &def_grid) != hipSuccess)
+        return fail(PSO_EDEVICE, "device query failed");
+    std::vector<pso::Layout> lay(count);
+    std::vector<size_t> off(count), goff(count);
+    std::vector<uint32_t> maxp(count);
+    size_t total = 0;
+    uint64_t max_entries = 0, sig = 1469598103934665603ull;
+    auto mix = [&](uint64_t v) { sig = (sig ^ v) * 1099511628211ull; };
+    mix((uint64_t)count);
     for (int64_t i = 0; i < count; ++i) {
         const pso_desc &d = descs[i];
-        int rc = pso_internal_check_desc(&d);
-        if (rc) return fail(rc, "descriptor %lld: %s", (long long)i, std::string(g_err).c_str());
         lay[i] = pso::layout_of((uint64_t)d.N, d.D, false);
-        parts[i] = pso::parts_for((uint64_t)d.N, d.D, capacity);
+        uint32_t mp = pso::parts_for((uint64_t)d.N, d.D, def_grid, pso::DEFAULT_BATCH_SHAPE);
+        for (size_t c = 0; c < cands.size(); ++c)
+            mp = std::max(mp, pso::parts_for((uint64_t)d.N, d.D, cand_grid[c], cands[c]));
+        maxp[i] = mp;
         off[i] = total;
-        total += lay[i].total + pso::gang_bytes(parts[i], d.D);
-        maxD = std::max(maxD, (int)d.D);
-        n_entries += parts[i];
+        goff[i] = total + lay[i].total;
+        total += lay[i].total + pso::gang_bytes(mp, d.D);
+        max_entries += mp;
+        mix((uint64_t)d.N);
+        mix((uint64_t)d.D);
+        mix((uint64_t)d.max_iter);
     }
     pso_batch *b = new (std::nothrow) pso_batch();
     if (!b) return fail(PSO_ENOMEM, "host allocation failed");
     b->count = count;
     b->maxD = maxD;
-    b->n_entries = (uint32_t)n_entries;
+    b->signature = sig;
     if (hip_stream) {
         b->stream = static_cast<hipStream_t>(hip_stream);
     } else {
@@ -516,7 +606,7 @@ int pso_batch_create(const pso_desc *descs, int64_t count, void *hip_stream, pso
         b->owns_stream = true;
     }
     if (hipMalloc(&b->slab, total) != hipSuccess || hipMalloc(&b->d_items, sizeof(pso::BatchItem) * count) != hipSuccess ||
-        hipMalloc(&b->d_entries, sizeof(pso::BatchEntry) * n_entries) != hipSuccess ||
+        hipMalloc(&b->d_entries, sizeof(pso::BatchEntry) * max_entries) != hipSuccess ||
         hipMalloc(&b->d_results, sizeof(pso::BatchResult) * count) != hipSuccess ||
         hipMalloc(&b->d_next, sizeof(unsigned int)) != hipSuccess ||
         hipMalloc(&b->d_err, sizeof(unsigned int)) != hipSuccess) {
@@ -524,6 +614,11 @@ int pso_batch_create(const pso_desc *descs, int64_t count, void *hip_stream, pso
         return fail(PSO_ENOMEM, "hipMalloc of %zu bytes for the batch failed", total);
     }
     b->items.resize(count);
+    b->gang.resize(count);
+    b->max_parts = maxp;
+    b->N.resize(count);
+    b->D.resize(count);
+    b->max_iter.resize(count);
     std::vector<float> shifts;
     for (int64_t i = 0; i < count; ++i) {
         const pso_desc &d = descs[i];
@@ -542,7 +637,10 @@ int pso_batch_create(const pso_desc *descs, int64_t count, void *hip_stream, pso
         it.max_iter = d.max_iter;
         it.tol = d.tol;
         it.fstar = d.f_star;
-        pso::bind_gang(&it, base + lay[i].total, parts[i]);
+        b->gang[i] = static_cast<char *>(b->slab) + goff[i];
+        b->N[i] = (uint64_t)d.N;
+        b->D[i] = d.D;
+        b->max_iter[i] = d.max_iter;
         shifts.assign(d.D, 0.0f);
         if (d.shift) std::memcpy(shifts.data(), d.shift, sizeof(float) * d.D);
         if (hipMemcpy(const_cast<float *>(it.a.shift), shifts.data(), sizeof(float) * d.D, hipMemcpyHostToDevice) !=
@@ -551,27 +649,24 @@ int pso_batch_create(const pso_desc *descs, int64_t count, void *hip_stream, pso
             return fail(PSO_EDEVICE, "shift upload failed");
         }
     }
-    // largest work first (the persistent workgroups drain the queue in this
-    // order); a swarm's parts are consecutive
-    std::vector<uint32_t> order(count);
-    for (int64_t i = 0; i < count; ++i) order[i] = (uint32_t)i;
-    std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) {
-        const double wx = double(descs[x].N) * descs[x].D * double(descs[x].max_iter + 1) / parts[x];
-        const double wy = double(descs[y].N) * descs[y].D * double(descs[y].max_iter + 1) / parts[y];
-        return wx > wy;
-    });
-    std::vector<pso::BatchEntry> entries;
-    entries.reserve(n_entries);
-    for (uint32_t i : order)
-        for (uint32_t p = 0; p < parts[i]; ++p) entries.push_back(pso::BatchEntry{i, p, i, 0u});
-    if (hipMemcpy(b->d_items, b->items.data(), sizeof(pso::BatchItem) * count, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(b->d_entries, entries.data(), sizeof(pso::BatchEntry) * n_entries, hipMemcpyHostToDevice) !=
-            hipSuccess ||
-        hipMemset(b->d_err, 0, sizeof(unsigned int)) != hipSuccess) {
+    if (hipMemset(b->d_err, 0, sizeof(unsigned int)) != hipSuccess) {
         batch_free(b);
         return fail(PSO_EDEVICE, "descriptor upload failed");
     }
-    b->grid = (int)std::min<int64_t>(n_entries, capacity);
+    // a shape the autotuner chose for the same workload on this device
+    pso::BatchShape sh = pso::DEFAULT_BATCH_SHAPE;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    {
+        std::lock_guard<std::mutex> g(g_tuned_mu);
+        auto f = g_tuned.find({sig, dev});
+        if (f != g_tuned.end()) sh = f->second;
+    }
+    int rc = batch_configure(b, sh);
+    if (rc) {
+        batch_free(b);
+        return rc;
+    }
     *out = b;
     return PSO_OK;
 }
@@ -579,9 +674,73 @@ int pso_batch_create(const pso_desc *descs, int64_t count, void *hip_stream, pso
 int pso_batch_launch(pso_batch *b)
 {
     if (!b) return fail(PSO_EINVAL, "batch is NULL");
-    HIP_TRY(pso::launch_batch_reset(b->d_items, b->d_results, (uint32_t)b->count, b->d_next, b->stream));
-    HIP_TRY(pso::launch_batch(b->d_items, b->d_entries, b->d_results, b->n_entries, b->d_next, b->maxD, b->grid,
-                              (long long)1 << 62, (long long)1 << 62, b->stream, nullptr, nullptr, b->d_err));
+    return batch_launch_iters(b, (long long)1 << 62, true);
+}
+
+int pso_batch_get_shape(pso_batch *b, pso_batch_shape *shape)
+{
+    if (!b || !shape) return fail(PSO_EINVAL, "batch or shape is NULL");
+    shape->lanes = b->shape.lanes;
+    shape->grid = b->grid;
+    shape->part_work = b->shape.part_work;
+    return PSO_OK;
+}
+
+int pso_batch_set_shape(pso_batch *b, const pso_batch_shape *shape)
+{
+    if (!b || !shape) return fail(PSO_EINVAL, "batch or shape is NULL");
+    if (shape->grid < 0) return fail(PSO_EINVAL, "grid must be >= 0 (0: the co-resident capacity)");
+    return batch_configure(b, pso::BatchShape{shape->lanes, shape->grid, shape->part_work});
+}
+
+int pso_batch_autotune(pso_batch *b, int64_t probe_iters, pso_batch_shape *chosen)
+{
+    if (!b) return fail(PSO_EINVAL, "batch is NULL");
+    if (probe_iters < 1) return fail(PSO_EINVAL, "probe_iters must be >= 1");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(PSO_EDEVICE, "hipEventCreate failed");
+    }
+    float best_ms = -1.0f;
+    pso::BatchShape best = b->shape;
+    int rc = PSO_OK;
+    for (const pso::BatchShape &sh : tuner_candidates()) {
+        // Step 1 and one iteration untimed, then probe_iters timed iterations
+        if ((rc = batch_configure(b, sh)) || (rc = batch_launch_iters(b, 1, true))) break;
+        if (hipEventRecord(e0, b->stream) != hipSuccess) {
+            rc = fail(PSO_EDEVICE, "hipEventRecord failed");
+            break;
+        }
+        if ((rc = batch_launch_iters(b, probe_iters, false))) break;
+        float ms = 0.0f;
+        if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            rc = fail(PSO_EDEVICE, "timing a probe launch failed");
+            break;
+        }
+        unsigned int err = 0;
+        if (hipMemcpy(&err, b->d_err, sizeof err, hipMemcpyDeviceToHost) != hipSuccess || err) {
+            rc = fail(PSO_EDEVICE, "a probe launch reported a device error");
+            break;
+        }
+        if (best_ms < 0.0f || ms < best_ms) {
+            best_ms = ms;
+            best = sh;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    if ((rc = batch_configure(b, best))) return rc;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    {
+        std::lock_guard<std::mutex> g(g_tuned_mu);
+        g_tuned[{b->signature, dev}] = best;
+    }
+    if (chosen) return pso_batch_get_shape(b, chosen);
     return PSO_OK;
 }
 

@@ -230,8 +230,9 @@ bool launch_ready(pso_server *s, int k)
         if (hipMalloc(&s->d_opos[k], sizeof(float) * s->cap_pos[k]) != hipSuccess) return false;
     }
     const int grid = std::min<int>((int)ne, s->grid_cap);
-    if (pso::launch_batch(s->d_items, s->d_entries[k], s->d_state, ne, s->d_next[k], maxD, grid, s->chunk, ITER_CAP,
-                          st, s->d_out[k], s->d_opos[k], s->d_err) != hipSuccess)
+    if (pso::launch_batch(s->d_items, s->d_entries[k], s->d_state, ne, s->d_next[k], maxD, grid,
+                          pso::DEFAULT_BATCH_SHAPE.lanes, s->chunk, ITER_CAP, st, s->d_out[k], s->d_opos[k],
+                          s->d_err) != hipSuccess)
         return false;
     if (hipMemcpyAsync(s->h_out[k], s->d_out[k], sizeof(pso::BatchResult) * n, hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipMemcpyAsync(s->h_err[k], s->d_err, sizeof(unsigned int), hipMemcpyDeviceToHost, st) != hipSuccess)
@@ -377,7 +378,7 @@ int pso_server_create(size_t mem_budget, int64_t chunk_updates, pso_server **out
     // two launches may run at once: each gets half of the co-resident
     // workgroups, so every launch's grid stays fully resident
     int capacity = 0;
-    if (pso::batch_capacity(MAX_SERVER_D, &capacity) != hipSuccess || capacity < 2) {
+    if (pso::batch_capacity(MAX_SERVER_D, pso::DEFAULT_BATCH_SHAPE.lanes, &capacity) != hipSuccess || capacity < 2) {
         server_free(s);
         return pso_internal_fail(PSO_EDEVICE, "device query failed");
     }
@@ -431,7 +432,7 @@ int pso_server_submit(pso_server *s, const pso_desc *d, uint64_t *ticket)
     if (d->shift) std::memcpy(r->shift.data(), d->shift, sizeof(float) * d->D);
     r->d.shift = nullptr;
     r->t_submit = Clock::now();
-    r->parts = pso::parts_for((uint64_t)d->N, d->D, s->grid_cap);
+    r->parts = pso::parts_for((uint64_t)d->N, d->D, s->grid_cap, pso::DEFAULT_BATCH_SHAPE);
     const size_t bytes = pso::layout_of((uint64_t)d->N, d->D, false).total + pso::gang_bytes(r->parts, d->D);
     std::lock_guard<std::mutex> g(s->mu);
     r->ticket = s->next_ticket++;

@@ -63,3 +63,7 @@ def test_pure_host_entry_points_without_gpu(libpath):
     assert lib.pso_destroy(None) == _native.PSO_EINVAL
     assert lib.pso_step(None) == _native.PSO_EINVAL
     assert lib.pso_run(None, 1, 0.0, 0.0, None, None, None, None) == _native.PSO_EINVAL
+    shape = _native.PsoBatchShape(256, 0, 1 << 17)
+    assert lib.pso_batch_get_shape(None, ctypes.byref(shape)) == _native.PSO_EINVAL
+    assert lib.pso_batch_set_shape(None, ctypes.byref(shape)) == _native.PSO_EINVAL
+    assert lib.pso_batch_autotune(None, 8, None) == _native.PSO_EINVAL

@@ -98,3 +98,37 @@ def test_large_swarms_split_into_parts_equal_alone_and_oracle():
         assert r["gbest_iter"] == a["gbest_iter"] and np.array_equal(r["gbest_pos"], a["gbest_pos"]), sp
         o = oracle_swarm(sp, nthreads=16).run_f32(sp.T, tol=getattr(sp, "tol", 0.0), f_star=getattr(sp, "f_star", 0.0))
         assert r["gbest_fit"] == o["gbest_fit"] and np.array_equal(r["gbest_pos"], o["gpos"]), sp
+
+
+def test_every_shape_and_the_autotuner_give_the_same_results():
+    """Lanes 64/128/256, part sizes that split the large swarms, a small and the
+    full grid: bit-identical results; the autotuner picks one of them and
+    leaves the batch ready to run."""
+    specs = mixed_specs(40, 21)
+    specs += [wl.SwarmSpec("rastrigin", 6000, 48, 30, seed=900, shift_amplitude=1.0),
+              wl.SwarmSpec("ackley", 9000, 20, 30, seed=901, shift_amplitude=1.0)]
+    announce(f"batch shapes, {len(specs)} swarms")
+    ref = None
+    with pso.Batch(specs) as b:
+        for lanes in (64, 128, 256):
+            for grid, pw in ((0, 1 << 17), (7, 1 << 14)):
+                b.set_shape(lanes, grid, pw)
+                sh = b.shape
+                assert sh["lanes"] == lanes and sh["part_work"] == pw and sh["grid"] >= 1
+                b.launch()
+                res = b.results()
+                if ref is None:
+                    ref = res
+                for r, q in zip(res, ref):
+                    assert r["gbest_fit"] == q["gbest_fit"] and r["gbest_iter"] == q["gbest_iter"]
+                    assert np.array_equal(r["gbest_pos"], q["gbest_pos"])
+        chosen = b.autotune(probe_iters=3)
+        assert chosen["lanes"] in (64, 128, 256) and chosen["grid"] >= 1
+        b.launch()
+        res = b.results()
+    for r, q in zip(res, ref):
+        assert r["gbest_fit"] == q["gbest_fit"] and np.array_equal(r["gbest_pos"], q["gbest_pos"])
+    # the oracle agrees on two of them
+    for k in (0, len(specs) - 1):
+        o = oracle_swarm(specs[k], 8).run_f32(specs[k].T)
+        assert ref[k]["gbest_fit"] == o["gbest_fit"] and ref[k]["gbest_iter"] == o["giter"]
