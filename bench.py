@@ -156,10 +156,48 @@ def deep_leg(pso, torch, wl, stream):
         sw.close()
         us = ms * 1e3 / spec.T
         alg = spec.N * spec.D * (20.0 + 4.0 * rho) + spec.N * (4.0 + 4.0 * rho)
+        # the same run in binary64 (the binary64 path computes the reference
+        # definition in double): the binary32 result's error against it
+        with pso.Swarm64(spec.fitness, spec.N, spec.D, spec.box, spec.w, spec.c1, spec.c2, spec.vmax, spec.seed,
+                         shift=spec.shift) as g64:
+            t0 = time.perf_counter()
+            r64 = g64.run(spec.T)
+            s64 = time.perf_counter() - t0
+        f32 = float(best["gbest_fit"])
+        f64 = float(r64["gbest_fit"])
         out[spec.fitness] = dict(value=spec.N * spec.D * spec.T / (ms / 1e3), unit="particle·dim updates/s",
                                  us_per_iteration=us, hbm_frac=alg / (us * 1e-6) / 1e9 / HBM_PEAK_GBS,
-                                 pbest_improvement_rate=rho, gbest=float(best["gbest_fit"]))
+                                 pbest_improvement_rate=rho, gbest=f32, gbest_f64=f64,
+                                 abs_err_vs_f64=abs(f32 - f64), rel_err_vs_f64=abs(f32 - f64) / max(abs(f64), 1e-300),
+                                 f64_run_s=s64)
     return out
+
+
+# The paper's experiments (Sec. 5, Tables 2-4): binary64, Cubic (Eq. 3, on
+# [-100, 100]), w = 1, c1 = c2 = 2; vmax is not stated there (0.1 of the box
+# here).  The paper's own Queue Lock (1D) and Queue (120D) seconds on its
+# GPU are printed beside each row as context.
+PAPER_ROWS = [  # N, D, iterations, paper seconds
+    (32, 1, 100000, 0.216), (256, 1, 100000, 0.222), (1024, 1, 100000, 0.227), (2048, 1, 100000, 0.230),
+    (4096, 1, 100000, 0.265), (16384, 1, 100000, 0.417), (65536, 1, 100000, 1.026), (131072, 1, 100000, 2.759),
+    (128, 120, 5000, 0.487), (1024, 120, 2000, 0.225), (8192, 120, 1000, 0.191), (32768, 120, 1000, 0.570),
+    (131072, 120, 800, 1.744)]
+
+
+def paper_leg(pso):
+    """Replay of the paper's shapes through the binary64 path (pso64_run),
+    seconds per run (after one untimed warm-up run of 200 iterations)."""
+    rows = []
+    for N, D, T, paper_s in PAPER_ROWS:
+        with pso.Swarm64("cubic", N, D, (-100.0, 100.0), 1.0, 2.0, 2.0, 20.0, 0) as g:
+            g.run(min(T, 200))
+            g.reset()
+            t0 = time.perf_counter()
+            g.run(T)
+            s = time.perf_counter() - t0
+        rows.append(dict(N=N, D=D, iterations=T, s=s, us_per_iteration=s / T * 1e6,
+                         updates_per_s=N * D * T / s, paper_s_context=paper_s))
+    return dict(precision="f64", fitness="cubic", rows=rows)
 
 
 def batched_leg(pso, torch, wl, stream, subset=96):
@@ -251,8 +289,8 @@ def main():
     ap.add_argument("--variant", choices=["sync", "async"], default="sync")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=200)
-    ap.add_argument("--legs", default="main,async,small,deep,batched,serving",
-                    help="comma list of legs beyond the main line: async, small, deep, batched, serving")
+    ap.add_argument("--legs", default="main,async,small,deep,paper,batched,serving",
+                    help="comma list of legs beyond the main line: async, small, deep, paper, batched, serving")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="for rocprofv3 counter runs: init + 20 step launches, then a 256 MiB torch copy "
                          "(calibration kernel of known size); prints nothing else")
@@ -375,6 +413,8 @@ def main():
         out["small"] = small_leg(pso, torch, wl, stream)
     if "deep" in legs:
         out["deep"] = deep_leg(pso, torch, wl, stream)
+    if "paper" in legs:
+        out["paper"] = paper_leg(pso)
     if "batched" in legs:
         out["batched"] = batched_leg(pso, torch, wl, stream)
     if "serving" in legs:

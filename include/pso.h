@@ -155,6 +155,49 @@ int pso_sync(pso_swarm *s);
 int pso_destroy(pso_swarm *s);
 
 /* ------------------------------------------------------------------------ */
+/* Binary64 path: the same method computed in double -- the paper's own     */
+/* precision (Sec. 5) -- from the same binary32 parameters, shift and 24-bit */
+/* Philox uniforms as the binary32 swarm.  Velocity and position updates    */
+/* follow Eq. 1 and Eq. 2 with their clamps (Alg. 1 Step 2), the gbest is   */
+/* synchronised once per iteration (lowest index among equal fitness), and  */
+/* the fitness functions are those of pso_create, Cubic (Eq. 3) negated.    */
+/* State is double, rows of N particles per dimension ((d, i) at d*N + i).  */
+/* ------------------------------------------------------------------------ */
+typedef struct pso_swarm64 pso_swarm64;
+
+/* As pso_create (same arguments and checks), then Step 1 in double.  The
+ * swarm owns its device memory and a stream until pso64_destroy. */
+int pso64_create(int fitness_id, int64_t N, int32_t D, const float bounds[2], float w, float c1, float c2,
+                 float vmax, uint64_t seed, pso_swarm64 **out);
+
+/* Shift s (D floats, host, copied; finite): f(x) = F(x - s); re-runs Step 1. */
+int pso64_set_shift(pso_swarm64 *s, const float *shift);
+
+/* Re-runs Step 1 (iteration count back to 0). */
+int pso64_reset(pso_swarm64 *s);
+
+/* Enqueues one iteration (asynchronous). */
+int pso64_step(pso_swarm64 *s);
+
+/* Up to max_iter more iterations, stopping once |gbest - f_star| < tol
+ * (tol <= 0: off; tested before the first and after every iteration);
+ * blocks.  Outputs (each may be NULL, host): gbest fitness, position (D
+ * doubles), iteration of the last gbest change, iterations run.  A swarm
+ * with N*D <= 4096 runs in one workgroup (one launch); larger ones launch
+ * one grid step per iteration. */
+int pso64_run(pso_swarm64 *s, int64_t max_iter, double tol, double f_star, double *gbest_value, double *gbest_pos,
+              int64_t *gbest_iter, int64_t *iters_done);
+
+/* Copies the state to host buffers (each may be NULL): x, v, p (D*N doubles
+ * each, (d, i) at d*N + i), pbest fitness (N doubles), gbest particle index,
+ * iterations completed.  Synchronises. */
+int pso64_get_state(pso_swarm64 *s, double *x, double *v, double *p, double *pf, int64_t *gbest_index,
+                    int64_t *t);
+
+/* Frees the swarm.  NULL -> EINVAL. */
+int pso64_destroy(pso_swarm64 *s);
+
+/* ------------------------------------------------------------------------ */
 /* Batches: many independent swarms (uneven N, D and fitness) run by one     */
 /* persistent launch; each swarm computes exactly what pso_create + pso_run  */
 /* (synchronous variant) computes for it alone.                              */

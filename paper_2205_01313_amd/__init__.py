@@ -167,6 +167,64 @@ def _descs(specs):
     return arr, keep
 
 
+class Swarm64:
+    """A swarm computed in binary64 (pso64_*): same parameters as Swarm."""
+
+    def __init__(self, fitness, N, D, bounds, w, c1, c2, vmax, seed, shift=None):
+        self.N, self.D = int(N), int(D)
+        self.h = ctypes.c_void_p()
+        b = (ctypes.c_float * 2)(*bounds)
+        _check(lib().pso64_create(fitness_id(fitness), self.N, self.D, b, float(w), float(c1), float(c2), float(vmax),
+                                  int(seed), ctypes.byref(self.h)), "pso64_create")
+        if shift is not None:
+            sh = np.ascontiguousarray(shift, np.float32)
+            _check(lib().pso64_set_shift(self.h, sh.ctypes.data_as(ctypes.POINTER(ctypes.c_float))),
+                   "pso64_set_shift")
+
+    def step(self, n=1):
+        for _ in range(n):
+            _check(lib().pso64_step(self.h), "pso64_step")
+
+    def reset(self):
+        _check(lib().pso64_reset(self.h), "pso64_reset")
+
+    def run(self, max_iter, tol=0.0, f_star=0.0):
+        val, git, done = ctypes.c_double(), ctypes.c_int64(), ctypes.c_int64()
+        pos = np.empty(self.D)
+        dp = ctypes.POINTER(ctypes.c_double)
+        _check(lib().pso64_run(self.h, int(max_iter), float(tol), float(f_star), ctypes.byref(val),
+                               pos.ctypes.data_as(dp), ctypes.byref(git), ctypes.byref(done)), "pso64_run")
+        return dict(gbest_fit=val.value, gbest_pos=pos, gbest_iter=git.value, iters=done.value)
+
+    def state(self):
+        N, D = self.N, self.D
+        out = dict(x=np.empty(D * N), v=np.empty(D * N), p=np.empty(D * N), pf=np.empty(N))
+        gi, t = ctypes.c_int64(), ctypes.c_int64()
+        dp = ctypes.POINTER(ctypes.c_double)
+        _check(lib().pso64_get_state(self.h, out["x"].ctypes.data_as(dp), out["v"].ctypes.data_as(dp),
+                                     out["p"].ctypes.data_as(dp), out["pf"].ctypes.data_as(dp), ctypes.byref(gi),
+                                     ctypes.byref(t)), "pso64_get_state")
+        out["gbest_idx"], out["t"] = gi.value, t.value
+        return out
+
+    def close(self):
+        if getattr(self, "h", None):
+            _check(lib().pso64_destroy(self.h), "pso64_destroy")
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Batch:
     """Many independent swarms run by one persistent launch (pso_batch_*)."""
 

@@ -15,6 +15,7 @@ PSO_SYNC, PSO_ASYNC, PSO_REDUCE, PSO_REDUCE_UNROLLED = 0, 1, 2, 3
 c_int, c_i32, c_i64, c_u64, c_f, c_size, c_vp = (ctypes.c_int, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
                                                    ctypes.c_float, ctypes.c_size_t, ctypes.c_void_p)
 P = ctypes.POINTER
+c_f64 = ctypes.c_double
 
 
 class PsoDesc(ctypes.Structure):
@@ -67,6 +68,13 @@ SIGNATURES = {
     "pso_batch_results": (c_int, [c_vp, P(PsoResult)]),
     "pso_batch_destroy": (c_int, [c_vp]),
     "pso_batch_run": (c_int, [P(PsoDesc), c_i64, P(PsoResult)]),
+    "pso64_create": (c_int, [c_int, c_i64, c_i32, P(c_f), c_f, c_f, c_f, c_f, c_u64, P(c_vp)]),
+    "pso64_set_shift": (c_int, [c_vp, P(c_f)]),
+    "pso64_reset": (c_int, [c_vp]),
+    "pso64_step": (c_int, [c_vp]),
+    "pso64_run": (c_int, [c_vp, c_i64, c_f64, c_f64, P(c_f64), P(c_f64), P(c_i64), P(c_i64)]),
+    "pso64_get_state": (c_int, [c_vp, P(c_f64), P(c_f64), P(c_f64), P(c_f64), P(c_i64), P(c_i64)]),
+    "pso64_destroy": (c_int, [c_vp]),
     "pso_batch_get_shape": (c_int, [c_vp, P(PsoBatchShape)]),
     "pso_batch_set_shape": (c_int, [c_vp, P(PsoBatchShape)]),
     "pso_batch_autotune": (c_int, [c_vp, c_i64, P(PsoBatchShape)]),

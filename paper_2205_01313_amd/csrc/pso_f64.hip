@@ -1,0 +1,636 @@
+// pso_f64.hip -- the binary64 path (the paper computes in double, Sec. 5).
+//
+// The method is the same as the binary32 kernels' (Alg. 1 Steps 1-5, Eq. 1
+// and Eq. 2 with their clamps, synchronous gbest), evaluated in double from
+// the binary32 parameters and the same 24-bit Philox uniforms.  Its fitness
+// expressions are written operation for operation as the binary64 reference
+// definition; Rastrigin and Ackley call the device's double cos and exp.
+//
+// Layout: x, v, p as double rows of Np particles (element (d, i) at
+// d*Np + i), one particle per lane (8-byte accesses, 512 bytes per
+// wavefront).  A new pbest position is written at once.  A 64-bit fitness
+// and a particle index no longer fit one 64-bit word, so the gbest is not an
+// atomic minimum: every workgroup writes its (order bits, index) minimum of
+// the improved particles into its own slot, and the last workgroup to arrive
+// reduces the slots (lowest index among equal fitness).
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "pso.h"
+#include "pso_device.hpp"
+#include "pso_f64.hpp"
+
+int pso_internal_fail(int code, const char *fmt, ...);
+int pso_internal_check_desc(const pso_desc *d);
+
+namespace pso {
+
+constexpr int BLOCK64 = 256;
+constexpr uint32_t NO_IDX = 0xFFFFFFFFu;
+
+static inline size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
+
+Layout64 layout64_of(uint64_t N, int D)
+{
+    Layout64 L;
+    L.Np = (N + 63) / 64 * 64;
+    L.nblocks = (uint32_t)((N + BLOCK64 - 1) / BLOCK64);
+    size_t o = 0;
+    L.ctrl = o;     o += al256(sizeof(Ctrl64));
+    L.gpos = o;     o += al256(sizeof(double) * D);
+    L.shift = o;    o += al256(sizeof(double) * D);
+    L.slot_ord = o; o += al256(sizeof(unsigned long long) * L.nblocks);
+    L.slot_idx = o; o += al256(sizeof(uint32_t) * L.nblocks);
+    L.pf = o;       o += al256(sizeof(double) * L.Np);
+    L.x = o;        o += al256(sizeof(double) * L.Np * (size_t)D);
+    L.v = o;        o += al256(sizeof(double) * L.Np * (size_t)D);
+    L.p = o;        o += al256(sizeof(double) * L.Np * (size_t)D);
+    L.total = o;
+    return L;
+}
+
+Swarm64Args bind64(void *base, const Layout64 &L, uint64_t N, int D)
+{
+    char *b = static_cast<char *>(base);
+    Swarm64Args a{};
+    a.ctrl = reinterpret_cast<Ctrl64 *>(b + L.ctrl);
+    a.gpos = reinterpret_cast<double *>(b + L.gpos);
+    a.shift = reinterpret_cast<const double *>(b + L.shift);
+    a.slot_ord = reinterpret_cast<unsigned long long *>(b + L.slot_ord);
+    a.slot_idx = reinterpret_cast<uint32_t *>(b + L.slot_idx);
+    a.pf = reinterpret_cast<double *>(b + L.pf);
+    a.x = reinterpret_cast<double *>(b + L.x);
+    a.v = reinterpret_cast<double *>(b + L.v);
+    a.p = reinterpret_cast<double *>(b + L.p);
+    a.N = (uint32_t)N;
+    a.Np = (uint32_t)L.Np;
+    a.D = D;
+    return a;
+}
+
+// Order bits of a binary64: unsigned order = numeric order, -0 = +0, NaN last.
+__device__ __forceinline__ unsigned long long ord64(double f)
+{
+    if (f != f) return ~0ull;
+    if (f == 0.0) f = 0.0;
+    const unsigned long long b = (unsigned long long)__double_as_longlong(f);
+    return (b & 0x8000000000000000ull) ? ~b : (b | 0x8000000000000000ull);
+}
+
+__device__ __forceinline__ double clampd(double v, double lo, double hi)
+{
+    v = (v < lo) ? lo : v;
+    return (v > hi) ? hi : v;
+}
+
+// cos(pi y) after the exact reduction y = n + r.
+__device__ __forceinline__ double cospi64(double y)
+{
+    const double n = rint(y);
+    const double r = y - n;
+    const double c = cos(M_PI * r);
+    return fmod(n, 2.0) != 0.0 ? -c : c;
+}
+
+// The fitness functions in binary64, accumulated in dimension order.
+template <int FIT>
+struct Fitness64 {
+    double acc = 0.0, aux = 0.0;
+
+    __device__ __forceinline__ void add(double z, int d)
+    {
+        if constexpr (FIT == F_SPHERE) {
+            acc = acc + z * z;
+        } else if constexpr (FIT == F_RASTRIGIN) {
+            acc = acc + (z * z - 10.0 * cospi64(2.0 * z));
+        } else if constexpr (FIT == F_ROSENBROCK) {
+            if (d > 0) {
+                const double a = z - aux * aux;
+                const double b = 1.0 - aux;
+                acc = acc + (100.0 * a * a + b * b);
+            }
+            aux = z;
+        } else if constexpr (FIT == F_ACKLEY) {
+            acc = acc + z * z;
+            aux = aux + cospi64(2.0 * z);
+        } else {
+            acc = acc + (z * z * z - 0.8 * z * z - 1000.0 * z + 8000.0);
+        }
+    }
+
+    __device__ __forceinline__ double value(int D) const
+    {
+        if constexpr (FIT == F_RASTRIGIN) {
+            return 10.0 * D + acc;
+        } else if constexpr (FIT == F_ACKLEY) {
+            return 20.0 - 20.0 * exp(-0.2 * sqrt(acc / D)) + M_E - exp(aux / D);
+        } else if constexpr (FIT == F_CUBIC) {
+            return -acc; // Eq. 3, negated: the paper maximises it
+        } else {
+            return acc;
+        }
+    }
+};
+
+__device__ __forceinline__ void lexmin(unsigned long long &k, uint32_t &i, unsigned long long k2, uint32_t i2)
+{
+    if (k2 < k || (k2 == k && i2 < i)) {
+        k = k2;
+        i = i2;
+    }
+}
+
+// Workgroup lexicographic minimum of (k, i) over LANES lanes; the result is
+// in every lane.  Ends with a barrier.
+template <int LANES = BLOCK64>
+__device__ void wg_lexmin(unsigned long long &k, uint32_t &i, unsigned long long *s_k, uint32_t *s_i)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const unsigned long long k2 = __shfl_xor(k, off, 64);
+        const uint32_t i2 = __shfl_xor(i, off, 64);
+        lexmin(k, i, k2, i2);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        s_k[w] = k;
+        s_i[w] = i;
+    }
+    __syncthreads();
+    k = s_k[0];
+    i = s_i[0];
+    for (int u = 1; u < LANES / 64; ++u) lexmin(k, i, s_k[u], s_i[u]);
+    __syncthreads();
+}
+
+// Step 1 for particle i: x ~ U[lo, hi), v ~ U[-vmax, vmax), p = x; returns F(x).
+template <int FIT>
+__device__ double init_particle64(const Swarm64Args &a, uint32_t i, const double *s_shift)
+{
+    const size_t Np = a.Np;
+    const int D = a.D;
+    Fitness64<FIT> fit;
+    for (int d = 0; d < D; d += 2) {
+        const U4 u = philox4x32_10(a.k0, a.k1, (uint32_t)d >> 1, i, 0u, TAG_INIT);
+        for (int h = 0; h < 2 && d + h < D; ++h) {
+            const double u0 = (double)unit_float(h ? u.c : u.a), u1 = (double)unit_float(h ? u.d : u.b);
+            const double x = clampd(a.lo + (a.hi - a.lo) * u0, a.lo, a.hi);
+            const double v = clampd(-a.vmax + 2.0 * a.vmax * u1, -a.vmax, a.vmax);
+            const size_t e = (size_t)(d + h) * Np + i;
+            a.x[e] = x;
+            a.v[e] = v;
+            a.p[e] = x;
+            fit.add(x - s_shift[d + h], d + h);
+        }
+    }
+    return fit.value(D);
+}
+
+// Steps 2-4 of iteration t for particle i; returns the order bits of its new
+// pbest fitness if it improved (strictly), else ~0.
+template <int FIT>
+__device__ unsigned long long iterate_particle64(const Swarm64Args &a, uint32_t i, uint32_t t, const double *s_g,
+                                                 const double *s_shift)
+{
+    const size_t Np = a.Np;
+    const int D = a.D;
+    Fitness64<FIT> fit;
+    for (int d = 0; d < D; d += 2) {
+        const U4 u = philox4x32_10(a.k0, a.k1, (uint32_t)d >> 1, i, t, TAG_VEL);
+        for (int h = 0; h < 2 && d + h < D; ++h) {
+            const double r1 = (double)unit_float(h ? u.c : u.a), r2 = (double)unit_float(h ? u.d : u.b);
+            const size_t e = (size_t)(d + h) * Np + i;
+            const double x = a.x[e], v = a.v[e], p = a.p[e];
+            // Eq. 1 left to right, clamp to [-vmax, vmax]; Eq. 2, clamp to [lo, hi]
+            double vn = a.w * v + a.c1 * r1 * (p - x) + a.c2 * r2 * (s_g[d + h] - x);
+            vn = clampd(vn, -a.vmax, a.vmax);
+            const double xn = clampd(x + vn, a.lo, a.hi);
+            a.x[e] = xn;
+            a.v[e] = vn;
+            fit.add(xn - s_shift[d + h], d + h);
+        }
+    }
+    const double f = fit.value(D);
+    if (!(f < a.pf[i])) return ~0ull; // strict; NaN never improves
+    a.pf[i] = f;
+    for (int d = 0; d < D; ++d) a.p[(size_t)d * Np + i] = a.x[(size_t)d * Np + i];
+    return ord64(f);
+}
+
+// The last workgroup of a grid launch: reduce the slots; a better gbest than
+// the control block's (or any, at Step 1) becomes the gbest of iteration t.
+__device__ void finish64(const Swarm64Args &a, uint32_t t, bool first, unsigned long long *s_k, uint32_t *s_i)
+{
+    Ctrl64 *c = a.ctrl;
+    unsigned long long k = ~0ull;
+    uint32_t i = NO_IDX;
+    for (uint32_t b = threadIdx.x; b < gridDim.x; b += BLOCK64) lexmin(k, i, a.slot_ord[b], a.slot_idx[b]);
+    wg_lexmin(k, i, s_k, s_i);
+    const bool changed = i != NO_IDX;
+    if (changed)
+        for (int d = threadIdx.x; d < a.D; d += BLOCK64) a.gpos[d] = a.x[(size_t)d * a.Np + i];
+    if (threadIdx.x == 0) {
+        if (changed) {
+            c->gord = k;
+            c->gidx = i;
+            c->giter = first ? 0 : (long long)t;
+        }
+        c->t = first ? 0 : (long long)t;
+        c->arrive = 0;
+        if (first) c->stop = 0;
+        const double gf = a.pf[c->gidx];
+        if (c->tol > 0.0 && fabs(gf - c->fstar) < c->tol) c->stop = 1;
+    }
+}
+
+// Posts the workgroup minimum and arrives; true in every lane of the last
+// workgroup (after its acquire).
+__device__ bool post_and_arrive64(const Swarm64Args &a, unsigned long long k, uint32_t i, int *last)
+{
+    if (threadIdx.x == 0) {
+        a.slot_ord[blockIdx.x] = k;
+        a.slot_idx[blockIdx.x] = i;
+        __threadfence(); // release: the slot and this workgroup's x (ordered by the barrier)
+        const unsigned int ticket = atomicAdd(&a.ctrl->arrive, 1u);
+        const int l = ticket == gridDim.x - 1;
+        if (l) __threadfence(); // acquire every slot and position
+        *last = l;
+    }
+    __syncthreads();
+    return *last != 0;
+}
+
+template <int FIT>
+__global__ void __launch_bounds__(BLOCK64) k_init64(Swarm64Args a)
+{
+    __shared__ unsigned long long s_k[BLOCK64 / 64];
+    __shared__ uint32_t s_i[BLOCK64 / 64];
+    __shared__ int last;
+    extern __shared__ double s_shift64[];
+    for (int d = threadIdx.x; d < a.D; d += BLOCK64) s_shift64[d] = a.shift[d];
+    __syncthreads();
+    const uint32_t i = blockIdx.x * BLOCK64 + threadIdx.x;
+    unsigned long long k = ~0ull;
+    uint32_t ki = NO_IDX;
+    if (i < a.N) {
+        const double f = init_particle64<FIT>(a, i, s_shift64);
+        a.pf[i] = f;
+        k = ord64(f);
+        ki = i;
+    }
+    wg_lexmin(k, ki, s_k, s_i);
+    if (post_and_arrive64(a, k, ki, &last)) finish64(a, 0u, true, s_k, s_i);
+}
+
+template <int FIT>
+__global__ void __launch_bounds__(BLOCK64) k_step64(Swarm64Args a)
+{
+    __shared__ unsigned long long s_k[BLOCK64 / 64];
+    __shared__ uint32_t s_i[BLOCK64 / 64];
+    __shared__ int last;
+    extern __shared__ double s_dyn64[]; // gbest position (D), shift (D)
+    Ctrl64 *c = a.ctrl;
+    if (c->stop) return;
+    const int D = a.D;
+    double *s_g = s_dyn64, *s_shift = s_dyn64 + D;
+    for (int d = threadIdx.x; d < D; d += BLOCK64) {
+        s_g[d] = a.gpos[d];
+        s_shift[d] = a.shift[d];
+    }
+    const uint32_t t = (uint32_t)(c->t + 1);
+    const unsigned long long pk = c->gord;
+    const uint32_t pi = c->gidx;
+    __syncthreads();
+    const uint32_t i = blockIdx.x * BLOCK64 + threadIdx.x;
+    unsigned long long k = ~0ull;
+    uint32_t ki = NO_IDX;
+    if (i < a.N) {
+        const unsigned long long o = iterate_particle64<FIT>(a, i, t, s_g, s_shift);
+        if (o < pk || (o == pk && i < pi)) {
+            k = o;
+            ki = i;
+        }
+    }
+    wg_lexmin(k, ki, s_k, s_i);
+    if (post_and_arrive64(a, k, ki, &last)) finish64(a, t, false, s_k, s_i);
+}
+
+// Up to T iterations of a small swarm in one workgroup of LANES lanes
+// (gbest position in LDS).
+template <int FIT, int LANES>
+__global__ void __launch_bounds__(LANES) k_block_run64(Swarm64Args a, long long T)
+{
+    __shared__ unsigned long long s_k[LANES / 64];
+    __shared__ uint32_t s_i[LANES / 64];
+    extern __shared__ double s_dyn64[];
+    Ctrl64 *c = a.ctrl;
+    const int D = a.D;
+    double *s_g = s_dyn64, *s_shift = s_dyn64 + D;
+    for (int d = threadIdx.x; d < D; d += LANES) {
+        s_g[d] = a.gpos[d];
+        s_shift[d] = a.shift[d];
+    }
+    unsigned long long gk = c->gord;
+    uint32_t gi = c->gidx;
+    long long giter = c->giter, t = c->t;
+    bool stop = c->stop != 0;
+    const double tol = c->tol, fstar = c->fstar;
+    __syncthreads();
+    for (long long it = 0; it < T && !stop; ++it) {
+        const uint32_t t1 = (uint32_t)(t + 1);
+        unsigned long long k = ~0ull;
+        uint32_t ki = NO_IDX;
+        for (uint32_t i = threadIdx.x; i < a.N; i += LANES) {
+            const unsigned long long o = iterate_particle64<FIT>(a, i, t1, s_g, s_shift);
+            if (o < gk || (o == gk && i < gi)) lexmin(k, ki, o, i);
+        }
+        wg_lexmin<LANES>(k, ki, s_k, s_i); // every lane's x and pf stores precede it
+        if (ki != NO_IDX) {
+            gk = k;
+            gi = ki;
+            giter = t1;
+            for (int d = threadIdx.x; d < D; d += LANES) s_g[d] = a.x[(size_t)d * a.Np + gi];
+        }
+        t = t1;
+        stop = tol > 0.0 && fabs(a.pf[gi] - fstar) < tol;
+        __syncthreads();
+    }
+    for (int d = threadIdx.x; d < D; d += LANES) a.gpos[d] = s_g[d];
+    if (threadIdx.x == 0) {
+        c->gord = gk;
+        c->gidx = gi;
+        c->giter = giter;
+        c->t = t;
+        c->stop = stop ? 1u : 0u;
+    }
+}
+
+__global__ void k_arm64(Swarm64Args a, double tol, double fstar)
+{
+    if (threadIdx.x != 0) return;
+    Ctrl64 *c = a.ctrl;
+    c->tol = tol;
+    c->fstar = fstar;
+    c->stop = (tol > 0.0 && fabs(a.pf[c->gidx] - fstar) < tol) ? 1u : 0u;
+}
+
+static inline dim3 grid64(const Swarm64Args &a) { return dim3((a.N + BLOCK64 - 1) / BLOCK64); }
+
+#define PSO64_DISPATCH(FN, ...)                                                                                    \
+    switch (fitness) {                                                                                             \
+    case F_SPHERE: FN<F_SPHERE>(__VA_ARGS__); break;                                                               \
+    case F_RASTRIGIN: FN<F_RASTRIGIN>(__VA_ARGS__); break;                                                         \
+    case F_ROSENBROCK: FN<F_ROSENBROCK>(__VA_ARGS__); break;                                                       \
+    case F_ACKLEY: FN<F_ACKLEY>(__VA_ARGS__); break;                                                               \
+    case F_CUBIC: FN<F_CUBIC>(__VA_ARGS__); break;                                                                 \
+    default: return hipErrorInvalidValue;                                                                          \
+    }
+
+template <int FIT>
+static void init64_f(const Swarm64Args &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_init64<FIT>, grid64(a), dim3(BLOCK64), sizeof(double) * a.D, s, a);
+}
+template <int FIT>
+static void step64_f(const Swarm64Args &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_step64<FIT>, grid64(a), dim3(BLOCK64), 2 * sizeof(double) * a.D, s, a);
+}
+// One workgroup: 256 lanes for up to 512 particle-dimensions, else 1024.
+template <int FIT>
+static void block64_f(const Swarm64Args &a, long long T, hipStream_t s)
+{
+    const size_t lds = 2 * sizeof(double) * a.D;
+    if ((uint64_t)a.N * (uint64_t)a.D <= 512)
+        hipLaunchKernelGGL((k_block_run64<FIT, 256>), dim3(1), dim3(256), lds, s, a, T);
+    else
+        hipLaunchKernelGGL((k_block_run64<FIT, 1024>), dim3(1), dim3(1024), lds, s, a, T);
+}
+
+hipError_t launch64_init(int fitness, const Swarm64Args &a, hipStream_t stream)
+{
+    PSO64_DISPATCH(init64_f, a, stream);
+    return hipGetLastError();
+}
+
+hipError_t launch64_step(int fitness, const Swarm64Args &a, hipStream_t stream)
+{
+    PSO64_DISPATCH(step64_f, a, stream);
+    return hipGetLastError();
+}
+
+hipError_t launch64_block_run(int fitness, const Swarm64Args &a, long long T, hipStream_t stream)
+{
+    PSO64_DISPATCH(block64_f, a, T, stream);
+    return hipGetLastError();
+}
+
+hipError_t launch64_arm(const Swarm64Args &a, double tol, double fstar, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_arm64, dim3(1), dim3(64), 0, stream, a, tol, fstar);
+    return hipGetLastError();
+}
+
+} // namespace pso
+
+// ---------------------------------------------------------------------------
+// C ABI of the binary64 path (include/pso.h).
+// ---------------------------------------------------------------------------
+struct pso_swarm64 {
+    int fitness = 0;
+    uint64_t N = 0;
+    int D = 0;
+    pso::Layout64 L{};
+    pso::Swarm64Args a{};
+    void *mem = nullptr;
+    hipStream_t stream = nullptr;
+};
+
+namespace {
+
+#define HIP64_TRY(expr)                                                                                            \
+    do {                                                                                                           \
+        hipError_t e_ = (expr);                                                                                    \
+        if (e_ != hipSuccess) return pso_internal_fail(PSO_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));      \
+    } while (0)
+
+// Swarms up to this many particle-dimensions run in one workgroup (one
+// launch for the whole run); PSO64_BLOCK_MAX_ND in the environment
+// overrides it (tests of both paths).
+// (Measured, Cubic 1D: one workgroup 1.5 / 3.1 / 5.9 / 9.7 us per iteration
+// at N = 256 / 1024 / 4096 / 8192 against 5.3 / 5.6 / 6.3 / 6.7 us for a
+// grid launch per iteration.)
+constexpr uint64_t BLOCK64_MAX_ND = 4096;
+
+uint64_t block64_max_nd()
+{
+    const char *env = getenv("PSO64_BLOCK_MAX_ND");
+    return env ? (uint64_t)strtoull(env, nullptr, 10) : BLOCK64_MAX_ND;
+}
+
+void free64(pso_swarm64 *s)
+{
+    if (!s) return;
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    (void)hipFree(s->mem);
+    if (s->stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+}
+
+int reinit64(pso_swarm64 *s)
+{
+    HIP64_TRY(hipMemsetAsync(s->a.ctrl, 0, sizeof(pso::Ctrl64), s->stream));
+    HIP64_TRY(pso::launch64_init(s->fitness, s->a, s->stream));
+    return PSO_OK;
+}
+
+// Pitched (Np) device rows -> dense (N) host rows.
+int rows_to_host(const pso_swarm64 *s, const double *src, double *dst)
+{
+    if (!dst) return PSO_OK;
+    HIP64_TRY(hipMemcpy2D(dst, sizeof(double) * s->N, src, sizeof(double) * s->L.Np, sizeof(double) * s->N, s->D,
+                          hipMemcpyDeviceToHost));
+    return PSO_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+int pso64_create(int fitness_id, int64_t N, int32_t D, const float bounds[2], float w, float c1, float c2,
+                 float vmax, uint64_t seed, pso_swarm64 **out)
+{
+    if (!out) return pso_internal_fail(PSO_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!bounds) return pso_internal_fail(PSO_EINVAL, "bounds is NULL");
+    pso_desc d{};
+    d.fitness_id = fitness_id;
+    d.D = D;
+    d.N = N;
+    d.bounds[0] = bounds[0];
+    d.bounds[1] = bounds[1];
+    d.w = w;
+    d.c1 = c1;
+    d.c2 = c2;
+    d.vmax = vmax;
+    d.seed = seed;
+    int rc = pso_internal_check_desc(&d);
+    if (rc) return rc;
+    pso_swarm64 *s = new (std::nothrow) pso_swarm64();
+    if (!s) return pso_internal_fail(PSO_ENOMEM, "host allocation failed");
+    s->fitness = fitness_id;
+    s->N = (uint64_t)N;
+    s->D = D;
+    s->L = pso::layout64_of(s->N, D);
+    if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
+        s->stream = nullptr;
+        free64(s);
+        return pso_internal_fail(PSO_EDEVICE, "hipStreamCreate failed");
+    }
+    if (hipMalloc(&s->mem, s->L.total) != hipSuccess) {
+        s->mem = nullptr;
+        free64(s);
+        return pso_internal_fail(PSO_ENOMEM, "hipMalloc of %zu bytes failed", s->L.total);
+    }
+    s->a = pso::bind64(s->mem, s->L, s->N, D);
+    s->a.lo = bounds[0];
+    s->a.hi = bounds[1];
+    s->a.w = w;
+    s->a.c1 = c1;
+    s->a.c2 = c2;
+    s->a.vmax = vmax;
+    s->a.k0 = (uint32_t)seed;
+    s->a.k1 = (uint32_t)(seed >> 32);
+    if (hipMemset(const_cast<double *>(s->a.shift), 0, sizeof(double) * D) != hipSuccess ||
+        (rc = reinit64(s)) != PSO_OK) {
+        free64(s);
+        return rc ? rc : pso_internal_fail(PSO_EDEVICE, "shift initialisation failed");
+    }
+    *out = s;
+    return PSO_OK;
+}
+
+int pso64_set_shift(pso_swarm64 *s, const float *shift)
+{
+    if (!s || !shift) return pso_internal_fail(PSO_EINVAL, "swarm or shift is NULL");
+    std::vector<double> sh(s->D);
+    for (int d = 0; d < s->D; ++d) {
+        if (!std::isfinite(shift[d])) return pso_internal_fail(PSO_EINVAL, "shift[%d] is not finite", d);
+        sh[d] = shift[d];
+    }
+    HIP64_TRY(hipStreamSynchronize(s->stream));
+    HIP64_TRY(hipMemcpy(const_cast<double *>(s->a.shift), sh.data(), sizeof(double) * s->D, hipMemcpyHostToDevice));
+    return reinit64(s);
+}
+
+int pso64_reset(pso_swarm64 *s)
+{
+    if (!s) return pso_internal_fail(PSO_EINVAL, "swarm is NULL");
+    return reinit64(s);
+}
+
+int pso64_step(pso_swarm64 *s)
+{
+    if (!s) return pso_internal_fail(PSO_EINVAL, "swarm is NULL");
+    HIP64_TRY(pso::launch64_step(s->fitness, s->a, s->stream));
+    return PSO_OK;
+}
+
+int pso64_run(pso_swarm64 *s, int64_t max_iter, double tol, double f_star, double *gbest_value, double *gbest_pos,
+              int64_t *gbest_iter, int64_t *iters_done)
+{
+    if (!s) return pso_internal_fail(PSO_EINVAL, "swarm is NULL");
+    if (max_iter < 0) return pso_internal_fail(PSO_EINVAL, "max_iter < 0");
+    pso::Ctrl64 c{};
+    HIP64_TRY(hipStreamSynchronize(s->stream));
+    HIP64_TRY(hipMemcpy(&c, s->a.ctrl, sizeof c, hipMemcpyDeviceToHost));
+    const long long t0 = c.t;
+    HIP64_TRY(pso::launch64_arm(s->a, tol, f_star, s->stream));
+    if (s->N * (uint64_t)s->D <= block64_max_nd()) {
+        HIP64_TRY(pso::launch64_block_run(s->fitness, s->a, max_iter, s->stream));
+    } else {
+        // chunks of launches; every launch returns at once after the stop rule holds
+        for (int64_t done = 0; done < max_iter;) {
+            const int64_t n = std::min<int64_t>(256, max_iter - done);
+            for (int64_t k = 0; k < n; ++k) HIP64_TRY(pso::launch64_step(s->fitness, s->a, s->stream));
+            done += n;
+            HIP64_TRY(hipStreamSynchronize(s->stream));
+            HIP64_TRY(hipMemcpy(&c, s->a.ctrl, sizeof c, hipMemcpyDeviceToHost));
+            if (c.stop) break;
+        }
+    }
+    HIP64_TRY(hipStreamSynchronize(s->stream));
+    HIP64_TRY(hipMemcpy(&c, s->a.ctrl, sizeof c, hipMemcpyDeviceToHost));
+    if (gbest_value) HIP64_TRY(hipMemcpy(gbest_value, s->a.pf + c.gidx, sizeof(double), hipMemcpyDeviceToHost));
+    if (gbest_pos) HIP64_TRY(hipMemcpy(gbest_pos, s->a.gpos, sizeof(double) * s->D, hipMemcpyDeviceToHost));
+    if (gbest_iter) *gbest_iter = c.giter;
+    if (iters_done) *iters_done = c.t - t0;
+    return PSO_OK;
+}
+
+int pso64_get_state(pso_swarm64 *s, double *x, double *v, double *p, double *pf, int64_t *gbest_index, int64_t *t)
+{
+    if (!s) return pso_internal_fail(PSO_EINVAL, "swarm is NULL");
+    HIP64_TRY(hipStreamSynchronize(s->stream));
+    int rc;
+    if ((rc = rows_to_host(s, s->a.x, x)) || (rc = rows_to_host(s, s->a.v, v)) || (rc = rows_to_host(s, s->a.p, p)))
+        return rc;
+    if (pf) HIP64_TRY(hipMemcpy(pf, s->a.pf, sizeof(double) * s->N, hipMemcpyDeviceToHost));
+    pso::Ctrl64 c{};
+    HIP64_TRY(hipMemcpy(&c, s->a.ctrl, sizeof c, hipMemcpyDeviceToHost));
+    if (gbest_index) *gbest_index = c.gidx;
+    if (t) *t = c.t;
+    return PSO_OK;
+}
+
+int pso64_destroy(pso_swarm64 *s)
+{
+    if (!s) return pso_internal_fail(PSO_EINVAL, "swarm is NULL");
+    free64(s);
+    return PSO_OK;
+}
+
+} // extern "C"

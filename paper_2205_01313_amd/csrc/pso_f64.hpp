@@ -1,0 +1,55 @@
+// pso_f64.hpp -- the binary64 path: the same method in double (the paper's
+// own precision, Sec. 5), from the same binary32 parameters and the same
+// 24-bit uniforms.  Host side of the kernels in pso_f64.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace pso {
+
+// Control block of a binary64 swarm (device memory).
+struct alignas(256) Ctrl64 {
+    unsigned long long gord; // order bits of the gbest fitness (see ord64)
+    uint32_t gidx;           // gbest particle
+    uint32_t arrive;         // workgroups that finished the current launch
+    long long giter;         // iteration of the last gbest change
+    long long t;             // iterations completed
+    uint32_t stop;           // stop rule met
+    uint32_t pad;
+    double tol, fstar;       // stop rule |gbest - fstar| < tol (tol <= 0: off)
+    unsigned char pad2[192];
+};
+static_assert(sizeof(Ctrl64) == 256, "Ctrl64 layout");
+
+struct Swarm64Args {
+    double *x, *v, *p, *pf;        // D*Np, D*Np, D*Np, Np; element (d, i) at d*Np + i
+    double *gpos;                  // D
+    const double *shift;           // D
+    unsigned long long *slot_ord;  // one per grid workgroup
+    uint32_t *slot_idx;            // one per grid workgroup
+    Ctrl64 *ctrl;
+    uint32_t N, Np;
+    int32_t D;
+    double lo, hi, w, c1, c2, vmax;
+    uint32_t k0, k1;
+};
+
+struct Layout64 {
+    size_t ctrl, gpos, shift, slot_ord, slot_idx, pf, x, v, p, total;
+    uint64_t Np;
+    uint32_t nblocks;
+};
+
+Layout64 layout64_of(uint64_t N, int D);
+Swarm64Args bind64(void *base, const Layout64 &L, uint64_t N, int D);
+
+// Step 1 (grid), one iteration (grid), or up to T iterations in one
+// workgroup (block).  All honour and update the control block's stop rule.
+hipError_t launch64_init(int fitness, const Swarm64Args &a, hipStream_t stream);
+hipError_t launch64_step(int fitness, const Swarm64Args &a, hipStream_t stream);
+hipError_t launch64_block_run(int fitness, const Swarm64Args &a, long long T, hipStream_t stream);
+hipError_t launch64_arm(const Swarm64Args &a, double tol, double fstar, hipStream_t stream);
+
+} // namespace pso

@@ -12,7 +12,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def declared(header):
     src = open(os.path.join(ROOT, "include", header)).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(pso_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(pso[0-9]*_[a-z0-9_]+)\s*\(", src)))
 
 
 @pytest.fixture(scope="module")
@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol(libpath):
     names = declared("pso.h")
     assert "pso_create" in names and "pso_run" in names
     out = subprocess.run(["nm", "-D", "--defined-only", libpath], capture_output=True, text=True, check=True).stdout
-    exported = set(re.findall(r"\bT (pso_[a-z_]+)$", out, flags=re.M))
+    exported = set(re.findall(r"\bT (pso[0-9]*_[a-z0-9_]+)$", out, flags=re.M))
     missing = [n for n in names if n not in exported]
     assert not missing, missing
 
@@ -67,3 +67,9 @@ def test_pure_host_entry_points_without_gpu(libpath):
     assert lib.pso_batch_get_shape(None, ctypes.byref(shape)) == _native.PSO_EINVAL
     assert lib.pso_batch_set_shape(None, ctypes.byref(shape)) == _native.PSO_EINVAL
     assert lib.pso_batch_autotune(None, 8, None) == _native.PSO_EINVAL
+    b = (ctypes.c_float * 2)(-1.0, 1.0)
+    h64 = ctypes.c_void_p()
+    assert lib.pso64_create(9, 16, 2, b, 0.7, 1.4, 1.4, 0.2, 0, ctypes.byref(h64)) == _native.PSO_EINVAL
+    assert lib.pso64_create(0, 0, 2, b, 0.7, 1.4, 1.4, 0.2, 0, ctypes.byref(h64)) == _native.PSO_EINVAL
+    assert lib.pso64_destroy(None) == _native.PSO_EINVAL
+    assert lib.pso64_step(None) == _native.PSO_EINVAL

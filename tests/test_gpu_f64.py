@@ -1,0 +1,112 @@
+"""The binary64 path against the oracle's binary64 mode.
+
+Sphere, Rosenbrock and Cubic use only +, -, * and / in double, so the state
+after a run (x, v, pbest position and fitness, gbest index and iteration) is
+compared bit for bit, on the one-workgroup path (N*D <= 4096, 256 or 1024
+lanes), the grid path and step by step.  Rastrigin and Ackley call cos and exp, whose device
+and host implementations may differ in the last bit: after one iteration the
+state is compared within 1e-12 relative, and after a longer run the
+invariants of the method are checked (bounds, velocity limit, pbest fitness
+equal to F(pbest position), gbest = lowest-index minimum of the pbest
+fitness)."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2205_01313_amd as pso
+from paper_2205_01313_amd import workloads as wl
+from tests.gpu_util import announce, oracle_swarm
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu64(spec):
+    return pso.Swarm64(spec.fitness, spec.N, spec.D, (spec.lo, spec.hi), spec.w, spec.c1, spec.c2, spec.vmax,
+                       spec.seed, shift=spec.shift)
+
+
+def assert_equal64(g, o, what=("x", "v", "p", "pf")):
+    for k in what:
+        a, b = np.asarray(g[k]), np.asarray(o[k])
+        bad = np.flatnonzero(a.view(np.uint64) != b.view(np.uint64))
+        assert bad.size == 0, f"{k} differs at {bad[:5].tolist()}: {a[bad[0]]!r} vs {b[bad[0]]!r}"
+
+
+@pytest.mark.parametrize("fit", ["sphere", "rosenbrock", "cubic"])
+@pytest.mark.parametrize("N,D,how", [(500, 7, "run"), (300, 1, "run"), (3001, 9, "run"), (777, 13, "step"),
+                                     (64, 2, "run")])
+def test_exact_functions_bit_for_bit(fit, N, D, how):
+    if fit == "rosenbrock" and D < 2:
+        pytest.skip("Rosenbrock needs D >= 2")
+    T = 50
+    spec = wl.SwarmSpec(fit, N, D, T, seed=N * 13 + D, shift_amplitude=2.0)
+    announce(f"f64 {fit} N={N} D={D} {how}")
+    o = oracle_swarm(spec, 8).run_f64(T)
+    with gpu64(spec) as g:
+        if how == "run":
+            r = g.run(T)
+            assert r["iters"] == T and r["gbest_iter"] == o["giter"]
+            assert r["gbest_fit"] == o["gbest_fit"]
+            assert np.array_equal(r["gbest_pos"].view(np.uint64), o["gpos"].view(np.uint64))
+        else:
+            g.step(T)
+        st = g.state()
+    assert st["t"] == T and st["gbest_idx"] == o["gbest_idx"]
+    assert_equal64(st, o)
+
+
+def test_paper_shape_cubic_1d():
+    """The paper's 1D problem: Cubic (Eq. 3, maximised there, minimised
+    negated here) on [-100, 100], w = 1, c1 = c2 = 2, double; vmax 20."""
+    spec = wl.SwarmSpec("cubic", 2048, 1, 3000, seed=3, box=(-100.0, 100.0), vmax=20.0, w=1.0, c1=2.0, c2=2.0)
+    announce("f64 paper-shape cubic 1D N=2048 T=3000")
+    o = oracle_swarm(spec, 8).run_f64(spec.T)
+    with gpu64(spec) as g:
+        r = g.run(spec.T)
+        st = g.state()
+    assert r["gbest_fit"] == o["gbest_fit"] and r["gbest_iter"] == o["giter"]
+    assert_equal64(st, o)
+
+
+def test_stop_rule_and_resume():
+    spec = wl.SwarmSpec("sphere", 512, 4, 400, seed=9)
+    announce("f64 stop rule")
+    o = oracle_swarm(spec).run_f64(400, tol=1e-3, f_star=0.0)
+    assert o["iters"] < 400
+    with gpu64(spec) as g:
+        r = g.run(400, tol=1e-3, f_star=0.0)
+        assert r["iters"] == o["iters"] and r["gbest_fit"] == o["gbest_fit"]
+        assert g.run(10, tol=1e-3, f_star=0.0)["iters"] == 0
+        g.reset()
+        a = g.run(30)
+        g.reset()
+        b1 = g.run(10)
+        b2 = g.run(20)
+    assert b1["iters"] + b2["iters"] == 30 and a["gbest_fit"] == b2["gbest_fit"]
+
+
+@pytest.mark.parametrize("fit", ["rastrigin", "ackley"])
+def test_transcendental_functions_close_then_invariants(fit):
+    spec = wl.SwarmSpec(fit, 4000, 24, 1, seed=5, shift_amplitude=3.0)
+    announce(f"f64 {fit} one iteration")
+    o = oracle_swarm(spec, 8).run_f64(1)
+    with gpu64(spec) as g:
+        g.run(1)
+        st = g.state()
+    assert st["gbest_idx"] == o["gbest_idx"]
+    assert_equal64(st, o, what=("x", "v"))
+    np.testing.assert_allclose(st["pf"], o["pf"], rtol=1e-12, atol=1e-12)
+    # a longer run: invariants of the method
+    T = 200
+    with gpu64(spec) as g:
+        g.run(T)
+        st = g.state()
+    N, D = spec.N, spec.D
+    x, v, p = (st[k].reshape(D, N) for k in ("x", "v", "p"))
+    assert (x >= spec.lo).all() and (x <= spec.hi).all()
+    assert (np.abs(v) <= np.float32(spec.vmax)).all()
+    ref = oracle_swarm(spec, 8).fitness_f64(p.T)
+    np.testing.assert_allclose(st["pf"], ref, rtol=1e-12, atol=1e-12)
+    gi = st["gbest_idx"]
+    assert st["pf"][gi] == st["pf"].min() and gi == int(np.flatnonzero(st["pf"] == st["pf"].min())[0])
+    assert st["t"] == T
