@@ -173,6 +173,27 @@ def deep_leg(pso, torch, wl, stream):
     return out
 
 
+def latency_leg(pso):
+    """Latency-bound swarms (binary32 Cubic 1D, N = 1024 / 4096 / 16384,
+    20 000 iterations; w = 1, c1 = c2 = 2, [-100, 100], vmax 20): microseconds
+    per iteration of a pso_run, synchronous against the fully asynchronous
+    persistent variant (one launch, no barrier between iterations)."""
+    rows = []
+    for N in (1024, 4096, 16384):
+        row = dict(N=N, D=1, iterations=20000)
+        for name, var in (("sync", pso.PSO_SYNC), ("persistent", pso.PSO_PERSISTENT)):
+            with pso.Swarm("cubic", N, 1, (-100.0, 100.0), 1.0, 2.0, 2.0, 20.0, 0, variant=var) as g:
+                g.run(200)
+                g.reset()
+                t0 = time.perf_counter()
+                r = g.run(20000)
+                s = time.perf_counter() - t0
+            row[name + "_us_per_iteration"] = s / 20000 * 1e6
+            row[name + "_gbest"] = float(r["gbest_fit"])
+        rows.append(row)
+    return dict(precision="f32", rows=rows)
+
+
 # The paper's experiments (Sec. 5, Tables 2-4): binary64, Cubic (Eq. 3, on
 # [-100, 100]), w = 1, c1 = c2 = 2; vmax is not stated there (0.1 of the box
 # here).  The paper's own Queue Lock (1D) and Queue (120D) seconds on its
@@ -289,8 +310,9 @@ def main():
     ap.add_argument("--variant", choices=["sync", "async"], default="sync")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=200)
-    ap.add_argument("--legs", default="main,async,small,deep,paper,batched,serving",
-                    help="comma list of legs beyond the main line: async, small, deep, paper, batched, serving")
+    ap.add_argument("--legs", default="main,async,small,deep,latency,paper,batched,serving",
+                    help="comma list of legs beyond the main line: async, small, deep, latency, paper, batched, "
+                         "serving")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="for rocprofv3 counter runs: init + 20 step launches, then a 256 MiB torch copy "
                          "(calibration kernel of known size); prints nothing else")
@@ -413,6 +435,8 @@ def main():
         out["small"] = small_leg(pso, torch, wl, stream)
     if "deep" in legs:
         out["deep"] = deep_leg(pso, torch, wl, stream)
+    if "latency" in legs:
+        out["latency"] = latency_leg(pso)
     if "paper" in legs:
         out["paper"] = paper_leg(pso)
     if "batched" in legs:

@@ -59,6 +59,7 @@ extern "C" {
 #define PSO_ASYNC 1 /* a workgroup publishes a better gbest at once (Sec. 3.2) */
 #define PSO_REDUCE 2 /* the paper's comparator: two kernels, tree reduction through auxiliary arrays (Sec. 2.2) */
 #define PSO_REDUCE_UNROLLED 3 /* the same with the last wavefront's reduction steps unrolled (Sec. 2.2) */
+#define PSO_PERSISTENT 4 /* fully asynchronous: one launch runs every iteration, no barrier between them (Sec. 6) */
 
 typedef struct pso_swarm pso_swarm;
 
@@ -97,10 +98,22 @@ int pso_create_in(int fitness_id, int64_t N, int32_t D, const float bounds[2], f
 int pso_set_shift(pso_swarm *s, const float *shift_host);
 
 /* Selects the aggregation of the iterations that follow: PSO_SYNC
- * (default), PSO_ASYNC, or the comparators PSO_REDUCE / PSO_REDUCE_UNROLLED
+ * (default), PSO_ASYNC, the comparators PSO_REDUCE / PSO_REDUCE_UNROLLED
  * (which compute exactly what PSO_SYNC computes, with two launches per
- * iteration). */
+ * iteration), or PSO_PERSISTENT: one launch runs all the iterations of a
+ * pso_run (pso_step: one), each workgroup iterating its own slice of the
+ * particles with no barrier between iterations, reading the published gbest
+ * as a consistent snapshot and publishing a better one at once (the
+ * asynchronous variant's rule); a particle still draws Philox numbers with
+ * its own iteration count, and bounded staleness (pso_set_max_lead) keeps
+ * workgroups within a window of each other.  Its trajectory is not
+ * deterministic; its gbest is always the minimum over the pbest fitness. */
 int pso_set_variant(pso_swarm *s, int variant);
+
+/* PSO_PERSISTENT: the most iterations a workgroup may run ahead of the
+ * slowest one (default 8; a value >= max_iter leaves it unbounded).
+ * max_lead < 0 -> EINVAL. */
+int pso_set_max_lead(pso_swarm *s, int64_t max_lead);
 
 /* Re-runs Step 1 in place: the swarm returns to iteration 0 with the same
  * parameters, seed and shift.  Allocates nothing. */

@@ -13,7 +13,7 @@ import numpy as np
 
 from . import _native
 from ._native import (PSO_ACKLEY, PSO_ASYNC, PSO_CUBIC, PSO_EAGAIN, PSO_EDEVICE, PSO_EINVAL,  # noqa: F401
-                      PSO_ENOMEM, PSO_ESTATE, PSO_OK, PSO_RASTRIGIN, PSO_REDUCE, PSO_REDUCE_UNROLLED,
+                      PSO_ENOMEM, PSO_ESTATE, PSO_OK, PSO_PERSISTENT, PSO_RASTRIGIN, PSO_REDUCE, PSO_REDUCE_UNROLLED,
                       PSO_ROSENBROCK, PSO_SPHERE, PSO_SYNC)
 
 FITNESS = {"sphere": PSO_SPHERE, "rastrigin": PSO_RASTRIGIN, "rosenbrock": PSO_ROSENBROCK,
@@ -73,6 +73,10 @@ def pso_set_shift(h, shift):
 
 def pso_set_variant(h, variant: int):
     return _check(lib().pso_set_variant(h, variant), "pso_set_variant")
+
+
+def pso_set_max_lead(h, max_lead: int):
+    return _check(lib().pso_set_max_lead(h, int(max_lead)), "pso_set_max_lead")
 
 
 def pso_reset(h):
@@ -365,6 +369,9 @@ class Swarm:
             pso_set_shift(self.h, shift)
         if variant != PSO_SYNC:
             pso_set_variant(self.h, variant)
+
+    def set_max_lead(self, max_lead):
+        pso_set_max_lead(self.h, max_lead)
 
     def step(self, n=1):
         for _ in range(n):

@@ -10,7 +10,7 @@ LIB_PATH = os.path.join(HERE, "libpso.so")
 
 PSO_OK, PSO_EINVAL, PSO_ENOMEM, PSO_EDEVICE, PSO_EAGAIN, PSO_ESTATE = 0, -1, -2, -3, -4, -5
 PSO_SPHERE, PSO_RASTRIGIN, PSO_ROSENBROCK, PSO_ACKLEY, PSO_CUBIC = 0, 1, 2, 3, 4
-PSO_SYNC, PSO_ASYNC, PSO_REDUCE, PSO_REDUCE_UNROLLED = 0, 1, 2, 3
+PSO_SYNC, PSO_ASYNC, PSO_REDUCE, PSO_REDUCE_UNROLLED, PSO_PERSISTENT = 0, 1, 2, 3, 4
 
 c_int, c_i32, c_i64, c_u64, c_f, c_size, c_vp = (ctypes.c_int, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
                                                    ctypes.c_float, ctypes.c_size_t, ctypes.c_void_p)
@@ -75,6 +75,7 @@ SIGNATURES = {
     "pso64_run": (c_int, [c_vp, c_i64, c_f64, c_f64, P(c_f64), P(c_f64), P(c_i64), P(c_i64)]),
     "pso64_get_state": (c_int, [c_vp, P(c_f64), P(c_f64), P(c_f64), P(c_f64), P(c_i64), P(c_i64)]),
     "pso64_destroy": (c_int, [c_vp]),
+    "pso_set_max_lead": (c_int, [c_vp, c_i64]),
     "pso_batch_get_shape": (c_int, [c_vp, P(PsoBatchShape)]),
     "pso_batch_set_shape": (c_int, [c_vp, P(PsoBatchShape)]),
     "pso_batch_autotune": (c_int, [c_vp, c_i64, P(PsoBatchShape)]),

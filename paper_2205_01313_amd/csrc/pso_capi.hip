@@ -67,6 +67,7 @@ int pso_internal_fail(int code, const char *fmt, ...)
 struct pso_swarm {
     int fitness = 0;
     int variant = PSO_SYNC;
+    int64_t max_lead = 8; // PSO_PERSISTENT staleness bound
     uint64_t N = 0;
     int32_t D = 0;
     Layout L{};
@@ -239,8 +240,16 @@ int pso_set_shift(pso_swarm *s, const float *shift_host)
 int pso_set_variant(pso_swarm *s, int variant)
 {
     if (!s) return fail(PSO_EINVAL, "swarm is NULL");
-    if (variant < PSO_SYNC || variant > PSO_REDUCE_UNROLLED) return fail(PSO_EINVAL, "unknown variant %d", variant);
+    if (variant < PSO_SYNC || variant > PSO_PERSISTENT) return fail(PSO_EINVAL, "unknown variant %d", variant);
     s->variant = variant;
+    return PSO_OK;
+}
+
+int pso_set_max_lead(pso_swarm *s, int64_t max_lead)
+{
+    if (!s) return fail(PSO_EINVAL, "swarm is NULL");
+    if (max_lead < 0) return fail(PSO_EINVAL, "max_lead < 0");
+    s->max_lead = max_lead;
     return PSO_OK;
 }
 
@@ -250,9 +259,27 @@ int pso_reset(pso_swarm *s)
     return enqueue_init(s);
 }
 
+namespace {
+
+// One persistent launch of T iterations (iteration counts cleared first).
+int persistent_launch(pso_swarm *s, int64_t T)
+{
+    while (T > 0) {
+        const uint32_t n = (uint32_t)std::min<int64_t>(T, int64_t(1) << 30);
+        const uint32_t lead = (uint32_t)std::min<int64_t>(s->max_lead, int64_t(0xFFFFFFFF));
+        HIP_TRY(hipMemsetAsync(s->args.prog, 0, sizeof(uint32_t) * pso::PERSIST_MAX_GRID, s->stream));
+        HIP_TRY(pso::launch_persistent(s->fitness, s->args, n, lead, s->stream));
+        T -= n;
+    }
+    return PSO_OK;
+}
+
+} // namespace
+
 int pso_step(pso_swarm *s)
 {
     if (!s) return fail(PSO_EINVAL, "swarm is NULL");
+    if (s->variant == PSO_PERSISTENT) return persistent_launch(s, 1);
     HIP_TRY(pso::launch_step(s->fitness, s->variant, s->args, s->stream));
     return PSO_OK;
 }
@@ -265,7 +292,10 @@ int pso_run(pso_swarm *s, int64_t max_iter, float tol, float f_star, float *gbes
     if (std::isnan(tol) || std::isnan(f_star)) return fail(PSO_EINVAL, "tol and f_star must not be NaN");
     HIP_TRY(pso::launch_arm(s->args, tol, f_star, s->stream));
     const bool block_path = s->variant == PSO_SYNC && int64_t(s->N) * s->D <= BLOCK_RUN_MAX_ND;
-    if (block_path) {
+    if (s->variant == PSO_PERSISTENT) {
+        int rc = persistent_launch(s, max_iter);
+        if (rc) return rc;
+    } else if (block_path) {
         if (max_iter > 0) HIP_TRY(pso::launch_block_run(s->fitness, s->args, max_iter, s->stream));
     } else if (tol > 0.0f) {
         // Chunks of iterations with one chunk always queued ahead; the

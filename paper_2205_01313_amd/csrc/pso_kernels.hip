@@ -25,6 +25,7 @@
 //   - Asynchronous variant (the lock-protected gbest of Sec. 3.2): a
 //     workgroup that lowers the gbest publishes its position at once under a
 //     seqlock, and workgroups that start later in the same iteration use it.
+#include <algorithm>
 #include <cstdlib>
 
 #include "pso_quad.hpp"
@@ -85,6 +86,7 @@ Layout layout_of(uint64_t N, int D, bool control)
     L.shift = o; o += align256(sizeof(float) * D);
     L.hist = o;  o += control ? align256(sizeof(unsigned long long) * HIST_CAP) : 0;
     L.aux = o;   o += control ? align256(sizeof(unsigned long long) * ((Np / 4 + BLOCK - 1) / BLOCK)) : 0;
+    L.prog = o;  o += control ? align256(sizeof(uint32_t) * PERSIST_MAX_GRID) : 0;
     L.pf = o;    o += align256(sizeof(float) * Np);
     L.pend = o;  o += align256(Np);
     L.x = o;     o += align256(sizeof(float) * Np * (size_t)D);
@@ -116,6 +118,7 @@ SwarmArgs bind(void *base, const Layout &L, uint64_t N, int D)
     a.shift = reinterpret_cast<const float *>(b + L.shift);
     a.hist = L.control ? reinterpret_cast<unsigned long long *>(b + L.hist) : nullptr;
     a.aux = L.control ? reinterpret_cast<unsigned long long *>(b + L.aux) : nullptr;
+    a.prog = L.control ? reinterpret_cast<uint32_t *>(b + L.prog) : nullptr;
     a.pf = reinterpret_cast<float *>(b + L.pf);
     a.pend = reinterpret_cast<uint8_t *>(b + L.pend);
     a.x = reinterpret_cast<float *>(b + L.x);
@@ -501,6 +504,136 @@ __global__ void PSO_STEP_ATTR k_step_split(SwarmArgs a, uint32_t L, uint32_t C)
 }
 
 // ---------------------------------------------------------------------------
+// Fully asynchronous persistent run (the further asynchronous scheme the
+// paper leaves to future work, Sec. 6): one launch runs T iterations.  Every
+// workgroup owns a fixed slice of particle quads and iterates it on its own:
+// it reads the published gbest as a consistent snapshot (seqlock, as the
+// asynchronous step), updates its particles with Philox counter t = its own
+// iteration count (so each particle draws the same numbers as in any other
+// variant), and publishes a better gbest at once.  No barrier separates
+// iterations.  Staleness is bounded: before iteration k a workgroup waits
+// until every workgroup has finished k - 1 - max_lead iterations (the grid is
+// fully co-resident, so the slowest always progresses; the wait is bounded
+// by the wall clock and sets an error bit if it gives up).  Any workgroup
+// that sees the stop rule met stops them all.
+// ---------------------------------------------------------------------------
+constexpr unsigned long long PERSIST_WAIT_TICKS = 2000000000ull; // 20 s of the 100 MHz wall clock
+
+// Waits (first wavefront) until every workgroup's iteration count is at
+// least `need`; false in every lane if the wait gave up.  Uniform call.
+__device__ bool wait_watermark(const uint32_t *prog, uint32_t need, uint32_t *s_seen, int *s_ok, Ctrl *c)
+{
+    if (*s_seen >= need) return true;
+    if (threadIdx.x < 64) {
+        const unsigned long long t0 = wall_clock64();
+        for (;;) {
+            uint32_t m = 0xFFFFFFFFu;
+            for (uint32_t b = threadIdx.x; b < gridDim.x; b += 64) {
+                const uint32_t v = __hip_atomic_load(&prog[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                m = v < m ? v : m;
+            }
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) {
+                const uint32_t o = __shfl_xor(m, off, 64);
+                m = o < m ? o : m;
+            }
+            if (m >= need) {
+                if (threadIdx.x == 0) {
+                    *s_seen = m;
+                    *s_ok = 1;
+                }
+                break;
+            }
+            // a workgroup that stopped (stop rule, or a wait that gave up)
+            // will not reach `need`: stop too
+            if (__hip_atomic_load(&c->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+                if (threadIdx.x == 0) *s_ok = 0;
+                break;
+            }
+            if (wall_clock64() - t0 > PERSIST_WAIT_TICKS) {
+                if (threadIdx.x == 0) {
+                    atomicOr(&c->err, ERR_STALE_WAIT);
+                    __hip_atomic_store(&c->stop, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    *s_ok = 0;
+                }
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+    }
+    __syncthreads();
+    return *s_ok != 0;
+}
+
+template <int FIT, int POL>
+__global__ void PSO_STEP_ATTR k_persist(SwarmArgs a, uint32_t T, uint32_t max_lead, uint32_t qpw)
+{
+    __shared__ unsigned long long wg_min;
+    __shared__ unsigned long long snap_key;
+    __shared__ uint32_t s_seen;
+    __shared__ int flag, s_go, s_ok;
+    extern __shared__ float s_dyn[]; // gbest snapshot (D floats), then shift
+    Ctrl *c = a.ctrl;
+    const int D = a.D;
+    float *s_g = s_dyn, *s_shift = s_dyn + D;
+    for (int d = threadIdx.x; d < D; d += BLOCK) s_shift[d] = a.shift[d];
+    if (threadIdx.x == 0) s_seen = 0;
+    const long long t0 = c->t;
+    const float tol = c->tol, fstar = c->fstar;
+    const uint32_t nq = (a.N + 3) / 4;
+    const uint32_t q_lo = blockIdx.x * qpw, q_hi = min(nq, q_lo + qpw);
+    uint32_t n_imp = 0, done = 0;
+    __syncthreads();
+    for (uint32_t k = 1; k <= T; ++k) {
+        if (threadIdx.x == 0) {
+            s_go = __hip_atomic_load(&c->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u;
+            wg_min = NO_KEY;
+        }
+        __syncthreads();
+        if (!s_go) break;
+        if (max_lead < T && k > max_lead + 1 && !wait_watermark(a.prog, k - 1 - max_lead, &s_seen, &s_ok, c)) break;
+        const uint32_t t = (uint32_t)(t0 + k);
+        const unsigned long long thr = snapshot_async(a, s_g, &snap_key); // ends with a barrier
+        unsigned long long key = NO_KEY;
+        for (uint32_t q = q_lo + threadIdx.x; q < q_hi; q += BLOCK) {
+            uint32_t n = 0;
+            const unsigned long long kk = iterate_quad<FIT, 0, 1, POL>(a, D, q, t, s_g, s_shift, &n);
+            key = kk < key ? kk : key;
+            n_imp += n;
+        }
+        const unsigned long long m = workgroup_min(key, thr, &wg_min);
+        publish_async(a, m, thr, &flag);
+        __syncthreads();
+        done = k;
+        if (threadIdx.x == 0) {
+            if (m < thr && flag) atomicMax(reinterpret_cast<unsigned long long *>(&c->giter), (unsigned long long)t);
+            __hip_atomic_store(&a.prog[blockIdx.x], k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned long long g = __hip_atomic_load(&c->gkey, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (tol > 0.0f && __builtin_fabsf(key_fitness(g) - fstar) < tol)
+                __hip_atomic_store(&c->stop, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    // bookkeeping: improvements, iteration count (the furthest workgroup's),
+    // and from the last workgroup to finish the gbest of the run
+    __shared__ unsigned int wg_count;
+    if (threadIdx.x == 0) wg_count = 0;
+    __syncthreads();
+    count_improvements(c, n_imp, &wg_count);
+    __syncthreads();
+    flush_count(c, &wg_count);
+    if (threadIdx.x == 0)
+        atomicMax(reinterpret_cast<unsigned long long *>(&c->t), (unsigned long long)(t0 + done));
+    if (threadIdx.x == 0) __threadfence();
+    if (arrive_last(c, &flag) && threadIdx.x == 0) {
+        const unsigned long long g = __hip_atomic_load(&c->gkey, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const long long tt = c->t;
+        a.hist[tt & (HIST_CAP - 1)] = g;
+        c->gkey_prev = g;
+        c->arrive = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // The paper's comparator (Sec. 2.2, Fig. 1): a two-kernel parallel
 // reduction.  Kernel 1 updates the particles and reduces every particle's
 // pbest key over its block with a shared-memory tree (log2 of the block
@@ -737,6 +870,50 @@ static void launch_reduce(const SwarmArgs &a, hipStream_t stream)
     case POL_X: launch_reduce_p<FIT, UNROLLED, POL_X>(a, stream); break;
     case POL_XV: launch_reduce_p<FIT, UNROLLED, POL_XV>(a, stream); break;
     default: launch_reduce_p<FIT, UNROLLED, POL_ALL>(a, stream); break;
+    }
+}
+
+template <int FIT, int POL>
+static hipError_t launch_persist_p(const SwarmArgs &a, uint32_t T, uint32_t max_lead, hipStream_t stream)
+{
+    const size_t lds = 2 * sizeof(float) * a.D;
+    int per_cu = 0, dev = 0, cus = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persist<FIT, POL>, BLOCK, lds);
+    if (e != hipSuccess) return e;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+    // every workgroup co-resident (three quarters of the occupancy bound),
+    // one particle quad per lane where the swarm allows it
+    const uint64_t cap = std::min<uint64_t>(PERSIST_MAX_GRID, std::max(1, per_cu * cus * 3 / 4));
+    const uint64_t nq = ((uint64_t)a.N + 3) / 4;
+    const uint64_t grid = std::max<uint64_t>(1, std::min<uint64_t>(cap, (nq + BLOCK - 1) / BLOCK));
+    const uint32_t qpw = (uint32_t)((nq + grid - 1) / grid);
+    const uint64_t used = (nq + qpw - 1) / qpw;
+    hipLaunchKernelGGL((k_persist<FIT, POL>), dim3((unsigned)used), dim3(BLOCK), lds, stream, a, T, max_lead, qpw);
+    return hipGetLastError();
+}
+
+template <int FIT>
+static hipError_t launch_persist_f(const SwarmArgs &a, uint32_t T, uint32_t max_lead, hipStream_t stream)
+{
+    switch (cache_policy(a.Np, a.D)) {
+    case POL_STREAM: return launch_persist_p<FIT, POL_STREAM>(a, T, max_lead, stream);
+    case POL_X: return launch_persist_p<FIT, POL_X>(a, T, max_lead, stream);
+    case POL_XV: return launch_persist_p<FIT, POL_XV>(a, T, max_lead, stream);
+    default: return launch_persist_p<FIT, POL_ALL>(a, T, max_lead, stream);
+    }
+}
+
+hipError_t launch_persistent(int fitness, const SwarmArgs &a, uint32_t T, uint32_t max_lead, hipStream_t stream)
+{
+    if (!a.ctrl || !a.prog || T == 0) return T == 0 ? hipSuccess : hipErrorInvalidValue;
+    switch (fitness) {
+    case F_SPHERE: return launch_persist_f<F_SPHERE>(a, T, max_lead, stream);
+    case F_RASTRIGIN: return launch_persist_f<F_RASTRIGIN>(a, T, max_lead, stream);
+    case F_ROSENBROCK: return launch_persist_f<F_ROSENBROCK>(a, T, max_lead, stream);
+    case F_ACKLEY: return launch_persist_f<F_ACKLEY>(a, T, max_lead, stream);
+    case F_CUBIC: return launch_persist_f<F_CUBIC>(a, T, max_lead, stream);
+    default: return hipErrorInvalidValue;
     }
 }
 

@@ -38,6 +38,7 @@ struct alignas(256) Ctrl {
 static_assert(sizeof(Ctrl) == 1024, "Ctrl layout");
 
 constexpr unsigned int ERR_SEQLOCK_SPIN = 1u; // a seqlock wait gave up
+constexpr unsigned int ERR_STALE_WAIT = 2u;   // a bounded-staleness wait gave up
 
 // Aggregation variants (values of PSO_SYNC / PSO_ASYNC / PSO_REDUCE /
 // PSO_REDUCE_UNROLLED in pso.h).
@@ -45,6 +46,10 @@ constexpr int VAR_SYNC = 0;
 constexpr int VAR_ASYNC = 1;
 constexpr int VAR_REDUCE = 2;
 constexpr int VAR_REDUCE_UNROLLED = 3;
+constexpr int VAR_PERSISTENT = 4;
+
+// Workgroups of a persistent run hold their iteration counts here.
+constexpr uint32_t PERSIST_MAX_GRID = 8192;
 
 // Device pointers and parameters of one swarm, passed by value to kernels
 // (the kernel-argument segment is read through the scalar cache, the role
@@ -56,6 +61,7 @@ struct SwarmArgs {
     const float *shift;         // D
     unsigned long long *hist;   // HIST_CAP
     unsigned long long *aux;    // one key per step workgroup (two-kernel reduction)
+    uint32_t *prog;             // PERSIST_MAX_GRID iteration counts (persistent run)
     Ctrl *ctrl;
     uint32_t N;
     uint32_t Np;                // row pitch: N rounded up to a multiple of 64
@@ -80,7 +86,7 @@ int cache_policy(uint64_t Np, int D);
 // Np = N rounded up to 64 particles, so every row starts 256-byte aligned and
 // a lane can move four consecutive particles with one 16-byte access.
 struct Layout {
-    size_t ctrl, gpos, shift, hist, aux, pf, pend, x, v, p, total;
+    size_t ctrl, gpos, shift, hist, aux, prog, pf, pend, x, v, p, total;
     uint64_t Np;
     bool control; // ctrl and hist present
 };
@@ -98,5 +104,11 @@ hipError_t launch_arm(const SwarmArgs &a, float tol, float fstar, hipStream_t st
 hipError_t launch_flush(const SwarmArgs &a, hipStream_t stream);
 // Marks no pbest position pending (after the state is replaced).
 hipError_t launch_clear_pending(const SwarmArgs &a, hipStream_t stream);
+// Fully asynchronous persistent run: T iterations in one launch, no barrier
+// between iterations; a workgroup runs at most max_lead iterations ahead of
+// the slowest one (>= T: unbounded).  Needs the control block (launch_arm
+// first for the stop rule) and the iteration counts a.prog zeroed for the
+// launch's workgroups (at most PERSIST_MAX_GRID).
+hipError_t launch_persistent(int fitness, const SwarmArgs &a, uint32_t T, uint32_t max_lead, hipStream_t stream);
 
 } // namespace pso
