@@ -257,7 +257,7 @@ def batched_leg(pso, torch, wl, stream, subset=96):
                 batched_vs_plain_speedup=ms_plain / ms_sub, equal_results=bool(same))
 
 
-def serving_leg(pso, wl, rates=(2000, 10000, 50000), count=2000, budget=32 << 30, chunk=1 << 20):
+def serving_leg(pso, wl, rates=(2000, 10000, 50000), count=2000, budget=32 << 30, chunk=0):
     """Poisson arrivals of solve requests (N lognormal median 512, D in
     [2, 64], stop at |gbest| < 1e-4 or 1000 iterations) submitted at their
     arrival times; latency is submit-to-completion inside the server."""

@@ -319,8 +319,10 @@ typedef struct pso_server_counters {
 } pso_server_counters;
 
 /* Starts a server with mem_budget bytes of device memory for swarm state
- * (allocated now) and chunk_updates updates per swarm and launch (<= 0:
- * 2^20). */
+ * (allocated now).  Each launch gives every admitted swarm the iterations
+ * that fit a 2 ms slice at its own measured speed (4 on its first launch),
+ * at most chunk_updates particle-dimension updates' worth (<= 0: no such
+ * cap). */
 int pso_server_create(size_t mem_budget, int64_t chunk_updates, pso_server **out);
 
 /* Queues one request (validated as a batch descriptor; the shift is copied)

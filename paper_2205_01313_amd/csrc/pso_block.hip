@@ -289,6 +289,7 @@ __global__ void k_batch_reset(const BatchItem *items, BatchResult *results, uint
         results[i].iters = 0;
         results[i].started = 0;
         results[i].stop = 0;
+        results[i].ticks = 0;
         if (items[i].parts > 1) {
             items[i].gang->arrive = 0ull;
             items[i].gang->err = 0u;
@@ -302,8 +303,8 @@ __global__ void k_counter_reset(unsigned int *next)
 }
 
 template <int FIT, int LANES>
-__device__ void batch_part(const BatchItem &it, uint32_t part, BatchResult *res, long long chunk, long long iter_cap,
-                           float *s_g,
+__device__ void batch_part(const BatchItem &it, uint32_t part, uint32_t fixed_iters, BatchResult *res, long long chunk,
+                           long long iter_cap, float *s_g,
                            float *s_shift, Scratch *sc, BatchResult *out_state, float *out_pos, uint32_t out,
                            int pos_stride)
 {
@@ -345,7 +346,10 @@ __device__ void batch_part(const BatchItem &it, uint32_t part, BatchResult *res,
     const long long nd = (long long)a.N * a.D;
     long long iters = chunk / nd;
     iters = iters < 1 ? 1 : (iters > iter_cap ? iter_cap : iters);
+    if (fixed_iters > 0) iters = fixed_iters;
+    const unsigned long long c0 = wall_clock64();
     block_iterate<FIT, LANES>(a, P, left < iters ? left : iters, it.tol, it.fstar, s_shift, s_g, sc, nullptr, L);
+    const unsigned long long ticks = wall_clock64() - c0;
     if (part == 0) {
         for (int d = threadIdx.x; d < D; d += LANES) {
             a.gpos[d] = s_g[d];
@@ -357,6 +361,7 @@ __device__ void batch_part(const BatchItem &it, uint32_t part, BatchResult *res,
             res->iters = L.t;
             res->stop = L.stop ? 1u : 0u;
             res->started = 1u;
+            res->ticks = ticks > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)ticks;
             if (out_state) out_state[out] = *res;
         }
     }
@@ -383,11 +388,11 @@ __global__ void __launch_bounds__(LANES) k_batch(const BatchItem *items, const B
         float *s_g = s_dyn, *s_shift = s_dyn + it.a.D;
         BatchResult *res = &results[e.item];
         switch (it.fitness) {
-        case F_SPHERE: batch_part<F_SPHERE, LANES>(it, e.part, res, chunk, iter_cap, s_g, s_shift, &sc, out_state, out_pos, e.out, pos_stride); break;
-        case F_RASTRIGIN: batch_part<F_RASTRIGIN, LANES>(it, e.part, res, chunk, iter_cap, s_g, s_shift, &sc, out_state, out_pos, e.out, pos_stride); break;
-        case F_ROSENBROCK: batch_part<F_ROSENBROCK, LANES>(it, e.part, res, chunk, iter_cap, s_g, s_shift, &sc, out_state, out_pos, e.out, pos_stride); break;
-        case F_ACKLEY: batch_part<F_ACKLEY, LANES>(it, e.part, res, chunk, iter_cap, s_g, s_shift, &sc, out_state, out_pos, e.out, pos_stride); break;
-        default: batch_part<F_CUBIC, LANES>(it, e.part, res, chunk, iter_cap, s_g, s_shift, &sc, out_state, out_pos, e.out, pos_stride); break;
+        case F_SPHERE: batch_part<F_SPHERE, LANES>(it, e.part, e.iters, res, chunk, iter_cap, s_g, s_shift, &sc, out_state, out_pos, e.out, pos_stride); break;
+        case F_RASTRIGIN: batch_part<F_RASTRIGIN, LANES>(it, e.part, e.iters, res, chunk, iter_cap, s_g, s_shift, &sc, out_state, out_pos, e.out, pos_stride); break;
+        case F_ROSENBROCK: batch_part<F_ROSENBROCK, LANES>(it, e.part, e.iters, res, chunk, iter_cap, s_g, s_shift, &sc, out_state, out_pos, e.out, pos_stride); break;
+        case F_ACKLEY: batch_part<F_ACKLEY, LANES>(it, e.part, e.iters, res, chunk, iter_cap, s_g, s_shift, &sc, out_state, out_pos, e.out, pos_stride); break;
+        default: batch_part<F_CUBIC, LANES>(it, e.part, e.iters, res, chunk, iter_cap, s_g, s_shift, &sc, out_state, out_pos, e.out, pos_stride); break;
         }
         __syncthreads();
     }

@@ -64,12 +64,16 @@ struct BatchResult {
     long long iters;         // iterations run
     uint32_t started;        // Step 1 done
     uint32_t stop;           // stop rule met
+    uint32_t ticks;          // device wall-clock ticks of the last launch's share (part 0)
+    uint32_t pad;
 };
 
 // One unit of a batched launch: part `part` of item `item`; the item's state
-// is also copied to position `out` of the launch's compact outputs.
+// is also copied to position `out` of the launch's compact outputs.  iters > 0
+// fixes the iterations of this launch for the swarm (every part of a swarm
+// carries the same value); 0 takes the `chunk` rule of launch_batch.
 struct BatchEntry {
-    uint32_t item, part, out, pad;
+    uint32_t item, part, out, iters;
 };
 
 // Runs up to T more iterations of one swarm in one workgroup, continuing from
@@ -82,10 +86,10 @@ hipError_t launch_batch_reset(const BatchItem *items, BatchResult *results, uint
                               hipStream_t stream);
 
 // One persistent launch of `grid` workgroups over `count` entries (every part
-// of a listed swarm, consecutive): Step 1 for swarms not started, then
-// clamp(chunk / (N*D), 1, iter_cap) more iterations of each -- `chunk` is a
-// budget of particle-dimension updates per swarm and launch -- within its
-// max_iter and stop rule.  `next` is a device work counter (cleared by the launch).  The
+// of a listed swarm, consecutive): Step 1 for swarms not started, then the
+// entry's iters, or clamp(chunk / (N*D), 1, iter_cap), more iterations of
+// each -- `chunk` is a budget of particle-dimension updates per swarm and
+// launch -- within its max_iter and stop rule.  `next` is a device work counter (cleared by the launch).  The
 // grid must be fully co-resident (at most batch_capacity workgroups, less
 // any other launch running concurrently) and every swarm's parts <= grid.
 // Optionally writes each swarm's state to out_state[out] and its gbest
