@@ -75,9 +75,21 @@ def cpu_baseline(spec, iters: int):
     for t in range(1, iters + 1):
         sw.step_f32(st, t)
     dt = time.perf_counter() - t0
+    # one core (the paper's serial baseline is single-threaded): the same
+    # problem at N = 65536 for 20 iterations, a rate per update
+    n1, it1 = 65536, 20
+    sw1 = oracle.Swarm(spec.fitness, n1, spec.D, spec.lo, spec.hi, spec.w, spec.c1, spec.c2, spec.vmax, spec.seed,
+                       nthreads=1)
+    st1 = sw1.init_f32()
+    t1 = time.perf_counter()
+    for t in range(1, it1 + 1):
+        sw1.step_f32(st1, t)
+    dt1 = time.perf_counter() - t1
     return dict(value=spec.N * spec.D * iters / dt, unit="particle·dim updates/s", cores=threads, kind="oracle",
                 sample=f"first {iters} iterations of the same swarm (N={spec.N}, D={spec.D}), init excluded, "
-                       f"{dt:.1f} s")
+                       f"{dt:.1f} s",
+                single_core=dict(value=n1 * spec.D * it1 / dt1, cores=1,
+                                 sample=f"N={n1}, D={spec.D}, {it1} iterations, {dt1:.1f} s"))
 
 
 def timed_events(torch, stream, fn):

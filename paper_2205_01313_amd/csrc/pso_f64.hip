@@ -13,6 +13,7 @@
 // atomic minimum: every workgroup writes its (order bits, index) minimum of
 // the improved particles into its own slot, and the last workgroup to arrive
 // reduces the slots (lowest index among equal fitness).
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -42,8 +43,9 @@ Layout64 layout64_of(uint64_t N, int D)
     L.ctrl = o;     o += al256(sizeof(Ctrl64));
     L.gpos = o;     o += al256(sizeof(double) * D);
     L.shift = o;    o += al256(sizeof(double) * D);
-    L.slot_ord = o; o += al256(sizeof(unsigned long long) * L.nblocks);
-    L.slot_idx = o; o += al256(sizeof(uint32_t) * L.nblocks);
+    L.slot_ord = o; o += al256(sizeof(unsigned long long) * 2 * L.nblocks);
+    L.slot_idx = o; o += al256(sizeof(uint32_t) * 2 * L.nblocks);
+    L.cand_pos = o; o += al256(sizeof(double) * 2 * L.nblocks * (size_t)D);
     L.pf = o;       o += al256(sizeof(double) * L.Np);
     L.x = o;        o += al256(sizeof(double) * L.Np * (size_t)D);
     L.v = o;        o += al256(sizeof(double) * L.Np * (size_t)D);
@@ -61,6 +63,7 @@ Swarm64Args bind64(void *base, const Layout64 &L, uint64_t N, int D)
     a.shift = reinterpret_cast<const double *>(b + L.shift);
     a.slot_ord = reinterpret_cast<unsigned long long *>(b + L.slot_ord);
     a.slot_idx = reinterpret_cast<uint32_t *>(b + L.slot_idx);
+    a.cand_pos = reinterpret_cast<double *>(b + L.cand_pos);
     a.pf = reinterpret_cast<double *>(b + L.pf);
     a.x = reinterpret_cast<double *>(b + L.x);
     a.v = reinterpret_cast<double *>(b + L.v);
@@ -78,6 +81,13 @@ __device__ __forceinline__ unsigned long long ord64(double f)
     if (f == 0.0) f = 0.0;
     const unsigned long long b = (unsigned long long)__double_as_longlong(f);
     return (b & 0x8000000000000000ull) ? ~b : (b | 0x8000000000000000ull);
+}
+
+// Inverse of ord64 (for non-NaN values; -0 comes back as +0).
+__device__ __forceinline__ double ord64_value(unsigned long long o)
+{
+    const unsigned long long b = (o & 0x8000000000000000ull) ? (o & 0x7FFFFFFFFFFFFFFFull) : ~o;
+    return __longlong_as_double((long long)b);
 }
 
 __device__ __forceinline__ double clampd(double v, double lo, double hi)
@@ -368,6 +378,119 @@ __global__ void __launch_bounds__(LANES) k_block_run64(Swarm64Args a, long long 
     }
 }
 
+// ---------------------------------------------------------------------------
+// Persistent gang (synchronous): the launch's G co-resident workgroups each
+// own a contiguous slice of particles and run T iterations, meeting once per
+// iteration.  Workgroup b posts its lexicographic minimum of the improved
+// particles and, if it has one, that particle's position into the slots of
+// the iteration's parity, then arrives; once all G arrivals of the iteration
+// are in, every workgroup reduces the same G slots the same way, so all agree
+// on the gbest and on the stop rule, and read the winner's position from its
+// staged copy (its owner may already be overwriting x in the next
+// iteration; the slots of that iteration have the other parity).  The
+// arrival count is monotonic (G per iteration); every wait is bounded by the
+// wall clock and sets an error bit if it gives up.
+// ---------------------------------------------------------------------------
+constexpr unsigned long long GANG64_WAIT_TICKS = 2000000000ull; // 20 s of the 100 MHz wall clock
+
+template <int FIT>
+__global__ void __launch_bounds__(BLOCK64) k_gang64(Swarm64Args a, long long T, uint32_t per_wg)
+{
+    __shared__ unsigned long long s_k[BLOCK64 / 64];
+    __shared__ uint32_t s_i[BLOCK64 / 64];
+    __shared__ int s_fail;
+    extern __shared__ double s_dyn64[]; // gbest position (D), shift (D)
+    Ctrl64 *c = a.ctrl;
+    const int D = a.D;
+    const uint32_t G = gridDim.x, b = blockIdx.x;
+    double *s_g = s_dyn64, *s_shift = s_dyn64 + D;
+    for (int d = threadIdx.x; d < D; d += BLOCK64) {
+        s_g[d] = a.gpos[d];
+        s_shift[d] = a.shift[d];
+    }
+    unsigned long long gk = c->gord;
+    uint32_t gi = c->gidx;
+    long long giter = c->giter, t = c->t;
+    bool stop = c->stop != 0;
+    const double tol = c->tol, fstar = c->fstar;
+    const uint32_t i_lo = b * per_wg, i_hi = min(a.N, i_lo + per_wg);
+    if (threadIdx.x == 0) s_fail = 0;
+    __syncthreads();
+    for (long long it = 0; it < T && !stop; ++it) {
+        const uint32_t t1 = (uint32_t)(t + 1);
+        const int par = (int)(it & 1);
+        unsigned long long k = ~0ull;
+        uint32_t ki = NO_IDX;
+        for (uint32_t i = i_lo + threadIdx.x; i < i_hi; i += BLOCK64) {
+            const unsigned long long o = iterate_particle64<FIT>(a, i, t1, s_g, s_shift);
+            if (o < gk || (o == gk && i < gi)) lexmin(k, ki, o, i);
+        }
+        wg_lexmin(k, ki, s_k, s_i); // every lane's stores precede it
+        double *mine = a.cand_pos + ((size_t)par * G + b) * D;
+        if (ki != NO_IDX)
+            for (int d = threadIdx.x; d < D; d += BLOCK64) mine[d] = a.x[(size_t)d * a.Np + ki];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            a.slot_ord[par * G + b] = k;
+            a.slot_idx[par * G + b] = ki;
+            __threadfence(); // release the slot and the staged position
+            atomicAdd(&c->gang_arrive, 1ull);
+            const unsigned long long target = (unsigned long long)G * (unsigned long long)(it + 1);
+            const unsigned long long w0 = wall_clock64();
+            while (__hip_atomic_load(&c->gang_arrive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                __builtin_amdgcn_s_sleep(1);
+                if (wall_clock64() - w0 > GANG64_WAIT_TICKS) {
+                    atomicOr(&c->err, 1u);
+                    s_fail = 1;
+                    break;
+                }
+            }
+            __threadfence(); // acquire every slot and staged position
+        }
+        __syncthreads();
+        if (s_fail) break; // uniform
+        // every workgroup reduces the same slots
+        unsigned long long rk = ~0ull;
+        uint32_t ri = NO_IDX, rb = NO_IDX;
+        for (uint32_t w = threadIdx.x; w < G; w += BLOCK64) {
+            const unsigned long long sk =
+                __hip_atomic_load(&a.slot_ord[par * G + w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t si = __hip_atomic_load(&a.slot_idx[par * G + w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (sk < rk || (sk == rk && si < ri)) {
+                rk = sk;
+                ri = si;
+                rb = w;
+            }
+        }
+        // carry the owning workgroup along with the index (indices are unique)
+        wg_lexmin(rk, ri, s_k, s_i);
+        if (ri != NO_IDX) {
+            rb = ri / per_wg;
+            const double *src = a.cand_pos + ((size_t)par * G + rb) * D;
+            for (int d = threadIdx.x; d < D; d += BLOCK64)
+                s_g[d] = __hip_atomic_load(&src[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            gk = rk;
+            gi = ri;
+            giter = t1;
+        }
+        t = t1;
+        // every workgroup holds the same key, so all take the same decision
+        // (the winner's pf may already be changing in its next iteration)
+        stop = tol > 0.0 && fabs(ord64_value(gk) - fstar) < tol;
+        __syncthreads();
+    }
+    if (b == 0) {
+        for (int d = threadIdx.x; d < D; d += BLOCK64) a.gpos[d] = s_g[d];
+        if (threadIdx.x == 0) {
+            c->gord = gk;
+            c->gidx = gi;
+            c->giter = giter;
+            c->t = t;
+            c->stop = stop ? 1u : 0u;
+        }
+    }
+}
+
 __global__ void k_arm64(Swarm64Args a, double tol, double fstar)
 {
     if (threadIdx.x != 0) return;
@@ -408,6 +531,53 @@ static void block64_f(const Swarm64Args &a, long long T, hipStream_t s)
         hipLaunchKernelGGL((k_block_run64<FIT, 256>), dim3(1), dim3(256), lds, s, a, T);
     else
         hipLaunchKernelGGL((k_block_run64<FIT, 1024>), dim3(1), dim3(1024), lds, s, a, T);
+}
+
+// Particles per lane of the gang kernel: fewer, fuller workgroups make the
+// per-iteration meeting cheaper (measured, Cubic 1D, us per iteration at
+// 1/2/4/8 particles per lane: N = 4096: 5.0/4.9/5.9/8.3; 16384: 8.2/6.7/6.7/
+// 8.4; 65536: 20.2/12.8/10.1/10.2; 131072: 40.1/21.1/14.0/12.4).
+// PSO64_GANG_PPL overrides it.
+static int gang_ppl(uint64_t N)
+{
+    if (const char *env = getenv("PSO64_GANG_PPL")) {
+        const int v = atoi(env);
+        if (v >= 1 && v <= 64) return v;
+    }
+    return N <= 4096 ? 2 : N <= 65536 ? 4 : 8;
+}
+
+template <int FIT>
+static hipError_t gang64_f(const Swarm64Args &a, long long T, hipStream_t s, bool *launched)
+{
+    const size_t lds = 2 * sizeof(double) * a.D;
+    int per_cu = 0, dev = 0, cus = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gang64<FIT>, BLOCK64, lds);
+    if (e != hipSuccess) return e;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+    const uint64_t cap = (uint64_t)std::max(1, per_cu * cus * 3 / 4); // co-resident with margin
+    uint64_t per_wg = BLOCK64 * (uint64_t)gang_ppl(a.N);              // particles per workgroup
+    const uint64_t G = ((uint64_t)a.N + per_wg - 1) / per_wg;
+    if (G > cap) {
+        *launched = false;
+        return hipSuccess;
+    }
+    hipLaunchKernelGGL(k_gang64<FIT>, dim3((unsigned)G), dim3(BLOCK64), lds, s, a, T, (uint32_t)per_wg);
+    *launched = true;
+    return hipGetLastError();
+}
+
+hipError_t launch64_gang(int fitness, const Swarm64Args &a, long long T, hipStream_t stream, bool *launched)
+{
+    switch (fitness) {
+    case F_SPHERE: return gang64_f<F_SPHERE>(a, T, stream, launched);
+    case F_RASTRIGIN: return gang64_f<F_RASTRIGIN>(a, T, stream, launched);
+    case F_ROSENBROCK: return gang64_f<F_ROSENBROCK>(a, T, stream, launched);
+    case F_ACKLEY: return gang64_f<F_ACKLEY>(a, T, stream, launched);
+    case F_CUBIC: return gang64_f<F_CUBIC>(a, T, stream, launched);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch64_init(int fitness, const Swarm64Args &a, hipStream_t stream)
@@ -457,13 +627,16 @@ namespace {
         if (e_ != hipSuccess) return pso_internal_fail(PSO_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));      \
     } while (0)
 
-// Swarms up to this many particle-dimensions run in one workgroup (one
-// launch for the whole run); PSO64_BLOCK_MAX_ND in the environment
-// overrides it (tests of both paths).
-// (Measured, Cubic 1D: one workgroup 1.5 / 3.1 / 5.9 / 9.7 us per iteration
-// at N = 256 / 1024 / 4096 / 8192 against 5.3 / 5.6 / 6.3 / 6.7 us for a
-// grid launch per iteration.)
-constexpr uint64_t BLOCK64_MAX_ND = 4096;
+// Paths of pso64_run.  Up to BLOCK64_MAX_ND particle-dimensions the whole
+// run is one workgroup; for D <= GANG64_MAX_D the persistent gang; else one
+// grid launch per iteration.  Measured (Cubic 1D, us per iteration, one
+// workgroup / gang / grid): N = 1024: 3.1 / 4.0 / 5.9; 2048: 3.9 / 4.2 / 6.0;
+// 4096: 5.9 / 4.9 / 6.3; 16384: 17.1 / 6.7 / 7.4; 131072: - / 12.4 / 15.7;
+// at D = 120 the gang and the grid are within 2 % (N = 8192), so the grid
+// runs.  PSO64_BLOCK_MAX_ND and PSO64_PATH (block, gang, grid) override the
+// choice (tests of every path).
+constexpr uint64_t BLOCK64_MAX_ND = 2048;
+constexpr int GANG64_MAX_D = 8;
 
 uint64_t block64_max_nd()
 {
@@ -589,9 +762,17 @@ int pso64_run(pso_swarm64 *s, int64_t max_iter, double tol, double f_star, doubl
     HIP64_TRY(hipMemcpy(&c, s->a.ctrl, sizeof c, hipMemcpyDeviceToHost));
     const long long t0 = c.t;
     HIP64_TRY(pso::launch64_arm(s->a, tol, f_star, s->stream));
-    if (s->N * (uint64_t)s->D <= block64_max_nd()) {
+    const uint64_t nd = s->N * (uint64_t)s->D;
+    const char *path = getenv("PSO64_PATH"); // tests of every path: block, gang, grid
+    bool done_gang = false;
+    if (path ? !strcmp(path, "block") : nd <= block64_max_nd()) {
         HIP64_TRY(pso::launch64_block_run(s->fitness, s->a, max_iter, s->stream));
-    } else {
+        done_gang = true;
+    } else if (path ? !strcmp(path, "gang") : s->D <= GANG64_MAX_D) {
+        HIP64_TRY(hipMemsetAsync(&s->a.ctrl->gang_arrive, 0, sizeof(unsigned long long), s->stream));
+        HIP64_TRY(pso::launch64_gang(s->fitness, s->a, max_iter, s->stream, &done_gang));
+    }
+    if (!done_gang) {
         // chunks of launches; every launch returns at once after the stop rule holds
         for (int64_t done = 0; done < max_iter;) {
             const int64_t n = std::min<int64_t>(256, max_iter - done);
@@ -604,6 +785,7 @@ int pso64_run(pso_swarm64 *s, int64_t max_iter, double tol, double f_star, doubl
     }
     HIP64_TRY(hipStreamSynchronize(s->stream));
     HIP64_TRY(hipMemcpy(&c, s->a.ctrl, sizeof c, hipMemcpyDeviceToHost));
+    if (c.err) return pso_internal_fail(PSO_EDEVICE, "a gang wait gave up (device error bits 0x%x)", c.err);
     if (gbest_value) HIP64_TRY(hipMemcpy(gbest_value, s->a.pf + c.gidx, sizeof(double), hipMemcpyDeviceToHost));
     if (gbest_pos) HIP64_TRY(hipMemcpy(gbest_pos, s->a.gpos, sizeof(double) * s->D, hipMemcpyDeviceToHost));
     if (gbest_iter) *gbest_iter = c.giter;

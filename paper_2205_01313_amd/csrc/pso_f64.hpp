@@ -17,9 +17,10 @@ struct alignas(256) Ctrl64 {
     long long giter;         // iteration of the last gbest change
     long long t;             // iterations completed
     uint32_t stop;           // stop rule met
-    uint32_t pad;
+    uint32_t err;            // a bounded wait of the gang kernel gave up
     double tol, fstar;       // stop rule |gbest - fstar| < tol (tol <= 0: off)
-    unsigned char pad2[192];
+    unsigned long long gang_arrive; // gang kernel: workgroup arrivals (monotonic within a launch)
+    unsigned char pad2[184];
 };
 static_assert(sizeof(Ctrl64) == 256, "Ctrl64 layout");
 
@@ -27,8 +28,9 @@ struct Swarm64Args {
     double *x, *v, *p, *pf;        // D*Np, D*Np, D*Np, Np; element (d, i) at d*Np + i
     double *gpos;                  // D
     const double *shift;           // D
-    unsigned long long *slot_ord;  // one per grid workgroup
-    uint32_t *slot_idx;            // one per grid workgroup
+    unsigned long long *slot_ord;  // one per grid workgroup (gang kernel: two per workgroup, by parity)
+    uint32_t *slot_idx;            // as slot_ord
+    double *cand_pos;              // gang kernel: [parity][workgroup][D] staged candidate positions
     Ctrl64 *ctrl;
     uint32_t N, Np;
     int32_t D;
@@ -37,7 +39,7 @@ struct Swarm64Args {
 };
 
 struct Layout64 {
-    size_t ctrl, gpos, shift, slot_ord, slot_idx, pf, x, v, p, total;
+    size_t ctrl, gpos, shift, slot_ord, slot_idx, cand_pos, pf, x, v, p, total;
     uint64_t Np;
     uint32_t nblocks;
 };
@@ -51,5 +53,10 @@ hipError_t launch64_init(int fitness, const Swarm64Args &a, hipStream_t stream);
 hipError_t launch64_step(int fitness, const Swarm64Args &a, hipStream_t stream);
 hipError_t launch64_block_run(int fitness, const Swarm64Args &a, long long T, hipStream_t stream);
 hipError_t launch64_arm(const Swarm64Args &a, double tol, double fstar, hipStream_t stream);
+// Up to T iterations by a persistent gang of co-resident workgroups that meet
+// once per iteration (bit-identical to T grid steps); ctrl->gang_arrive must
+// be zero.  *launched = false if the swarm needs more workgroups than can be
+// co-resident (nothing is enqueued then).
+hipError_t launch64_gang(int fitness, const Swarm64Args &a, long long T, hipStream_t stream, bool *launched);
 
 } // namespace pso

@@ -2,8 +2,9 @@
 
 Sphere, Rosenbrock and Cubic use only +, -, * and / in double, so the state
 after a run (x, v, pbest position and fitness, gbest index and iteration) is
-compared bit for bit, on the one-workgroup path (N*D <= 4096, 256 or 1024
-lanes), the grid path and step by step.  Rastrigin and Ackley call cos and exp, whose device
+compared bit for bit on every path: one workgroup (256 or 1024 lanes), the
+persistent gang of workgroups that meet once per iteration, one grid launch
+per iteration, and step by step.  Rastrigin and Ackley call cos and exp, whose device
 and host implementations may differ in the last bit: after one iteration the
 state is compared within 1e-12 relative, and after a longer run the
 invariants of the method are checked (bounds, velocity limit, pbest fitness
@@ -52,6 +53,38 @@ def test_exact_functions_bit_for_bit(fit, N, D, how):
             g.step(T)
         st = g.state()
     assert st["t"] == T and st["gbest_idx"] == o["gbest_idx"]
+    assert_equal64(st, o)
+
+
+@pytest.mark.parametrize("path", ["block", "gang", "grid"])
+@pytest.mark.parametrize("fit,N,D", [("cubic", 2049, 1), ("rosenbrock", 1500, 6), ("sphere", 700, 3)])
+def test_every_run_path_bit_for_bit(monkeypatch, path, fit, N, D):
+    monkeypatch.setenv("PSO64_PATH", path)
+    T = 60
+    spec = wl.SwarmSpec(fit, N, D, T, seed=7 * N + D, shift_amplitude=1.5)
+    announce(f"f64 path={path} {fit} N={N} D={D}")
+    o = oracle_swarm(spec, 8).run_f64(T)
+    with gpu64(spec) as g:
+        r1 = g.run(T // 3)
+        r2 = g.run(T - T // 3)
+        st = g.state()
+    assert r1["iters"] + r2["iters"] == T and st["t"] == T
+    assert r2["gbest_fit"] == o["gbest_fit"] and r2["gbest_iter"] == o["giter"]
+    assert np.array_equal(r2["gbest_pos"].view(np.uint64), o["gpos"].view(np.uint64))
+    assert_equal64(st, o)
+
+
+@pytest.mark.parametrize("path", ["block", "gang", "grid"])
+def test_stop_rule_on_every_path(monkeypatch, path):
+    monkeypatch.setenv("PSO64_PATH", path)
+    spec = wl.SwarmSpec("sphere", 3000, 3, 500, seed=4)
+    announce(f"f64 stop rule path={path}")
+    o = oracle_swarm(spec, 8).run_f64(500, tol=1e-2, f_star=0.0)
+    assert o["iters"] < 500
+    with gpu64(spec) as g:
+        r = g.run(500, tol=1e-2, f_star=0.0)
+        st = g.state()
+    assert r["iters"] == o["iters"] and r["gbest_fit"] == o["gbest_fit"]
     assert_equal64(st, o)
 
 
