@@ -261,13 +261,12 @@ int pso_reset(pso_swarm *s)
 
 namespace {
 
-// One persistent launch of T iterations (iteration counts cleared first).
+// Persistent launches for T iterations (each clears its iteration counts).
 int persistent_launch(pso_swarm *s, int64_t T)
 {
     while (T > 0) {
         const uint32_t n = (uint32_t)std::min<int64_t>(T, int64_t(1) << 30);
         const uint32_t lead = (uint32_t)std::min<int64_t>(s->max_lead, int64_t(0xFFFFFFFF));
-        HIP_TRY(hipMemsetAsync(s->args.prog, 0, sizeof(uint32_t) * pso::PERSIST_MAX_GRID, s->stream));
         HIP_TRY(pso::launch_persistent(s->fitness, s->args, n, lead, s->stream));
         T -= n;
     }

@@ -491,6 +491,19 @@ __global__ void __launch_bounds__(BLOCK64) k_gang64(Swarm64Args a, long long T, 
     }
 }
 
+// Clears the control block (a kernel, not a memset: the call may be
+// captured into a graph).
+__global__ void k_reset64(Swarm64Args a)
+{
+    if (threadIdx.x == 0) *a.ctrl = Ctrl64{};
+}
+
+hipError_t launch64_reset(const Swarm64Args &a, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_reset64, dim3(1), dim3(64), 0, stream, a);
+    return hipGetLastError();
+}
+
 __global__ void k_arm64(Swarm64Args a, double tol, double fstar)
 {
     if (threadIdx.x != 0) return;
@@ -655,7 +668,7 @@ void free64(pso_swarm64 *s)
 
 int reinit64(pso_swarm64 *s)
 {
-    HIP64_TRY(hipMemsetAsync(s->a.ctrl, 0, sizeof(pso::Ctrl64), s->stream));
+    HIP64_TRY(pso::launch64_reset(s->a, s->stream));
     HIP64_TRY(pso::launch64_init(s->fitness, s->a, s->stream));
     return PSO_OK;
 }

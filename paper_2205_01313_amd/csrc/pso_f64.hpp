@@ -49,6 +49,7 @@ Swarm64Args bind64(void *base, const Layout64 &L, uint64_t N, int D);
 
 // Step 1 (grid), one iteration (grid), or up to T iterations in one
 // workgroup (block).  All honour and update the control block's stop rule.
+hipError_t launch64_reset(const Swarm64Args &a, hipStream_t stream);
 hipError_t launch64_init(int fitness, const Swarm64Args &a, hipStream_t stream);
 hipError_t launch64_step(int fitness, const Swarm64Args &a, hipStream_t stream);
 hipError_t launch64_block_run(int fitness, const Swarm64Args &a, long long T, hipStream_t stream);

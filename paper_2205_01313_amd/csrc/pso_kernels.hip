@@ -904,9 +904,19 @@ static hipError_t launch_persist_f(const SwarmArgs &a, uint32_t T, uint32_t max_
     }
 }
 
+__global__ void k_zero_u32(uint32_t *p, uint32_t n)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
 hipError_t launch_persistent(int fitness, const SwarmArgs &a, uint32_t T, uint32_t max_lead, hipStream_t stream)
 {
     if (!a.ctrl || !a.prog || T == 0) return T == 0 ? hipSuccess : hipErrorInvalidValue;
+    // the workgroups' iteration counts start at zero (a kernel, not a memset:
+    // the call may be captured into a graph)
+    hipLaunchKernelGGL(k_zero_u32, dim3((PERSIST_MAX_GRID + 255) / 256), dim3(256), 0, stream, a.prog,
+                       PERSIST_MAX_GRID);
     switch (fitness) {
     case F_SPHERE: return launch_persist_f<F_SPHERE>(a, T, max_lead, stream);
     case F_RASTRIGIN: return launch_persist_f<F_RASTRIGIN>(a, T, max_lead, stream);

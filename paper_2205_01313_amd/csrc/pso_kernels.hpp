@@ -107,8 +107,7 @@ hipError_t launch_clear_pending(const SwarmArgs &a, hipStream_t stream);
 // Fully asynchronous persistent run: T iterations in one launch, no barrier
 // between iterations; a workgroup runs at most max_lead iterations ahead of
 // the slowest one (>= T: unbounded).  Needs the control block (launch_arm
-// first for the stop rule) and the iteration counts a.prog zeroed for the
-// launch's workgroups (at most PERSIST_MAX_GRID).
+// first for the stop rule); clears the workgroups' iteration counts itself.
 hipError_t launch_persistent(int fitness, const SwarmArgs &a, uint32_t T, uint32_t max_lead, hipStream_t stream);
 
 } // namespace pso
