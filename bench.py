@@ -325,9 +325,10 @@ def main():
     ap.add_argument("--legs", default="main,async,small,deep,latency,paper,batched,serving",
                     help="comma list of legs beyond the main line: async, small, deep, latency, paper, batched, "
                          "serving")
-    ap.add_argument("--pmc-probe", action="store_true",
-                    help="for rocprofv3 counter runs: init + 20 step launches, then a 256 MiB torch copy "
-                         "(calibration kernel of known size); prints nothing else")
+    ap.add_argument("--pmc-probe", nargs="?", const="step", choices=["step", "batch"],
+                    help="for rocprofv3 counter runs: 'step' (default) = init + 20 step launches, then a 256 MiB "
+                         "torch copy (calibration kernel of known size); 'batch' = one untimed and one timed launch "
+                         "of the 4096-swarm batch (128 lanes, full grid, 2^17 per part); prints one line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the path is single-GPU (--gpus {args.gpus} is not supported)",
@@ -353,6 +354,18 @@ def main():
     sw = pso.Swarm(spec.fitness, spec.N, spec.D, spec.box, spec.w, spec.c1, spec.c2, spec.vmax, spec.seed,
                    variant=variant, workspace=ws, stream=stream)
 
+    if args.pmc_probe == "batch":
+        sw.close()
+        specs = wl.batch_specs()
+        with pso.Batch(specs, stream=stream) as b:
+            b.set_shape(128, 0, 1 << 17)
+            b.launch()
+            torch.cuda.synchronize()
+            ms = timed_events(torch, stream, b.launch)
+            res = b.results(positions=False)
+        print(json.dumps({"pmc_probe": "batch", "ms": ms,
+                          "updates": int(sum(sp.N * sp.D * r["iters"] for sp, r in zip(specs, res)))}), flush=True)
+        return
     if args.pmc_probe:
         sw.reset()
         for _ in range(20):
