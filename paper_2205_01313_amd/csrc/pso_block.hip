@@ -191,7 +191,7 @@ __device__ void block_init(const SwarmArgs &a, const Part &P, const float *s_shi
 // alternates between iterations: slot (t & 1) collects iteration t's
 // minimum, and the other slot is cleared for iteration t+1.  hist (may be
 // null) receives each iteration's gbest key.
-template <int FIT, int LANES>
+template <int FIT, int LANES, bool PF>
 __device__ void block_iterate(const SwarmArgs &a, const Part &P, long long T, float tol, float fstar,
                               const float *s_shift, float *s_g, Scratch *sc, unsigned long long *hist, SwarmLoop &L)
 {
@@ -203,7 +203,7 @@ __device__ void block_iterate(const SwarmArgs &a, const Part &P, long long T, fl
         unsigned long long key = NO_KEY;
         for (uint32_t q = P.q_lo + threadIdx.x; q < P.q_hi; q += LANES) {
             uint32_t n = 0;
-            const unsigned long long k = iterate_quad<FIT, 0, 1, PSO_SWARM_POLICY>(a, D, q, t, s_g, s_shift, &n);
+            const unsigned long long k = iterate_quad<FIT, 0, 1, PSO_SWARM_POLICY, PF>(a, D, q, t, s_g, s_shift, &n);
             key = k < key ? k : key;
             n_imp += n;
         }
@@ -252,7 +252,7 @@ __global__ void __launch_bounds__(RUN_LANES) k_block_run(SwarmArgs a, long long 
     L.stop = c->stop != 0u;
     const float tol = c->tol, fstar = c->fstar;
     __syncthreads();
-    block_iterate<FIT, RUN_LANES>(a, whole_swarm(a), T, tol, fstar, s_shift, s_g, &sc, a.hist, L);
+    block_iterate<FIT, RUN_LANES, false>(a, whole_swarm(a), T, tol, fstar, s_shift, s_g, &sc, a.hist, L);
     if (L.improved) atomicAdd(&c->improved, (unsigned long long)L.improved);
     for (int d = threadIdx.x; d < D; d += RUN_LANES) a.gpos[d] = s_g[d];
     if (threadIdx.x == 0) {
@@ -348,7 +348,9 @@ __device__ void batch_part(const BatchItem &it, uint32_t part, uint32_t fixed_it
     iters = iters < 1 ? 1 : (iters > iter_cap ? iter_cap : iters);
     if (fixed_iters > 0) iters = fixed_iters;
     const unsigned long long c0 = wall_clock64();
-    block_iterate<FIT, LANES>(a, P, left < iters ? left : iters, it.tol, it.fstar, s_shift, s_g, sc, nullptr, L);
+    // prefetch pays in the batch: many short rows need more loads in flight
+    block_iterate<FIT, LANES, true>(a, P, left < iters ? left : iters, it.tol, it.fstar, s_shift, s_g, sc, nullptr,
+                                    L);
     const unsigned long long ticks = wall_clock64() - c0;
     if (part == 0) {
         for (int d = threadIdx.x; d < D; d += LANES) {

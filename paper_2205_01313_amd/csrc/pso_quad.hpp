@@ -105,12 +105,12 @@ __device__ __forceinline__ unsigned long long init_quad(const SwarmArgs &a, int 
 #ifndef PSO_PBEST_GROUP
 #define PSO_PBEST_GROUP 4
 #endif
-// Software prefetch of the next dimension pair: pays where the fitness is
-// heavy enough to leave memory idle between pairs (Ackley: 196 -> 173 us
-// per iteration at N = 2^18, D = 128); slightly slower for the others.
-#ifndef PSO_PREFETCH
-#define PSO_PREFETCH (FIT == F_ACKLEY)
-#endif
+// Software prefetch of the next dimension pair (PF): pays where the fitness
+// is heavy enough to leave memory idle between pairs (grid step, Ackley:
+// 196 -> 173 us per iteration at N = 2^18, D = 128; slightly slower for the
+// other functions there) and in the batched kernel, whose short per-swarm
+// rows need the extra loads in flight (4096-swarm batch: 749 -> 670 ms; a
+// one-workgroup run of D = 2 is slower with it: 2.1 -> 2.6 us per iteration).
 // Eq. 1 and Eq. 2 for one dimension row of the four particles (x, v, p as
 // loaded; p replaced by x where the pbest position is pending) and the stores
 // of x, v and (for a dirty group) p.  Returns the new positions.
@@ -149,7 +149,7 @@ __device__ __forceinline__ bool group_dirty(uint32_t pend)
     return ((dirty >> ((threadIdx.x & 63) & ~(G - 1))) & ((1ull << G) - 1)) != 0;
 }
 
-template <int FIT, int DC, int UNROLL, int POL>
+template <int FIT, int DC, int UNROLL, int POL, bool PF = (FIT == F_ACKLEY)>
 __device__ __forceinline__ unsigned long long iterate_quad(const SwarmArgs &a, int D, uint32_t q, uint32_t t,
                                                            const float *s_g, const float *s_shift,
                                                            uint32_t *n_improved = nullptr)
@@ -161,7 +161,7 @@ __device__ __forceinline__ unsigned long long iterate_quad(const SwarmArgs &a, i
     const bool line_dirty = group_dirty(pend);
     constexpr bool KX = (POL & KEEP_X) != 0, KV = (POL & KEEP_V) != 0, KP = (POL & KEEP_P) != 0;
     Fitness<FIT> fit[4];
-    if constexpr (PSO_PREFETCH) {
+    if constexpr (PF) {
         // Software pipeline over dimension pairs: the next pair's x, v, p are
         // loaded before this pair's stores (the compiler may not hoist them
         // past stores to the same arrays), so two pairs' loads are in flight.
