@@ -254,7 +254,9 @@ int pso_batch_create(const pso_desc *descs, int64_t count, void *hip_stream, pso
 
 /* Enqueues the whole batch -- Step 1 and every iteration of every swarm --
  * as one persistent launch; returns without synchronising.  May be called
- * again to rerun the batch from scratch. */
+ * again to rerun the batch from scratch.  The launch is captured into a HIP
+ * graph on first use (and again after a shape change) and replayed from
+ * then on; PSO_BATCH_GRAPH=0 in the environment launches it directly. */
 int pso_batch_launch(pso_batch *b);
 
 /* Synchronises and writes results[i] for every swarm i (results[i].gbest_pos

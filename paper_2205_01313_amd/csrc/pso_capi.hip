@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -487,14 +488,25 @@ struct pso_batch {
     uint64_t signature = 0;
     hipStream_t stream = nullptr;
     bool owns_stream = false;
+    hipGraph_t graph = nullptr;         // the captured launch of the current shape
+    hipGraphExec_t graph_exec = nullptr;
 };
 
 namespace {
+
+void drop_graph(pso_batch *b)
+{
+    if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->graph_exec = nullptr;
+    b->graph = nullptr;
+}
 
 void batch_free(pso_batch *b)
 {
     if (!b) return;
     if (b->stream) (void)hipStreamSynchronize(b->stream);
+    drop_graph(b);
     if (b->slab) (void)hipFree(b->slab);
     if (b->d_items) (void)hipFree(b->d_items);
     if (b->d_entries) (void)hipFree(b->d_entries);
@@ -563,6 +575,7 @@ int batch_configure(pso_batch *b, const pso::BatchShape &sh)
     b->n_entries = (uint32_t)n_entries;
     b->grid = (int)std::min<uint64_t>(n_entries, (uint64_t)grid);
     b->shape = sh;
+    drop_graph(b); // the captured launch had the old grid and lanes
     return PSO_OK;
 }
 
@@ -703,7 +716,28 @@ int pso_batch_create(const pso_desc *descs, int64_t count, void *hip_stream, pso
 int pso_batch_launch(pso_batch *b)
 {
     if (!b) return fail(PSO_EINVAL, "batch is NULL");
-    return batch_launch_iters(b, (long long)1 << 62, true);
+    const char *env = getenv("PSO_BATCH_GRAPH");
+    if (env && !strcmp(env, "0")) return batch_launch_iters(b, (long long)1 << 62, true);
+    // the whole launch (reset kernel, counter kernel, persistent kernel; no
+    // memset) is captured once per shape and replayed as one graph
+    if (!b->graph_exec) {
+        HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+        int rc = batch_launch_iters(b, (long long)1 << 62, true);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(b->stream, &g);
+        if (rc) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return fail(PSO_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+        b->graph = g;
+        if (hipGraphInstantiate(&b->graph_exec, b->graph, nullptr, nullptr, 0) != hipSuccess) {
+            drop_graph(b);
+            return fail(PSO_EDEVICE, "graph instantiation failed");
+        }
+    }
+    HIP_TRY(hipGraphLaunch(b->graph_exec, b->stream));
+    return PSO_OK;
 }
 
 int pso_batch_get_shape(pso_batch *b, pso_batch_shape *shape)

@@ -132,3 +132,32 @@ def test_every_shape_and_the_autotuner_give_the_same_results():
     for k in (0, len(specs) - 1):
         o = oracle_swarm(specs[k], 8).run_f32(specs[k].T)
         assert ref[k]["gbest_fit"] == o["gbest_fit"] and ref[k]["gbest_iter"] == o["giter"]
+
+
+def test_graph_replays_equal_the_direct_launch(monkeypatch):
+    """pso_batch_launch captures the launch into a HIP graph once and replays
+    it: three replays, with other eager GPU work and synchronisations between
+    them, each give exactly the results of a direct (uncaptured) launch."""
+    import torch
+    specs = mixed_specs(60, 33)
+    specs.append(wl.SwarmSpec("rastrigin", 7000, 40, 25, seed=77, shift_amplitude=1.0))  # several parts
+    announce("batch graph replays")
+    monkeypatch.setenv("PSO_BATCH_GRAPH", "0")
+    with pso.Batch(specs) as b:
+        b.launch()
+        ref = b.results()
+    monkeypatch.delenv("PSO_BATCH_GRAPH")
+    other = wl.SwarmSpec("sphere", 5000, 6, 20, seed=3)
+    with pso.Batch(specs) as b:
+        for rep in range(3):
+            b.launch()
+            res = b.results()
+            for r, q in zip(res, ref):
+                assert r["gbest_fit"] == q["gbest_fit"] and r["gbest_iter"] == q["gbest_iter"], rep
+                assert r["iters"] == q["iters"] and np.array_equal(r["gbest_pos"], q["gbest_pos"]), rep
+            # unrelated eager work between replays
+            with gpu_swarm(other) as g:
+                g.run(other.T)
+            x = torch.ones(1 << 20, device="cuda")
+            torch.cuda.synchronize()
+            assert float(x.sum()) == float(1 << 20)
