@@ -107,7 +107,9 @@ int pso_set_shift(pso_swarm *s, const float *shift_host);
  * asynchronous variant's rule); a particle still draws Philox numbers with
  * its own iteration count, and bounded staleness (pso_set_max_lead) keeps
  * workgroups within a window of each other.  Its trajectory is not
- * deterministic; its gbest is always the minimum over the pbest fitness. */
+ * deterministic; its gbest is always the minimum over the pbest fitness, and
+ * its history entry for iteration t is the best key known when the first
+ * workgroup finished iteration t (non-increasing in t). */
 int pso_set_variant(pso_swarm *s, int variant);
 
 /* PSO_PERSISTENT: the most iterations a workgroup may run ahead of the

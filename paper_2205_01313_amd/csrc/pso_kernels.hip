@@ -609,6 +609,8 @@ __global__ void PSO_STEP_ATTR k_persist(SwarmArgs a, uint32_t T, uint32_t max_le
             if (m < thr && flag) atomicMax(reinterpret_cast<unsigned long long *>(&c->giter), (unsigned long long)t);
             __hip_atomic_store(&a.prog[blockIdx.x], k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const unsigned long long g = __hip_atomic_load(&c->gkey, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // history: the best key seen when a workgroup finished iteration t
+            atomicMin(&a.hist[t & (HIST_CAP - 1)], g);
             if (tol > 0.0f && __builtin_fabsf(key_fitness(g) - fstar) < tol)
                 __hip_atomic_store(&c->stop, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
@@ -626,8 +628,6 @@ __global__ void PSO_STEP_ATTR k_persist(SwarmArgs a, uint32_t T, uint32_t max_le
     if (threadIdx.x == 0) __threadfence();
     if (arrive_last(c, &flag) && threadIdx.x == 0) {
         const unsigned long long g = __hip_atomic_load(&c->gkey, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const long long tt = c->t;
-        a.hist[tt & (HIST_CAP - 1)] = g;
         c->gkey_prev = g;
         c->arrive = 0;
     }
@@ -904,19 +904,22 @@ static hipError_t launch_persist_f(const SwarmArgs &a, uint32_t T, uint32_t max_
     }
 }
 
-__global__ void k_zero_u32(uint32_t *p, uint32_t n)
+// Before a persistent run: the workgroups' iteration counts to zero, and the
+// history entries of the run's iterations (after the control block's t) to
+// "no key", so that each can take the minimum of what the workgroups saw.
+__global__ void k_persist_prepare(SwarmArgs a, uint32_t T)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0u;
+    if (i < PERSIST_MAX_GRID) a.prog[i] = 0u;
+    if (i < T && i < (uint32_t)HIST_CAP) a.hist[(a.ctrl->t + 1 + i) & (HIST_CAP - 1)] = NO_KEY;
 }
 
 hipError_t launch_persistent(int fitness, const SwarmArgs &a, uint32_t T, uint32_t max_lead, hipStream_t stream)
 {
     if (!a.ctrl || !a.prog || T == 0) return T == 0 ? hipSuccess : hipErrorInvalidValue;
-    // the workgroups' iteration counts start at zero (a kernel, not a memset:
-    // the call may be captured into a graph)
-    hipLaunchKernelGGL(k_zero_u32, dim3((PERSIST_MAX_GRID + 255) / 256), dim3(256), 0, stream, a.prog,
-                       PERSIST_MAX_GRID);
+    // a kernel, not a memset: the call may be captured into a graph
+    const uint32_t n = std::max<uint32_t>(PERSIST_MAX_GRID, (uint32_t)HIST_CAP);
+    hipLaunchKernelGGL(k_persist_prepare, dim3((n + 255) / 256), dim3(256), 0, stream, a, T);
     switch (fitness) {
     case F_SPHERE: return launch_persist_f<F_SPHERE>(a, T, max_lead, stream);
     case F_RASTRIGIN: return launch_persist_f<F_RASTRIGIN>(a, T, max_lead, stream);

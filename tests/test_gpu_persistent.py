@@ -33,12 +33,17 @@ def test_invariants_after_persistent_runs(fit, N, D, lead):
         check_invariants(spec, st, prev, osw)
         assert r["gbest_fit"] == oracle.key_value(st["gkey"])
         assert 0 <= r["gbest_iter"] <= 25
+        # the history: non-increasing, ending at the run's gbest
+        h = g.history(1, 25)
+        assert np.all(h[1:] <= h[:-1]) and h[-1] == st["gkey"]
         # a second run continues the iteration count; pso_step runs one
         r2 = g.run(10)
         g.step()
         st2 = g.state()
         assert r2["iters"] == 10 and st2["t"] == 36
         check_invariants(spec, st2, st, None)
+        h2 = g.history(1, 36)
+        assert np.all(h2[1:] <= h2[:-1]) and h2[-1] == st2["gkey"]
 
 
 def test_persistent_stop_rule():
