@@ -101,8 +101,11 @@ def timed_events(torch, stream, fn):
     return a.elapsed_time(b)
 
 
-def async_leg(pso, torch, spec, ws, stream):
-    """Asynchronous variant on the same swarm: updates/s over one solve."""
+def async_leg(pso, torch, wl, spec, ws, stream, seeds=32):
+    """Asynchronous variant on the same swarm: updates/s over one solve; and
+    the final-fitness distribution over 32 seeds of the synchronous,
+    asynchronous and persistent variants (quantiles 0, 10, 50, 90, 100)."""
+    import numpy as np
     sw = pso.Swarm(spec.fitness, spec.N, spec.D, spec.box, spec.w, spec.c1, spec.c2, spec.vmax, spec.seed,
                    variant=pso.PSO_ASYNC, workspace=ws, stream=stream)
 
@@ -114,8 +117,17 @@ def async_leg(pso, torch, spec, ws, stream):
     ms = timed_events(torch, stream, solve)
     best = sw.best()
     sw.close()
+    dist = {}
+    for name, var in (("sync", pso.PSO_SYNC), ("async", pso.PSO_ASYNC), ("persistent", pso.PSO_PERSISTENT)):
+        fs = []
+        for seed in range(seeds):
+            sp = wl.large_rastrigin(seed=seed)
+            with pso.Swarm(sp.fitness, sp.N, sp.D, sp.box, sp.w, sp.c1, sp.c2, sp.vmax, sp.seed, variant=var,
+                           workspace=ws, stream=stream) as g:
+                fs.append(float(g.run(sp.T)["gbest_fit"]))
+        dist[name] = [float(q) for q in np.percentile(fs, [0, 10, 50, 90, 100])]
     return dict(value=spec.N * spec.D * spec.T / (ms / 1e3), unit="particle·dim updates/s", ms_per_solve=ms,
-                gbest=float(best["gbest_fit"]))
+                gbest=float(best["gbest_fit"]), final_fitness_quantiles_32_seeds=dist)
 
 
 def small_leg(pso, torch, wl, stream):
@@ -455,7 +467,7 @@ def main():
     }
     legs = set(args.legs.split(","))
     if "async" in legs:
-        out["async"] = async_leg(pso, torch, spec, ws, stream)
+        out["async"] = async_leg(pso, torch, wl, spec, ws, stream)
     if "small" in legs:
         out["small"] = small_leg(pso, torch, wl, stream)
     if "deep" in legs:
