@@ -248,18 +248,28 @@ def paper_leg(pso):
 def batched_leg(pso, torch, wl, stream, subset=96):
     """4096 swarms (N log-uniform in [32, 8192], D in {2..64}, four fitness
     functions with shifts, 500 iterations) in one persistent launch, its
-    shape (lanes, workgroups, part size) picked by the autotuner; and a
+    shape (lanes, workgroups, part size, LDS staging) picked by the
+    autotuner, and the streamed kernel's time on the same batch; and a
     spread subset run both as a batch and as a plain loop of pso_run calls
     (one swarm after another, allocation outside the timed loop)."""
     specs = wl.batch_specs()
     with pso.Batch(specs, stream=stream) as b:
+        default_shape = b.shape
         t0 = time.perf_counter()
-        shape = b.autotune(probe_iters=8)
+        shape = b.autotune(probe_iters=16)
         tune_s = time.perf_counter() - t0
         b.launch()
         torch.cuda.synchronize()
         ms = timed_events(torch, stream, b.launch)
         res = b.results(positions=False)
+        # the streamed kernel on the same batch, for comparison
+        b.set_shape(128, 0, 1 << 17)
+        b.launch()
+        torch.cuda.synchronize()
+        ms_streamed = timed_events(torch, stream, b.launch)
+        res_streamed = b.results(positions=False)
+    same_streamed = all(a["gbest_fit"] == c["gbest_fit"] and a["iters"] == c["iters"]
+                        for a, c in zip(res, res_streamed))
     updates = sum(sp.N * sp.D * r["iters"] for sp, r in zip(specs, res))
     sub = specs[:: len(specs) // subset][:subset]
     with pso.Batch(sub, stream=stream) as b:
@@ -276,7 +286,9 @@ def batched_leg(pso, torch, wl, stream, subset=96):
         sw.close()
     same = all(a["gbest_fit"] == c["gbest_fit"] and (a["gbest_pos"] == c["gbest_pos"]).all() for a, c in zip(rb, rp))
     return dict(swarms=len(specs), iterations=500, ms=ms, value=updates / (ms / 1e3), unit="particle·dim updates/s",
-                autotuned_shape=shape, autotune_s=tune_s,
+                autotuned_shape=shape, autotune_s=tune_s, default_shape=default_shape,
+                streamed_ms=ms_streamed, streamed_shape=dict(lanes=128, grid=0, part_work=1 << 17, stage_kib=0),
+                streamed_equal_results=bool(same_streamed),
                 subset=len(sub), subset_batched_ms=ms_sub, subset_plain_loop_ms=ms_plain,
                 batched_vs_plain_speedup=ms_plain / ms_sub, equal_results=bool(same))
 
@@ -370,7 +382,7 @@ def main():
         sw.close()
         specs = wl.batch_specs()
         with pso.Batch(specs, stream=stream) as b:
-            b.set_shape(128, 0, 1 << 17)
+            b.set_shape(1024, 0, 0, stage_kib=158)
             b.launch()
             torch.cuda.synchronize()
             ms = timed_events(torch, stream, b.launch)

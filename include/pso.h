@@ -272,38 +272,53 @@ int pso_batch_destroy(pso_batch *b);
 int pso_batch_run(const pso_desc *descs, int64_t count, pso_result *results);
 
 /* Tiles and schedule of a batch's launches (they change the time, never the
- * results): lanes per workgroup (64, 128 or 256), co-resident workgroups
- * (grid; 0 = the device's co-resident capacity for that lane count), and the
- * particle-dimension updates per part and iteration at which a large swarm is
- * split over several workgroups (part_work >= 1).  A new batch takes the
- * shape pso_batch_autotune chose earlier in this process for the same
- * swarm sizes and iteration limits on the same device, else 256 lanes, the
- * full capacity and 2^17 updates per part. */
+ * results).  stage_kib = 0 streams each swarm's state from device memory
+ * every iteration: lanes per workgroup (64, 128 or 256), co-resident
+ * workgroups (grid; 0 = the device's co-resident capacity for that shape),
+ * and the particle-dimension updates per part and iteration at which a
+ * large swarm is split over several workgroups (part_work >= 1).
+ * stage_kib > 0 keeps each part's state in stage_kib KiB of LDS for a whole
+ * launch (lanes 256, 512 or 1024; part_work is ignored): a swarm is split into as
+ * many parts as its state needs, at most 512 and at most the grid.  A new
+ * batch takes the shape pso_batch_autotune chose earlier in this process for
+ * the same swarm sizes and iteration limits on the same device, else 1024
+ * lanes with 158 KiB staged if every swarm fits that, else 256 lanes, the
+ * full capacity, 2^17 updates per part, streamed.  The co-resident capacity
+ * is three quarters of the occupancy bound streamed and all but 8 compute
+ * units' worth staged: a batch sharing the device with other long-running
+ * kernels may find its parts not co-resident, which its bounded waits report
+ * as PSO_EDEVICE from pso_batch_results. */
 typedef struct pso_batch_shape {
     int32_t lanes;
     int32_t grid;
     int64_t part_work;
+    int32_t stage_kib;
+    int32_t reserved; /* 0 */
 } pso_batch_shape;
 
 /* The batch's current shape (grid as launched: at most the entry count). */
 int pso_batch_get_shape(pso_batch *b, pso_batch_shape *shape);
 
 /* Sets the shape for the following launches (synchronises the batch's
- * stream).  EINVAL for unsupported lanes, grid < 0 or part_work < 1; a grid
- * above the co-resident capacity is reduced to it, so every launch stays
+ * stream).  EINVAL for unsupported lanes, grid < 0, part_work < 1 (streamed),
+ * stage_kib < 0, more staged KiB than a workgroup's LDS, or a swarm whose
+ * staged parts would exceed 512, the grid or the parts the batch's gang
+ * regions were sized for (those of the autotuner's shapes); a grid above the
+ * co-resident capacity is reduced to it, so every launch stays
  * deadlock-free.  Between launches only: the batch's state is restarted by
  * the next pso_batch_launch anyway. */
 int pso_batch_set_shape(pso_batch *b, const pso_batch_shape *shape);
 
 /* Autotuner (the batching row of the workload set: tiles and schedules
  * picked by measurement on the device).  Times probe_iters iterations of the
- * whole batch under each candidate shape -- 64/128/256 lanes x 2^15/2^17
- * updates per part x all or half of the co-resident workgroups, each after
- * an untimed Step 1 -- keeps the fastest, records it for later batches of
- * the same signature, and writes it to *chosen (may be NULL).  Leaves the
- * batch ready for pso_batch_launch (which restarts it).  Synchronous; costs
- * about 12 x (probe_iters + 1) iterations of the batch.  probe_iters < 1 ->
- * EINVAL. */
+ * whole batch under each candidate shape -- streamed: 64/128/256 lanes x
+ * 2^15/2^17 updates per part x all or half of the co-resident workgroups;
+ * LDS-staged: 512/1024 lanes x 78/158 KiB per workgroup, where the swarms
+ * fit -- each after an untimed Step 1, keeps the fastest, records it for
+ * later batches of the same signature, and writes it to *chosen (may be
+ * NULL).  Leaves the batch ready for pso_batch_launch (which restarts it).
+ * Synchronous; costs about 16 x (probe_iters + 1) iterations of the batch.
+ * probe_iters < 1 -> EINVAL. */
 int pso_batch_autotune(pso_batch *b, int64_t probe_iters, pso_batch_shape *chosen);
 
 /* ------------------------------------------------------------------------ */

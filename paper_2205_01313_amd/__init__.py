@@ -244,13 +244,15 @@ class Batch:
 
     @property
     def shape(self):
-        """Current tiles and schedule: dict(lanes, grid, part_work)."""
+        """Current tiles and schedule: dict(lanes, grid, part_work, stage_kib)."""
         sh = _native.PsoBatchShape()
         _check(lib().pso_batch_get_shape(self.h, ctypes.byref(sh)), "pso_batch_get_shape")
-        return dict(lanes=sh.lanes, grid=sh.grid, part_work=sh.part_work)
+        return dict(lanes=sh.lanes, grid=sh.grid, part_work=sh.part_work, stage_kib=sh.stage_kib)
 
-    def set_shape(self, lanes, grid=0, part_work=1 << 17):
-        sh = _native.PsoBatchShape(int(lanes), int(grid), int(part_work))
+    def set_shape(self, lanes, grid=0, part_work=1 << 17, stage_kib=0):
+        """stage_kib > 0: each part's state in that many KiB of LDS for a
+        whole launch (lanes 256, 512 or 1024); 0: streamed from device memory."""
+        sh = _native.PsoBatchShape(int(lanes), int(grid), int(part_work), int(stage_kib), 0)
         _check(lib().pso_batch_set_shape(self.h, ctypes.byref(sh)), "pso_batch_set_shape")
 
     def autotune(self, probe_iters=8):
@@ -258,7 +260,7 @@ class Batch:
         the fastest (pso_batch_autotune); returns it."""
         sh = _native.PsoBatchShape()
         _check(lib().pso_batch_autotune(self.h, int(probe_iters), ctypes.byref(sh)), "pso_batch_autotune")
-        return dict(lanes=sh.lanes, grid=sh.grid, part_work=sh.part_work)
+        return dict(lanes=sh.lanes, grid=sh.grid, part_work=sh.part_work, stage_kib=sh.stage_kib)
 
     def results(self, positions=True):
         n = len(self.specs)

@@ -28,7 +28,8 @@ class PsoDesc(ctypes.Structure):
 
 
 class PsoBatchShape(ctypes.Structure):
-    _fields_ = [("lanes", ctypes.c_int32), ("grid", ctypes.c_int32), ("part_work", ctypes.c_int64)]
+    _fields_ = [("lanes", ctypes.c_int32), ("grid", ctypes.c_int32), ("part_work", ctypes.c_int64),
+                ("stage_kib", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class PsoResult(ctypes.Structure):

@@ -94,9 +94,87 @@ struct Scratch {
 
 constexpr unsigned long long GANG_WAIT_TICKS = 2000000000ull; // 20 s of the 100 MHz wall clock
 
-// Combines the workgroup minimum m of step tau (Step 1 = step 0, iteration t
-// = step t) over the swarm's parts.  Returns the swarm minimum; *owner is
-// the part that posted it (its candidate position is in cand_pos).
+// Posts this part's candidate position for step tau: the D coordinates of
+// memory column mi of row-major state x (row pitch `pitch`).
+template <int LANES>
+__device__ __forceinline__ void stage_candidate(const Part &P, long long tau, int D, const float *x, size_t pitch,
+                                                uint32_t mi)
+{
+    float *dst = P.cand_pos + ((size_t)(tau & 1) * P.parts + P.part) * D;
+    for (int d = threadIdx.x; d < D; d += LANES) dst[d] = x[(size_t)d * pitch + mi];
+}
+
+// Combining the workgroup minima of step tau over the swarm's parts, in two
+// halves so that a caller can work between them.  gang_post publishes this
+// part's minimum m (its candidate position already posted if m != NO_KEY)
+// and arrives; gang_wait waits for every part and returns the swarm minimum,
+// with *owner the part that posted it (its position is in cand_pos).  One
+// lane arrives and waits; the first wavefront then reads the parts' keys in
+// parallel.
+template <int LANES>
+__device__ __forceinline__ void gang_post(const Part &P, long long tau, unsigned long long m)
+{
+    if (threadIdx.x == 0) P.cand_key[(size_t)(tau & 1) * P.parts + P.part] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // release the candidate before arriving: the barrier orders every
+        // lane's stores before this one fence
+        __threadfence();
+        atomicAdd(&P.gang->arrive, 1ull);
+    }
+}
+
+template <int LANES>
+__device__ unsigned long long gang_wait(const Part &P, long long tau, Scratch *sc, uint32_t *owner)
+{
+    const int b = (int)(tau & 1);
+    if (threadIdx.x < 64) {
+        if (threadIdx.x == 0) {
+            const unsigned long long target = (unsigned long long)P.parts * (unsigned long long)(tau + 1);
+            const unsigned long long t0 = wall_clock64();
+            while (__hip_atomic_load(&P.gang->arrive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                __builtin_amdgcn_s_sleep(4);
+                if (wall_clock64() - t0 > GANG_WAIT_TICKS) {
+                    sc->err = 1u;
+                    break;
+                }
+            }
+        }
+        __threadfence(); // acquire every part's candidate
+        unsigned long long g = NO_KEY;
+        uint32_t o = 0;
+        for (uint32_t p = threadIdx.x; p < P.parts; p += 64) {
+            const unsigned long long k = __hip_atomic_load(&P.cand_key[(size_t)b * P.parts + p], __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT);
+            if (k < g) {
+                g = k;
+                o = p;
+            }
+        }
+        const unsigned long long gm = wave_min_u64(g);
+        // keys name distinct particles, so one lane holds gm (or all hold NO_KEY)
+        const int src = __builtin_ctzll(__ballot(g == gm));
+        const uint32_t om = (uint32_t)__shfl((int)o, src, 64);
+        if (threadIdx.x == 0) {
+            sc->bkey = gm;
+            sc->owner = om;
+        }
+    }
+    __syncthreads();
+    *owner = sc->owner;
+    return sc->bkey;
+}
+
+template <int LANES>
+__device__ __forceinline__ unsigned long long gang_exchange(const Part &P, long long tau, unsigned long long m,
+                                                            Scratch *sc, uint32_t *owner)
+{
+    gang_post<LANES>(P, tau, m);
+    return gang_wait<LANES>(P, tau, sc, owner);
+}
+
+// The same over the streamed state: the candidate's position is column m of
+// x in device memory (stored by this workgroup).
 template <int LANES>
 __device__ unsigned long long gang_min(const SwarmArgs &a, const Part &P, long long tau, unsigned long long m,
                                        Scratch *sc, uint32_t *owner)
@@ -105,46 +183,8 @@ __device__ unsigned long long gang_min(const SwarmArgs &a, const Part &P, long l
         *owner = 0;
         return m;
     }
-    const int b = (int)(tau & 1);
-    const int D = a.D;
-    if (m != NO_KEY) { // stage this part's candidate position (x just stored by this workgroup)
-        const size_t gi = (uint32_t)m;
-        float *dst = P.cand_pos + ((size_t)b * P.parts + P.part) * D;
-        for (int d = threadIdx.x; d < D; d += LANES) dst[d] = a.x[(size_t)d * a.Np + gi];
-    }
-    if (threadIdx.x == 0) P.cand_key[(size_t)b * P.parts + P.part] = m;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        // release the candidate before arriving: the barrier orders every
-        // lane's stores before this one fence
-        __threadfence();
-        atomicAdd(&P.gang->arrive, 1ull);
-        const unsigned long long target = (unsigned long long)P.parts * (unsigned long long)(tau + 1);
-        const unsigned long long t0 = wall_clock64();
-        while (__hip_atomic_load(&P.gang->arrive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            __builtin_amdgcn_s_sleep(4);
-            if (wall_clock64() - t0 > GANG_WAIT_TICKS) {
-                sc->err = 1u;
-                break;
-            }
-        }
-        __threadfence(); // acquire every part's candidate
-        unsigned long long g = NO_KEY;
-        unsigned int o = 0;
-        for (uint32_t p = 0; p < P.parts; ++p) {
-            const unsigned long long k = __hip_atomic_load(&P.cand_key[(size_t)b * P.parts + p], __ATOMIC_RELAXED,
-                                                           __HIP_MEMORY_SCOPE_AGENT);
-            if (k < g) {
-                g = k;
-                o = p;
-            }
-        }
-        sc->bkey = g;
-        sc->owner = o;
-    }
-    __syncthreads();
-    *owner = sc->owner;
-    return sc->bkey;
+    if (m != NO_KEY) stage_candidate<LANES>(P, tau, a.D, a.x, a.Np, (uint32_t)m);
+    return gang_exchange<LANES>(P, tau, m, sc, owner);
 }
 
 // gbest position <- the particle of key k: from x (one part: stored by this
@@ -369,6 +409,269 @@ __device__ void batch_part(const BatchItem &it, uint32_t part, uint32_t fixed_it
     }
 }
 
+// ---------------------------------------------------------------------------
+// LDS-staged batched part.  A part's state (x, v, p, pf, pending marks) is
+// copied into LDS once per launch and every iteration of the launch works
+// there, so device memory sees two passes per launch instead of one per
+// iteration.  A part holds so few particles at high D that one particle per
+// lane would leave most lanes idle, so the iteration has two phases, as in
+// the split grid step: (1) each lane takes (particle, dimension pair) items
+// -- one Philox call each; consecutive lanes take consecutive particles of
+// one pair, so LDS accesses are conflict-free, and items of one particle
+// each are small enough that the last round over the lanes wastes little --
+// and applies Eq. 1 and Eq. 2 with the per-element functions every other
+// kernel uses, staging each dimension's fitness terms; (2) after a barrier
+// one lane per particle folds the terms in dimension order, so the fitness
+// is the sequential sum of the other paths bit for bit, and applies the
+// strict pbest test.  A pbest position stays pending in x until the next
+// iteration copies it (only that particle's own elements are written: LDS
+// has no write granularity to respect).  Step 1 runs in device memory (block_init over
+// exactly this part's quads and, for the last part, the padding) and is then
+// staged like a resumed part.
+// ---------------------------------------------------------------------------
+// Lane-strided walk over the cells (row, col) of a rows x cols grid in
+// row-major order, starting at cell threadIdx.x: one division at the start,
+// then additions only.
+template <int LANES>
+struct GridWalk {
+    uint32_t row, col, drow, dcol, cols;
+    __device__ __forceinline__ explicit GridWalk(uint32_t ncols) : cols(ncols)
+    {
+        row = threadIdx.x / ncols;
+        col = threadIdx.x - row * ncols;
+        drow = LANES / ncols;
+        dcol = LANES - drow * ncols;
+    }
+    __device__ __forceinline__ void next()
+    {
+        row += drow;
+        col += dcol;
+        if (col >= cols) {
+            col -= cols;
+            ++row;
+        }
+    }
+};
+
+static constexpr int staged_words(int fitness) { return fitness == F_ACKLEY ? 2 : 1; }
+
+size_t staged_quad_bytes(int D, int fitness)
+{
+    return 4 * (sizeof(float) * (3 + staged_words(fitness)) * (size_t)D + sizeof(float) + 1);
+}
+
+template <int FIT, int LANES>
+__device__ void staged_part(const BatchItem &it, uint32_t part, uint32_t fixed_iters, BatchResult *res,
+                            long long chunk, long long iter_cap, float *s_g, float *s_shift, Scratch *sc,
+                            float *s_state, BatchResult *out_state, float *out_pos, uint32_t out, int pos_stride)
+{
+    constexpr int W = Fitness<FIT>::STAGE_WORDS;
+    static_assert(W == staged_words(FIT), "staged LDS sizing");
+    const SwarmArgs &a = it.a;
+    const int D = a.D;
+    const size_t Np = a.Np;
+    const uint32_t nq = (a.N + 3) / 4, nqi = a.Np / 4;
+    Part P;
+    P.parts = it.parts;
+    P.part = part;
+    P.q_lo = (uint32_t)((unsigned long long)nq * part / it.parts);
+    P.q_hi = (uint32_t)((unsigned long long)nq * (part + 1) / it.parts);
+    P.qi_lo = P.q_lo;
+    P.qi_hi = part + 1 == it.parts ? nqi : P.q_hi;
+    P.gang = it.gang;
+    P.cand_key = it.cand_key;
+    P.cand_pos = it.cand_pos;
+    const uint32_t nql = P.q_hi - P.q_lo, pitch = 4 * nql, ibase = 4 * P.q_lo;
+    for (int d = threadIdx.x; d < D; d += LANES) s_shift[d] = a.shift[d];
+    if (threadIdx.x == 0) {
+        sc->min[0] = NO_KEY;
+        sc->min[1] = NO_KEY;
+    }
+    SwarmLoop L;
+    const bool started = res->started != 0u;
+    __syncthreads();
+    if (!started) {
+        L.stop = false;
+        block_init<FIT, LANES>(a, P, s_shift, s_g, sc, L);
+    } else {
+        L.gkey = res->gkey;
+        L.giter = res->giter;
+        L.t = res->iters;
+        L.stop = res->stop != 0u;
+        for (int d = threadIdx.x; d < D; d += LANES) s_g[d] = a.gpos[d];
+    }
+    // the part's view in LDS: rows of `pitch` particles, local quad q is
+    // particle ibase + 4q + k
+    SwarmArgs la = a;
+    la.x = s_state;
+    la.v = la.x + (size_t)D * pitch;
+    la.p = la.v + (size_t)D * pitch;
+    float *s_t0 = la.p + (size_t)D * pitch, *s_t1 = s_t0 + (size_t)D * pitch;
+    la.pf = s_t0 + (size_t)W * D * pitch;
+    la.pend = reinterpret_cast<uint8_t *>(la.pf + pitch);
+    la.Np = pitch;
+    for (uint32_t e = threadIdx.x; e < (uint32_t)D * nql; e += LANES) {
+        const uint32_t d = e / nql, q = e - d * nql;
+        const size_t g = (size_t)d * Np / 4 + P.q_lo + q, l = (size_t)d * nql + q;
+        reinterpret_cast<f4 *>(la.x)[l] = reinterpret_cast<const f4 *>(a.x)[g];
+        reinterpret_cast<f4 *>(la.v)[l] = reinterpret_cast<const f4 *>(a.v)[g];
+        reinterpret_cast<f4 *>(la.p)[l] = reinterpret_cast<const f4 *>(a.p)[g];
+    }
+    for (uint32_t q = threadIdx.x; q < nql; q += LANES) {
+        reinterpret_cast<f4 *>(la.pf)[q] = reinterpret_cast<const f4 *>(a.pf)[P.q_lo + q];
+        reinterpret_cast<uint32_t *>(la.pend)[q] = reinterpret_cast<const uint32_t *>(a.pend)[P.q_lo + q];
+    }
+    __syncthreads();
+
+    const long long left = it.max_iter - L.t;
+    const long long nd = (long long)a.N * a.D;
+    long long iters = chunk / nd;
+    iters = iters < 1 ? 1 : (iters > iter_cap ? iter_cap : iters);
+    if (fixed_iters > 0) iters = fixed_iters;
+    const long long T = left < iters ? left : iters;
+    const unsigned long long c0 = wall_clock64();
+    const uint32_t npairs = (uint32_t)(D + 1) / 2;
+    // Without a stop rule every iteration of the launch runs, so a part of
+    // several can compute the gbest-independent half of the next iteration's
+    // Eq. 1 -- the Philox draws, (w v) + ((c1 r1)(p - x)) into v's slot and
+    // c2 r2 into the first term slot, the pending pbest positions copied --
+    // while the other parts arrive, and finish it once the gbest is known.
+    const bool split = P.parts > 1 && !(it.tol > 0.0f);
+    auto own_half = [&](uint32_t tn) {
+        for (GridWalk<LANES> gw(pitch); gw.row < npairs; gw.next()) {
+            const uint32_t pr = gw.row, sidx = gw.col;
+            const bool pend = la.pend[sidx] != 0;
+            const U4 u = philox4x32_10(a.k0, a.k1, pr, ibase + sidx, tn, TAG_VEL);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int d = 2 * (int)pr + h;
+                if (d >= D) break;
+                const size_t e = (size_t)d * pitch + sidx;
+                const float x = la.x[e];
+                const float p = pend ? x : la.p[e];
+                la.v[e] = velocity_eq1_own(la, x, la.v[e], p, unit_float(word_r1(u, h)));
+                s_t0[e] = a.c2 * unit_float(word_r2(u, h));
+                if (pend) la.p[e] = p;
+            }
+        }
+    };
+    L.stop = L.stop || meets_tol(L.gkey, it.tol, it.fstar);
+    if (split && T > 0 && !L.stop) own_half((uint32_t)(L.t + 1));
+    for (long long n = 0; n < T && !L.stop; ++n) {
+        const uint32_t t = (uint32_t)(L.t + 1);
+        if (split) {
+            // (1') the social half of Eq. 1 and Eq. 2; fitness terms staged
+            __syncthreads(); // own_half's stores before they are read
+            for (GridWalk<LANES> gw(pitch); gw.row < (uint32_t)D; gw.next()) {
+                const uint32_t d = gw.row;
+                const size_t e = (size_t)d * pitch + gw.col;
+                const float x = la.x[e];
+                const float nv = velocity_eq1_social(la, la.v[e], s_t0[e], x, s_g[d]);
+                const float xn = position_eq2(la, x, nv);
+                la.x[e] = xn;
+                la.v[e] = nv;
+                float t0 = 0.0f, t1 = 0.0f;
+                Fitness<FIT>::stage(xn - s_shift[d], &t0, &t1);
+                s_t0[e] = t0;
+                if constexpr (W == 2) s_t1[e] = t1;
+            }
+        } else {
+            // (1) Eq. 1 and Eq. 2 per (particle, dimension pair); fitness terms staged
+            for (GridWalk<LANES> gw(pitch); gw.row < npairs; gw.next()) {
+                const uint32_t pr = gw.row, sidx = gw.col;
+                const bool pend = la.pend[sidx] != 0;
+                const U4 u = philox4x32_10(a.k0, a.k1, pr, ibase + sidx, t, TAG_VEL);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int d = 2 * (int)pr + h;
+                    if (d >= D) break;
+                    const size_t e = (size_t)d * pitch + sidx;
+                    const float x = la.x[e], v = la.v[e];
+                    const float p = pend ? x : la.p[e];
+                    const float nv =
+                        velocity_eq1(la, x, v, p, s_g[d], unit_float(word_r1(u, h)), unit_float(word_r2(u, h)));
+                    const float xn = position_eq2(la, x, nv);
+                    la.x[e] = xn;
+                    la.v[e] = nv;
+                    if (pend) la.p[e] = p;
+                    float t0 = 0.0f, t1 = 0.0f;
+                    Fitness<FIT>::stage(xn - s_shift[d], &t0, &t1);
+                    s_t0[e] = t0;
+                    if constexpr (W == 2) s_t1[e] = t1;
+                }
+            }
+        }
+        __syncthreads();
+        // (2) fold in dimension order; Step 4 (strict improvement, NaN never improves)
+        unsigned long long key = NO_KEY;
+        for (uint32_t sidx = threadIdx.x; sidx < pitch; sidx += LANES) {
+            const uint32_t i = ibase + sidx;
+            bool imp = false;
+            if (i < a.N) {
+                const float f = fold_terms<FIT>(s_t0, s_t1, pitch, sidx, D);
+                imp = f < la.pf[sidx];
+                if (imp) {
+                    la.pf[sidx] = f;
+                    const unsigned long long kk = make_key(f, i);
+                    key = kk < key ? kk : key;
+                }
+            }
+            la.pend[sidx] = imp ? 1 : 0;
+        }
+        const unsigned long long m = block_min(key, L.gkey, &sc->min[t & 1]);
+        if (threadIdx.x == 0) sc->min[(t + 1) & 1] = NO_KEY;
+        unsigned long long g = m;
+        uint32_t owner = 0;
+        if (P.parts > 1) {
+            if (m != NO_KEY) stage_candidate<LANES>(P, t, D, la.x, pitch, (uint32_t)m - ibase);
+            gang_post<LANES>(P, t, m);
+            if (split && n + 1 < T) own_half(t + 1);
+            g = gang_wait<LANES>(P, t, sc, &owner);
+        }
+        if (g < L.gkey) {
+            L.gkey = g;
+            L.giter = t;
+            if (P.parts == 1) {
+                const uint32_t mi = (uint32_t)g - ibase;
+                for (int d = threadIdx.x; d < D; d += LANES) s_g[d] = la.x[(size_t)d * pitch + mi];
+            } else {
+                gather_gbest<LANES>(a, P, t, g, owner, s_g);
+            }
+        }
+        L.t = t;
+        L.stop = meets_tol(L.gkey, it.tol, it.fstar);
+        __syncthreads();
+    }
+    const unsigned long long ticks = wall_clock64() - c0;
+    // the state back to device memory (pending marks included)
+    for (uint32_t e = threadIdx.x; e < (uint32_t)D * nql; e += LANES) {
+        const uint32_t d = e / nql, q = e - d * nql;
+        const size_t g = (size_t)d * Np / 4 + P.q_lo + q, l = (size_t)d * nql + q;
+        reinterpret_cast<f4 *>(a.x)[g] = reinterpret_cast<const f4 *>(la.x)[l];
+        reinterpret_cast<f4 *>(a.v)[g] = reinterpret_cast<const f4 *>(la.v)[l];
+        reinterpret_cast<f4 *>(a.p)[g] = reinterpret_cast<const f4 *>(la.p)[l];
+    }
+    for (uint32_t q = threadIdx.x; q < nql; q += LANES) {
+        reinterpret_cast<f4 *>(a.pf)[P.q_lo + q] = reinterpret_cast<const f4 *>(la.pf)[q];
+        reinterpret_cast<uint32_t *>(a.pend)[P.q_lo + q] = reinterpret_cast<const uint32_t *>(la.pend)[q];
+    }
+    if (part == 0) {
+        for (int d = threadIdx.x; d < D; d += LANES) {
+            a.gpos[d] = s_g[d];
+            if (out_pos) out_pos[(size_t)out * pos_stride + d] = s_g[d];
+        }
+        if (threadIdx.x == 0) {
+            res->gkey = L.gkey;
+            res->giter = L.giter;
+            res->iters = L.t;
+            res->stop = L.stop ? 1u : 0u;
+            res->started = 1u;
+            res->ticks = ticks > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)ticks;
+            if (out_state) out_state[out] = *res;
+        }
+    }
+}
+
 template <int LANES>
 __global__ void __launch_bounds__(LANES) k_batch(const BatchItem *items, const BatchEntry *entries,
                                                  BatchResult *results, uint32_t count, unsigned int *next,
@@ -401,6 +704,62 @@ __global__ void __launch_bounds__(LANES) k_batch(const BatchItem *items, const B
     if (threadIdx.x == 0 && sc.err && err) atomicOr(err, 1u);
 }
 
+// The LDS-staged batched kernel: k_batch's work queue over staged parts.  The
+// dynamic LDS holds the gbest position and shift (maxD floats each, rounded
+// up to 16 bytes) and then the part's staged state.
+__host__ __device__ constexpr int staged_head_floats(int maxD) { return 2 * ((maxD + 3) & ~3); }
+
+template <int LANES>
+__global__ void __launch_bounds__(LANES) k_batch_staged(const BatchItem *items, const BatchEntry *entries,
+                                                        BatchResult *results, uint32_t count, unsigned int *next,
+                                                        long long chunk, long long iter_cap, BatchResult *out_state,
+                                                        float *out_pos, int pos_stride, unsigned int *err)
+{
+    __shared__ Scratch sc;
+    __shared__ uint32_t s_idx;
+    extern __shared__ float s_dyn[];
+    float *s_state = s_dyn + staged_head_floats(pos_stride);
+    if (threadIdx.x == 0) sc.err = 0;
+    for (;;) {
+        if (threadIdx.x == 0) s_idx = atomicAdd(next, 1u);
+        __syncthreads();
+        const uint32_t j = s_idx;
+        __syncthreads();
+        if (j >= count) break; // uniform: every workgroup leaves once the list is drained
+        const BatchEntry e = entries[j];
+        const BatchItem &it = items[e.item];
+        float *s_g = s_dyn, *s_shift = s_dyn + ((pos_stride + 3) & ~3);
+        BatchResult *res = &results[e.item];
+        switch (it.fitness) {
+        case F_SPHERE: staged_part<F_SPHERE, LANES>(it, e.part, e.iters, res, chunk, iter_cap, s_g, s_shift, &sc, s_state, out_state, out_pos, e.out, pos_stride); break;
+        case F_RASTRIGIN: staged_part<F_RASTRIGIN, LANES>(it, e.part, e.iters, res, chunk, iter_cap, s_g, s_shift, &sc, s_state, out_state, out_pos, e.out, pos_stride); break;
+        case F_ROSENBROCK: staged_part<F_ROSENBROCK, LANES>(it, e.part, e.iters, res, chunk, iter_cap, s_g, s_shift, &sc, s_state, out_state, out_pos, e.out, pos_stride); break;
+        case F_ACKLEY: staged_part<F_ACKLEY, LANES>(it, e.part, e.iters, res, chunk, iter_cap, s_g, s_shift, &sc, s_state, out_state, out_pos, e.out, pos_stride); break;
+        default: staged_part<F_CUBIC, LANES>(it, e.part, e.iters, res, chunk, iter_cap, s_g, s_shift, &sc, s_state, out_state, out_pos, e.out, pos_stride); break;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && sc.err && err) atomicOr(err, 1u);
+}
+
+uint32_t staged_parts(uint64_t N, int D, int fitness, int stage_kib, int grid_cap)
+{
+    if (stage_kib < 1 || D < 1 || N < 1) return 0;
+    const uint64_t qmax = (uint64_t)stage_kib * 1024 / staged_quad_bytes(D, fitness);
+    if (qmax < 1) return 0;
+    const uint64_t nq = (N + 3) / 4;
+    // part p takes quads [nq*p/parts, nq*(p+1)/parts): at most ceil(nq/parts) <= qmax
+    const uint64_t parts = (nq + qmax - 1) / qmax;
+    if (parts > MAX_STAGED_PARTS || parts > (uint64_t)std::max(1, grid_cap)) return 0;
+    return (uint32_t)parts;
+}
+
+size_t batch_dynamic_lds(int maxD, int stage_kib)
+{
+    if (stage_kib > 0) return sizeof(float) * staged_head_floats(maxD) + (size_t)stage_kib * 1024;
+    return 2 * sizeof(float) * maxD;
+}
+
 uint32_t parts_for(uint64_t N, int D, int grid_cap, const BatchShape &shape)
 {
     const uint64_t work = N * (uint64_t)D;
@@ -413,7 +772,11 @@ uint32_t parts_for(uint64_t N, int D, int grid_cap, const BatchShape &shape)
     return (uint32_t)std::max<uint64_t>(parts, 1);
 }
 
-bool batch_lanes_supported(int lanes) { return lanes == 64 || lanes == 128 || lanes == 256; }
+bool batch_lanes_supported(int lanes, bool staged)
+{
+    if (staged) return lanes == 256 || lanes == 512 || lanes == 1024;
+    return lanes == 64 || lanes == 128 || lanes == 256;
+}
 
 size_t gang_bytes(uint32_t parts, int D)
 {
@@ -463,13 +826,37 @@ hipError_t launch_batch_reset(const BatchItem *items, BatchResult *results, uint
     return hipGetLastError();
 }
 
+template <int LANES>
+static hipError_t launch_staged(const BatchItem *items, const BatchEntry *entries, BatchResult *results, uint32_t count,
+                                unsigned int *next, int maxD, int grid, long long chunk, long long iter_cap,
+                                hipStream_t stream, BatchResult *out_state, float *out_pos, unsigned int *err,
+                                int stage_kib)
+{
+    // the kernel's dynamic-LDS limit was raised by batch_capacity (no
+    // attribute call here: this launch may be captured into a graph)
+    const size_t lds = batch_dynamic_lds(maxD, stage_kib);
+    hipLaunchKernelGGL(k_batch_staged<LANES>, dim3(grid), dim3(LANES), lds, stream, items, entries, results, count,
+                       next, chunk, iter_cap, out_state, out_pos, maxD, err);
+    return hipGetLastError();
+}
+
 hipError_t launch_batch(const BatchItem *items, const BatchEntry *entries, BatchResult *results, uint32_t count,
                         unsigned int *next, int maxD, int grid, int lanes, long long chunk, long long iter_cap,
-                        hipStream_t stream, BatchResult *out_state, float *out_pos, unsigned int *err)
+                        hipStream_t stream, BatchResult *out_state, float *out_pos, unsigned int *err, int stage_kib)
 {
-    if (!batch_lanes_supported(lanes)) return hipErrorInvalidValue;
+    if (!batch_lanes_supported(lanes, stage_kib > 0)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_counter_reset, dim3(1), dim3(64), 0, stream, next);
-    const size_t lds = 2 * sizeof(float) * maxD;
+    if (stage_kib > 0) {
+        if (lanes == 1024)
+            return launch_staged<1024>(items, entries, results, count, next, maxD, grid, chunk, iter_cap, stream,
+                                       out_state, out_pos, err, stage_kib);
+        if (lanes == 512)
+            return launch_staged<512>(items, entries, results, count, next, maxD, grid, chunk, iter_cap, stream,
+                                      out_state, out_pos, err, stage_kib);
+        return launch_staged<256>(items, entries, results, count, next, maxD, grid, chunk, iter_cap, stream,
+                                  out_state, out_pos, err, stage_kib);
+    }
+    const size_t lds = batch_dynamic_lds(maxD, 0);
     switch (lanes) {
     case 64:
         hipLaunchKernelGGL(k_batch<64>, dim3(grid), dim3(64), lds, stream, items, entries, results, count, next, chunk,
@@ -487,20 +874,47 @@ hipError_t launch_batch(const BatchItem *items, const BatchEntry *entries, Batch
     return hipGetLastError();
 }
 
-hipError_t batch_capacity(int maxD, int lanes, int *workgroups)
+hipError_t batch_capacity(int maxD, int lanes, int *workgroups, int stage_kib)
 {
-    if (!batch_lanes_supported(lanes)) return hipErrorInvalidValue;
-    const size_t lds = 2 * sizeof(float) * maxD;
-    int per_cu = 0, dev = 0, cus = 0;
-    hipError_t e = lanes == 64    ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<64>, 64, lds)
-                   : lanes == 128 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<128>, 128, lds)
-                                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<256>, 256, lds);
-    if (e != hipSuccess) return e;
+    if (!batch_lanes_supported(lanes, stage_kib > 0)) return hipErrorInvalidValue;
+    const size_t lds = batch_dynamic_lds(maxD, stage_kib);
+    int per_cu = 0, dev = 0, cus = 0, lds_max = 0;
+    hipError_t e;
     if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if (stage_kib > 0) {
+        if ((e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev)) != hipSuccess)
+            return e;
+        if (lds + 1024 > (size_t)lds_max) { // static LDS of the kernel included
+            *workgroups = 0;
+            return hipSuccess;
+        }
+        const void *f = lanes == 1024  ? reinterpret_cast<const void *>(k_batch_staged<1024>)
+                        : lanes == 512 ? reinterpret_cast<const void *>(k_batch_staged<512>)
+                                       : reinterpret_cast<const void *>(k_batch_staged<256>);
+        // the most any batch may ask for (batches of other maxD share the kernel)
+        if ((e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max - 1024)) != hipSuccess)
+            return e;
+        e = lanes == 1024  ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_staged<1024>, 1024, lds)
+            : lanes == 512 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_staged<512>, 512, lds)
+                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_staged<256>, 256, lds);
+    } else {
+        e = lanes == 64    ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<64>, 64, lds)
+            : lanes == 128 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<128>, 128, lds)
+                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<256>, 256, lds);
+    }
+    if (e != hipSuccess) return e;
     if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
-    // three quarters of the occupancy bound: a margin for anything else the
-    // device keeps resident, so every launched workgroup is co-resident
-    *workgroups = std::max(1, per_cu * cus * 3 / 4);
+    // A margin below the occupancy bound for anything else the device keeps
+    // resident, so every launched workgroup is co-resident: three quarters
+    // of it for the streamed kernel (several workgroups per compute unit, so
+    // the quarter left out costs little), the workgroups of all but 8
+    // compute units for the staged one (at most a few per compute unit,
+    // where a quarter of the units left idle would cost a quarter of the
+    // time: 4096-swarm batch, 572 ms with 192 of 256 units, 479 ms with 248).
+    if (stage_kib > 0)
+        *workgroups = per_cu * std::max(1, cus - 8);
+    else
+        *workgroups = std::max(1, per_cu * cus * 3 / 4);
     return hipSuccess;
 }
 

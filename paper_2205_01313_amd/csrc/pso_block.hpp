@@ -6,7 +6,8 @@
 
 namespace pso {
 
-constexpr uint32_t MAX_PARTS = 64; // workgroups one batched swarm may span
+constexpr uint32_t MAX_PARTS = 64;         // workgroups one streamed batched swarm may span
+constexpr uint32_t MAX_STAGED_PARTS = 512; // workgroups one LDS-staged batched swarm may span
 
 // Meeting point of the parts of one swarm (parts > 1): each part posts its
 // workgroup-minimum key and, if it has one, that particle's position into the
@@ -32,18 +33,36 @@ struct BatchItem {
     float *cand_pos;
 };
 
-// Tiles and schedule of a batched launch: lanes per workgroup (64, 128 or
-// 256), co-resident workgroups, and particle-dimension updates per part and
-// iteration when a large swarm is split into parts.  Every shape computes the
-// same bits; only the time differs.
+// Tiles and schedule of a batched launch: lanes per workgroup, co-resident
+// workgroups, particle-dimension updates per part and iteration when a large
+// swarm is split into parts, and the state's home during a launch.
+// stage_kib = 0 streams every part's state from device memory each
+// iteration (lanes 64, 128 or 256; parts by part_work); stage_kib > 0 copies
+// each part's state into stage_kib KiB of LDS for the whole launch and
+// splits swarms into as many parts as that takes (lanes 256, 512 or 1024;
+// part_work unused).  Every shape computes the same bits; only the time
+// differs.
 struct BatchShape {
     int lanes;
     int grid;
     long long part_work;
+    int stage_kib;
 };
-constexpr BatchShape DEFAULT_BATCH_SHAPE = {256, 0, 1 << 17}; // grid 0: three quarters of occupancy
+constexpr BatchShape DEFAULT_BATCH_SHAPE = {256, 0, 1 << 17, 0}; // grid 0: the co-resident capacity
+// A batch's shape before any autotuning when every swarm fits it (else the
+// streamed default): one 1024-lane workgroup per compute unit with 158 KiB
+// of staged state.
+constexpr BatchShape DEFAULT_STAGED_SHAPE = {1024, 0, 0, 158};
 
-bool batch_lanes_supported(int lanes);
+bool batch_lanes_supported(int lanes, bool staged = false);
+
+// LDS bytes one staged particle quad takes: x, v, p and the fitness terms of
+// each of D dimensions, its pbest fitness and pending marks.
+size_t staged_quad_bytes(int D, int fitness);
+// Parts of a swarm under an LDS-staged shape (each part's quads fit
+// stage_kib KiB), or 0 if it would need more than MAX_STAGED_PARTS or
+// grid_cap workgroups.
+uint32_t staged_parts(uint64_t N, int D, int fitness, int stage_kib, int grid_cap);
 
 // Parts for a batched swarm: about one part per shape.part_work
 // particle-dimension updates of an iteration, at least one particle quad per
@@ -94,11 +113,18 @@ hipError_t launch_batch_reset(const BatchItem *items, BatchResult *results, uint
 // any other launch running concurrently) and every swarm's parts <= grid.
 // Optionally writes each swarm's state to out_state[out] and its gbest
 // position to out_pos[out*maxD ..]; device errors set *err.
+// stage_kib > 0 runs the LDS-staged kernel (every item's parts must come from
+// staged_parts for the same stage_kib).
 hipError_t launch_batch(const BatchItem *items, const BatchEntry *entries, BatchResult *results, uint32_t count,
                         unsigned int *next, int maxD, int grid, int lanes, long long chunk, long long iter_cap,
-                        hipStream_t stream, BatchResult *out_state, float *out_pos, unsigned int *err);
-// Workgroups of `lanes` lanes of the batched kernel that are safely
-// co-resident (three quarters of the occupancy bound).
-hipError_t batch_capacity(int maxD, int lanes, int *workgroups);
+                        hipStream_t stream, BatchResult *out_state, float *out_pos, unsigned int *err,
+                        int stage_kib = 0);
+// Workgroups of `lanes` lanes of the batched kernel (LDS-staged with
+// stage_kib KiB if > 0) that are safely co-resident: three quarters of the
+// occupancy bound streamed, all but 8 compute units' worth staged; 0 if the
+// staged LDS does not fit a workgroup.
+hipError_t batch_capacity(int maxD, int lanes, int *workgroups, int stage_kib = 0);
+// LDS bytes a workgroup of the batched kernel takes dynamically.
+size_t batch_dynamic_lds(int maxD, int stage_kib);
 
 } // namespace pso

@@ -517,14 +517,19 @@ void batch_free(pso_batch *b)
     delete b;
 }
 
-// The shapes the autotuner tries: lanes per workgroup x part size x
-// co-resident workgroups (all of them, or half: a smaller working set).
+// The shapes the autotuner tries: streamed, lanes per workgroup x part size
+// x co-resident workgroups (all of them, or half: a smaller working set);
+// LDS-staged, lanes x staged KiB per workgroup (two or one workgroups per
+// compute unit's 160 KiB; smaller parts meet too often: 38 KiB was 3x
+// slower on the 4096-swarm batch).
 std::vector<pso::BatchShape> tuner_candidates()
 {
     std::vector<pso::BatchShape> c;
     for (int lanes : {64, 128, 256})
         for (long long pw : {1LL << 15, 1LL << 17})
-            for (int half : {0, 1}) c.push_back(pso::BatchShape{lanes, half ? -2 : 0, pw});
+            for (int half : {0, 1}) c.push_back(pso::BatchShape{lanes, half ? -2 : 0, pw, 0});
+    for (int lanes : {512, 1024})
+        for (int kib : {78, 158}) c.push_back(pso::BatchShape{lanes, 0, 0, kib});
     return c;
 }
 
@@ -533,8 +538,12 @@ std::vector<pso::BatchShape> tuner_candidates()
 hipError_t shape_grid(int maxD, const pso::BatchShape &sh, int *grid)
 {
     int cap = 0;
-    hipError_t e = pso::batch_capacity(maxD, sh.lanes, &cap);
+    hipError_t e = pso::batch_capacity(maxD, sh.lanes, &cap, sh.stage_kib);
     if (e != hipSuccess) return e;
+    if (cap < 1) { // a staged shape whose LDS does not fit a workgroup
+        *grid = 0;
+        return hipSuccess;
+    }
     *grid = sh.grid > 0 ? std::min(sh.grid, cap) : sh.grid < 0 ? std::max(1, cap / -sh.grid) : cap;
     return hipSuccess;
 }
@@ -547,14 +556,27 @@ std::map<std::pair<uint64_t, int>, pso::BatchShape> g_tuned;
 // per-part work first, a swarm's parts consecutive) and the grid.
 int batch_configure(pso_batch *b, const pso::BatchShape &sh)
 {
-    if (!pso::batch_lanes_supported(sh.lanes) || sh.part_work < 1)
-        return fail(PSO_EINVAL, "batch shape: lanes must be 64, 128 or 256 and part_work >= 1");
+    const bool staged = sh.stage_kib > 0;
+    if (sh.stage_kib < 0 || !pso::batch_lanes_supported(sh.lanes, staged) || (!staged && sh.part_work < 1))
+        return fail(PSO_EINVAL, "batch shape: lanes must be 64, 128 or 256 with part_work >= 1 (streamed), or 256, "
+                                "512 or 1024 (LDS-staged, stage_kib > 0)");
     int grid = 0;
     HIP_TRY(shape_grid(b->maxD, sh, &grid));
+    if (grid < 1) return fail(PSO_EINVAL, "batch shape: %d KiB of staged state per workgroup exceed the LDS", sh.stage_kib);
     std::vector<uint32_t> parts(b->count);
+    for (int64_t i = 0; i < b->count; ++i) {
+        if (staged) {
+            parts[i] = pso::staged_parts(b->N[i], b->D[i], b->items[i].fitness, sh.stage_kib, grid);
+            if (parts[i] == 0 || parts[i] > b->max_parts[i])
+                return fail(PSO_EINVAL, "batch shape: swarm %lld (N=%llu, D=%d) does not fit %d KiB of LDS per "
+                                        "workgroup in the parts this batch provides",
+                            (long long)i, (unsigned long long)b->N[i], b->D[i], sh.stage_kib);
+        } else {
+            parts[i] = std::min(pso::parts_for(b->N[i], b->D[i], grid, sh), b->max_parts[i]);
+        }
+    }
     uint64_t n_entries = 0;
     for (int64_t i = 0; i < b->count; ++i) {
-        parts[i] = std::min(pso::parts_for(b->N[i], b->D[i], grid, sh), b->max_parts[i]);
         pso::bind_gang(&b->items[i], b->gang[i], parts[i]);
         n_entries += parts[i];
     }
@@ -583,7 +605,8 @@ int batch_launch_iters(pso_batch *b, long long iter_cap, bool reset)
 {
     if (reset) HIP_TRY(pso::launch_batch_reset(b->d_items, b->d_results, (uint32_t)b->count, b->d_next, b->stream));
     HIP_TRY(pso::launch_batch(b->d_items, b->d_entries, b->d_results, b->n_entries, b->d_next, b->maxD, b->grid,
-                              b->shape.lanes, (long long)1 << 62, iter_cap, b->stream, nullptr, nullptr, b->d_err));
+                              b->shape.lanes, (long long)1 << 62, iter_cap, b->stream, nullptr, nullptr, b->d_err,
+                              b->shape.stage_kib));
     return PSO_OK;
 }
 
@@ -623,7 +646,9 @@ int pso_batch_create(const pso_desc *descs, int64_t count, void *hip_stream, pso
         lay[i] = pso::layout_of((uint64_t)d.N, d.D, false);
         uint32_t mp = pso::parts_for((uint64_t)d.N, d.D, def_grid, pso::DEFAULT_BATCH_SHAPE);
         for (size_t c = 0; c < cands.size(); ++c)
-            mp = std::max(mp, pso::parts_for((uint64_t)d.N, d.D, cand_grid[c], cands[c]));
+            mp = std::max(mp, cands[c].stage_kib > 0
+                                  ? pso::staged_parts((uint64_t)d.N, d.D, d.fitness_id, cands[c].stage_kib, cand_grid[c])
+                                  : pso::parts_for((uint64_t)d.N, d.D, cand_grid[c], cands[c]));
         maxp[i] = mp;
         off[i] = total;
         goff[i] = total + lay[i].total;
@@ -695,16 +720,22 @@ int pso_batch_create(const pso_desc *descs, int64_t count, void *hip_stream, pso
         batch_free(b);
         return fail(PSO_EDEVICE, "descriptor upload failed");
     }
-    // a shape the autotuner chose for the same workload on this device
-    pso::BatchShape sh = pso::DEFAULT_BATCH_SHAPE;
+    // a shape the autotuner chose for the same workload on this device, else
+    // the staged default where every swarm fits it, else the streamed one
+    pso::BatchShape sh = pso::DEFAULT_STAGED_SHAPE;
+    bool tuned = false;
     int dev = 0;
     (void)hipGetDevice(&dev);
     {
         std::lock_guard<std::mutex> g(g_tuned_mu);
         auto f = g_tuned.find({sig, dev});
-        if (f != g_tuned.end()) sh = f->second;
+        if (f != g_tuned.end()) {
+            sh = f->second;
+            tuned = true;
+        }
     }
     int rc = batch_configure(b, sh);
+    if (rc == PSO_EINVAL && !tuned) rc = batch_configure(b, pso::DEFAULT_BATCH_SHAPE);
     if (rc) {
         batch_free(b);
         return rc;
@@ -746,6 +777,7 @@ int pso_batch_get_shape(pso_batch *b, pso_batch_shape *shape)
     shape->lanes = b->shape.lanes;
     shape->grid = b->grid;
     shape->part_work = b->shape.part_work;
+    shape->stage_kib = b->shape.stage_kib;
     return PSO_OK;
 }
 
@@ -753,7 +785,7 @@ int pso_batch_set_shape(pso_batch *b, const pso_batch_shape *shape)
 {
     if (!b || !shape) return fail(PSO_EINVAL, "batch or shape is NULL");
     if (shape->grid < 0) return fail(PSO_EINVAL, "grid must be >= 0 (0: the co-resident capacity)");
-    return batch_configure(b, pso::BatchShape{shape->lanes, shape->grid, shape->part_work});
+    return batch_configure(b, pso::BatchShape{shape->lanes, shape->grid, shape->part_work, shape->stage_kib});
 }
 
 int pso_batch_autotune(pso_batch *b, int64_t probe_iters, pso_batch_shape *chosen)
@@ -770,8 +802,16 @@ int pso_batch_autotune(pso_batch *b, int64_t probe_iters, pso_batch_shape *chose
     pso::BatchShape best = b->shape;
     int rc = PSO_OK;
     for (const pso::BatchShape &sh : tuner_candidates()) {
-        // Step 1 and one iteration untimed, then probe_iters timed iterations
-        if ((rc = batch_configure(b, sh)) || (rc = batch_launch_iters(b, 1, true))) break;
+        // Step 1 and one iteration untimed, then probe_iters timed iterations;
+        // a staged shape that this batch's swarms do not fit is skipped
+        if ((rc = batch_configure(b, sh))) {
+            if (sh.stage_kib > 0 && rc == PSO_EINVAL) {
+                rc = PSO_OK;
+                continue;
+            }
+            break;
+        }
+        if ((rc = batch_launch_iters(b, 1, true))) break;
         if (hipEventRecord(e0, b->stream) != hipSuccess) {
             rc = fail(PSO_EDEVICE, "hipEventRecord failed");
             break;

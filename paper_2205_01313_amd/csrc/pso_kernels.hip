@@ -484,9 +484,7 @@ __global__ void PSO_STEP_ATTR k_step_split(SwarmArgs a, uint32_t L, uint32_t C)
     for (uint32_t sidx = threadIdx.x; sidx < P; sidx += BLOCK) {
         const uint32_t i = blockIdx.x * P + sidx;
         if (i >= a.N) break;
-        Fitness<FIT> fit;
-        for (int d = 0; d < D; ++d) fit.fold(s_t0[(size_t)d * P + sidx], W == 2 ? s_t1[(size_t)d * P + sidx] : 0.0f, d);
-        const float f = fit.value(D);
+        const float f = fold_terms<FIT>(s_t0, s_t1, P, sidx, D);
         const bool imp = f < a.pf[i];
         if (imp) {
             a.pf[i] = f;

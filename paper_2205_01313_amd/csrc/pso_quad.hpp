@@ -111,6 +111,31 @@ __device__ __forceinline__ unsigned long long init_quad(const SwarmArgs &a, int 
 // other functions there) and in the batched kernel, whose short per-swarm
 // rows need the extra loads in flight (4096-swarm batch: 749 -> 670 ms; a
 // one-workgroup run of D = 2 is slower with it: 2.1 -> 2.6 us per iteration).
+// Eq. 1 for one element, left to right, clamped to [-vmax, vmax]: the new
+// velocity from position x, velocity v, pbest position p, gbest position g
+// and the draws r1, r2.
+// Split in two for callers that know the gbest position later: the inertia
+// and cognitive terms (w v) + ((c1 r1)(p - x)) and the social coefficient
+// c2 r2 first, then the social term and the clamp -- the same operations in
+// the same order.
+__device__ __forceinline__ float velocity_eq1_own(const SwarmArgs &a, float x, float v, float p, float r1)
+{
+    return (a.w * v) + ((a.c1 * r1) * (p - x));
+}
+
+__device__ __forceinline__ float velocity_eq1_social(const SwarmArgs &a, float own, float c2r2, float x, float g)
+{
+    return clampf(own + (c2r2 * (g - x)), -a.vmax, a.vmax);
+}
+
+__device__ __forceinline__ float velocity_eq1(const SwarmArgs &a, float x, float v, float p, float g, float r1, float r2)
+{
+    return velocity_eq1_social(a, velocity_eq1_own(a, x, v, p, r1), a.c2 * r2, x, g);
+}
+
+// Eq. 2 for one element, clamped to [lo, hi].
+__device__ __forceinline__ float position_eq2(const SwarmArgs &a, float x, float nv) { return clampf(x + nv, a.lo, a.hi); }
+
 // Eq. 1 and Eq. 2 for one dimension row of the four particles (x, v, p as
 // loaded; p replaced by x where the pbest position is pending) and the stores
 // of x, v and (for a dirty group) p.  Returns the new positions.
@@ -118,7 +143,6 @@ template <int POL>
 __device__ __forceinline__ f4 update_row(const SwarmArgs &a, size_t row, uint32_t q, f4 xs, f4 vs, f4 ps,
                                          uint32_t pend, bool line_dirty, const U4 *u, int h, float g)
 {
-    const float w = a.w, c1 = a.c1, c2 = a.c2, vmax = a.vmax, lo = a.lo, hi = a.hi;
 #pragma unroll
     for (int k = 0; k < 4; ++k)
         if (pend & (0xFFu << (8 * k))) ps[k] = xs[k];
@@ -127,11 +151,8 @@ __device__ __forceinline__ f4 update_row(const SwarmArgs &a, size_t row, uint32_
     for (int k = 0; k < 4; ++k) {
         const float r1 = unit_float(word_r1(u[k], h));
         const float r2 = unit_float(word_r2(u[k], h));
-        // Eq. 1 left to right, clamp to [-vmax, vmax]; Eq. 2, clamp to [lo, hi]
-        float nv = ((w * vs[k]) + ((c1 * r1) * (ps[k] - xs[k]))) + ((c2 * r2) * (g - xs[k]));
-        nv = clampf(nv, -vmax, vmax);
-        xn[k] = clampf(xs[k] + nv, lo, hi);
-        vn[k] = nv;
+        vn[k] = velocity_eq1(a, xs[k], vs[k], ps[k], g, r1, r2);
+        xn[k] = position_eq2(a, xs[k], vn[k]);
     }
     st_state<(POL & KEEP_X) != 0>(a.x + row, q, xn);
     st_state<(POL & KEEP_V) != 0>(a.v + row, q, vn);
@@ -241,6 +262,31 @@ __device__ __forceinline__ unsigned long long iterate_quad(const SwarmArgs &a, i
     if (pend_new != pend) *reinterpret_cast<uint32_t *>(a.pend + i0) = pend_new;
     if (n_improved) *n_improved = __builtin_popcount(pend_new);
     return key;
+}
+
+// Folds the staged fitness terms of one particle (column idx of the
+// [dimension][particle] term arrays, row pitch `pitch`) in dimension order.
+// The loads of eight dimensions are issued before their additions, so the
+// sequential sum waits on LDS once per eight terms, not once per term; the
+// order of the additions is unchanged.
+template <int FIT>
+__device__ __forceinline__ float fold_terms(const float *t0, const float *t1, size_t pitch, uint32_t idx, int D)
+{
+    constexpr int W = Fitness<FIT>::STAGE_WORDS;
+    Fitness<FIT> fit;
+    int d = 0;
+    for (; d + 8 <= D; d += 8) {
+        float a0[8], a1[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            a0[j] = t0[(size_t)(d + j) * pitch + idx];
+            a1[j] = W == 2 ? t1[(size_t)(d + j) * pitch + idx] : 0.0f;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) fit.fold(a0[j], a1[j], d + j);
+    }
+    for (; d < D; ++d) fit.fold(t0[(size_t)d * pitch + idx], W == 2 ? t1[(size_t)d * pitch + idx] : 0.0f, d);
+    return fit.value(D);
 }
 
 // p <- x for the marked particles of quad q; clears the marks.

@@ -123,7 +123,7 @@ def test_every_shape_and_the_autotuner_give_the_same_results():
                     assert r["gbest_fit"] == q["gbest_fit"] and r["gbest_iter"] == q["gbest_iter"]
                     assert np.array_equal(r["gbest_pos"], q["gbest_pos"])
         chosen = b.autotune(probe_iters=3)
-        assert chosen["lanes"] in (64, 128, 256) and chosen["grid"] >= 1
+        assert chosen["lanes"] in (64, 128, 256, 512, 1024) and chosen["grid"] >= 1
         b.launch()
         res = b.results()
     for r, q in zip(res, ref):
@@ -132,6 +132,66 @@ def test_every_shape_and_the_autotuner_give_the_same_results():
     for k in (0, len(specs) - 1):
         o = oracle_swarm(specs[k], 8).run_f32(specs[k].T)
         assert ref[k]["gbest_fit"] == o["gbest_fit"] and ref[k]["gbest_iter"] == o["giter"]
+
+
+@pytest.mark.parametrize("lanes,kib", [(512, 78), (1024, 78), (1024, 158)])
+def test_lds_staged_shapes_equal_streamed_and_oracle(lanes, kib):
+    """LDS-staged shapes (each part's state in LDS for the whole launch, the
+    iteration split into per-(quad, dimension pair) updates and an in-order
+    fold): bit-identical to the streamed shape and to the oracle, with swarms
+    of one part and of many (at 78 KiB the Rastrigin swarm takes 59 parts
+    that meet every iteration), ragged N, D = 1 and the stop rule (whose
+    swarms take the unsplit iteration)."""
+    specs = mixed_specs(30, 31)
+    specs += [wl.SwarmSpec("rastrigin", 6001, 48, 20, seed=910, shift_amplitude=1.0),
+              wl.SwarmSpec("ackley", 9003, 20, 20, seed=911, shift_amplitude=1.0),
+              wl.SwarmSpec("rosenbrock", 2050, 64, 15, seed=912),
+              wl.SwarmSpec("cubic", 4097, 1, 25, seed=913),
+              wl.SwarmSpec("sphere", 5, 3, 30, seed=914)]
+    specs[-2].tol, specs[-2].f_star = 1e3, -5e5
+    announce(f"staged batch lanes={lanes} kib={kib}, {len(specs)} swarms")
+    with pso.Batch(specs) as b:
+        b.set_shape(256, 0, 1 << 17)
+        assert b.shape["stage_kib"] == 0
+        b.launch()
+        ref = b.results()
+        try:
+            b.set_shape(lanes, 0, 0, stage_kib=kib)
+        except pso.PsoError as e:
+            if kib > 78 and e.code == pso.PSO_EINVAL and "exceed the LDS" in str(e):
+                pytest.skip(f"{kib} KiB of LDS per workgroup not available on this device")
+            raise
+        sh = b.shape
+        assert sh["lanes"] == lanes and sh["stage_kib"] == kib and sh["grid"] >= 1
+        for rep in range(2):
+            b.launch()
+            res = b.results()
+            for sp, r, q in zip(specs, res, ref):
+                assert r["gbest_fit"] == q["gbest_fit"] and r["gbest_iter"] == q["gbest_iter"], (rep, sp)
+                assert r["iters"] == q["iters"] and np.array_equal(r["gbest_pos"], q["gbest_pos"]), (rep, sp)
+    for k in (len(specs) - 5, len(specs) - 4, len(specs) - 2, 3):
+        sp = specs[k]
+        o = oracle_swarm(sp, 16).run_f32(sp.T, tol=getattr(sp, "tol", 0.0), f_star=getattr(sp, "f_star", 0.0))
+        assert ref[k]["gbest_fit"] == o["gbest_fit"] and ref[k]["gbest_iter"] == o["giter"], sp
+        assert np.array_equal(ref[k]["gbest_pos"], o["gpos"]), sp
+
+
+def test_lds_staged_shape_rejections():
+    """A staged budget too small for one particle quad of the widest swarm,
+    more KiB than the LDS holds, or unsupported lanes: EINVAL, and the batch
+    keeps working under its previous shape."""
+    specs = [wl.SwarmSpec("rastrigin", 100, 64, 5, seed=1), wl.SwarmSpec("sphere", 50, 2, 5, seed=2)]
+    with pso.Batch(specs) as b:
+        before = b.shape
+        for lanes, kib in ((256, 1), (256, 100000), (128, 38), (256, -1)):
+            with pytest.raises(pso.PsoError) as e:
+                b.set_shape(lanes, 0, 0, stage_kib=kib)
+            assert e.value.code == pso.PSO_EINVAL
+        assert b.shape == before
+        b.launch()
+        r = b.results()
+    o = oracle_swarm(specs[0]).run_f32(5)
+    assert r[0]["gbest_fit"] == o["gbest_fit"]
 
 
 def test_graph_replays_equal_the_direct_launch(monkeypatch):
