@@ -340,10 +340,14 @@ typedef struct pso_server_counters {
 } pso_server_counters;
 
 /* Starts a server with mem_budget bytes of device memory for swarm state
- * (allocated now).  Each launch gives every admitted swarm the iterations
- * that fit a 2 ms slice at its own measured speed (4 on its first launch),
- * at most chunk_updates particle-dimension updates' worth (<= 0: no such
- * cap). */
+ * (allocated now).  Each launch gives each of its swarms the iterations
+ * that fit a 2 ms slice at the swarm's own measured speed (4 on its first
+ * launch), at most chunk_updates particle-dimension updates' worth (<= 0: no
+ * such cap).  A request whose state fits runs in LDS-staged launches (its
+ * state in LDS during each launch), others in streamed ones; a launch is of
+ * one kind and takes the longest-waiting ready swarms of that kind, at most
+ * 8 parts per workgroup (PSO_SERVER_STAGED=0 in the environment streams
+ * every request). */
 int pso_server_create(size_t mem_budget, int64_t chunk_updates, pso_server **out);
 
 /* Queues one request (validated as a batch descriptor; the shift is copied)

@@ -57,6 +57,7 @@ struct Req {
     std::vector<float> gpos;
     double us_per_iter = 0.0; // measured time of one iteration on the device (0: not yet)
     long long prev_iters = 0;
+    bool staged = false;      // runs in LDS-staged launches (else streamed ones)
 };
 
 constexpr int STREAMS = 2;
@@ -71,8 +72,23 @@ constexpr int STREAMS = 2;
 // 127 / 377 and 235 / 481).
 constexpr double SLICE_US_DEFAULT = 2000.0;
 constexpr uint32_t FIRST_ITERS = 4;
+// Parts of one launch: at most this many per workgroup (a launch's swarms
+// are the longest-waiting ready ones).  Measured on the serving workload with
+// staged launches (p99 ms and requests/s at 10 000 and 50 000 requests/s):
+// 1: 227 / 4.7k, 397 / 4.5k; 2: 198 / 5.1k, 353 / 5.1k; 4: 156 / 5.8k,
+// 308 / 5.7k; 8: 155 / 6.1k, 292 / 6.0k; 16: 204 / 5.9k, 290 / 6.1k; no
+// limit: 295 / 5.1k, 451 / 4.1k.  PSO_SERVER_LAUNCH_WAVES overrides it.
+constexpr int LAUNCH_WAVES_DEFAULT = 8;
 constexpr uint32_t MAX_SLICE_ITERS = 4096;
 constexpr int MAX_SERVER_D = 4096; // LDS of a launch is sized for the largest D it lists
+// LDS-staged launches: one 1024-lane workgroup per compute unit with 126 KiB
+// of staged state, which leaves room for the gbest position and shift of
+// any D up to MAX_SERVER_D in the 160 KiB.  A request whose staged parts fit
+// a launch runs staged (its state in LDS for each launch), others streamed;
+// each launch is of one kind, the kind of the longest-waiting ready request.
+// PSO_SERVER_STAGED=0 in the environment streams every request.
+constexpr int SERVER_STAGE_LANES = 1024;
+constexpr int SERVER_STAGE_KIB = 126;
 
 } // namespace
 
@@ -81,9 +97,11 @@ struct pso_server {
     size_t budget = 0;
     long long chunk = 1LL << 40; // at most this many particle-dimension updates per swarm and launch
     int max_slots = 0;
-    int grid_cap = 1;
+    int grid_cap = 1;            // workgroups of a streamed launch
+    int grid_cap_staged = 0;     // workgroups of a staged launch (0: staging off)
     double ticks_per_us = 100.0; // device wall clock
     double slice_us = SLICE_US_DEFAULT;
+    int launch_waves = LAUNCH_WAVES_DEFAULT;
     // device memory
     void *base = nullptr;
     pso::BatchItem *d_items = nullptr;
@@ -183,14 +201,44 @@ pso::BatchItem make_item(pso_server *s, const Req &r)
     return it;
 }
 
-// Launches one chunk over every ready swarm on stream k.
+// Launches one chunk on stream k over ready swarms of one kind (staged or
+// streamed): the kind of the ready swarm submitted first, and of that kind
+// the longest-waiting swarms whose parts fit the launch's workgroups.
 bool launch_ready(pso_server *s, int k)
 {
     if (s->ready.empty()) return true;
     hipStream_t st = s->st[k];
-    // upload the items, fresh loop states and shift vectors of new swarms
+    const Req *first = s->slot_req[s->ready[0]];
+    for (int slot : s->ready)
+        if (s->slot_req[slot]->t_submit < first->t_submit) first = s->slot_req[slot];
+    const bool staged = first->staged;
+    // the longest-waiting swarms of that kind, at most launch_waves parts per
+    // workgroup, so that a launch lasts about that many slices and the two
+    // streams take turns
+    const int grid_cap = staged ? s->grid_cap_staged : s->grid_cap;
+    std::stable_sort(s->ready.begin(), s->ready.end(),
+                     [&](int x, int y) { return s->slot_req[x]->t_submit < s->slot_req[y]->t_submit; });
+    std::vector<int> sel, rest;
+    uint64_t parts = 0;
+    for (int slot : s->ready) {
+        const Req *r = s->slot_req[slot];
+        if (r->staged == staged && parts + r->parts <= (uint64_t)grid_cap * s->launch_waves) {
+            sel.push_back(slot);
+            parts += r->parts;
+        } else {
+            rest.push_back(slot);
+        }
+    }
+    // upload the items, fresh loop states and shift vectors of the new swarms
+    // this launch runs (others wait for the launch, on either stream, that
+    // runs them: an upload is ordered before its own launch only)
+    std::vector<int> fresh_rest, gang_rest;
     for (int slot : s->fresh) {
         Req *r = s->slot_req[slot];
+        if (r->staged != staged) {
+            fresh_rest.push_back(slot);
+            continue;
+        }
         if (hipMemcpyAsync(&s->d_items[slot], &s->h_items[slot], sizeof(pso::BatchItem), hipMemcpyHostToDevice, st) !=
                 hipSuccess ||
             hipMemcpyAsync(&s->d_state[slot], &s->h_state[slot], sizeof(pso::BatchResult), hipMemcpyHostToDevice, st) !=
@@ -199,12 +247,18 @@ bool launch_ready(pso_server *s, int k)
                            hipMemcpyHostToDevice, st) != hipSuccess)
             return false;
     }
-    for (int slot : s->fresh_gang)
+    for (int slot : s->fresh_gang) {
+        if (s->slot_req[slot]->staged != staged) {
+            gang_rest.push_back(slot);
+            continue;
+        }
         if (hipMemcpyAsync(s->h_items[slot].gang, s->h_gang0, sizeof(pso::GangSync), hipMemcpyHostToDevice, st) !=
             hipSuccess)
             return false;
-    s->fresh.clear();
-    s->fresh_gang.clear();
+    }
+    s->fresh.swap(fresh_rest);
+    s->fresh_gang.swap(gang_rest);
+    s->ready.swap(sel); // the launch's swarms, until they move to inflight
     // largest per-part work first; a swarm's parts are consecutive
     std::stable_sort(s->ready.begin(), s->ready.end(), [&](int x, int y) {
         const Req *a = s->slot_req[x], *b = s->slot_req[y];
@@ -252,10 +306,10 @@ bool launch_ready(pso_server *s, int k)
         s->cap_pos[k] = std::max(need, 2 * s->cap_pos[k]);
         if (hipMalloc(&s->d_opos[k], sizeof(float) * s->cap_pos[k]) != hipSuccess) return false;
     }
-    const int grid = std::min<int>((int)ne, s->grid_cap);
+    const int grid = std::min<int>((int)ne, grid_cap);
     if (pso::launch_batch(s->d_items, s->d_entries[k], s->d_state, ne, s->d_next[k], maxD, grid,
-                          pso::DEFAULT_BATCH_SHAPE.lanes, s->chunk, MAX_SLICE_ITERS, st, s->d_out[k], s->d_opos[k],
-                          s->d_err) != hipSuccess)
+                          staged ? SERVER_STAGE_LANES : pso::DEFAULT_BATCH_SHAPE.lanes, s->chunk, MAX_SLICE_ITERS, st,
+                          s->d_out[k], s->d_opos[k], s->d_err, staged ? SERVER_STAGE_KIB : 0) != hipSuccess)
         return false;
     if (hipMemcpyAsync(s->h_out[k], s->d_out[k], sizeof(pso::BatchResult) * n, hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipMemcpyAsync(s->h_err[k], s->d_err, sizeof(unsigned int), hipMemcpyDeviceToHost, st) != hipSuccess)
@@ -263,7 +317,7 @@ bool launch_ready(pso_server *s, int k)
     if (hipEventRecord(s->ev[k], st) != hipSuccess) return false;
     s->launch_maxD[k] = maxD;
     s->inflight[k].swap(s->ready);
-    s->ready.clear();
+    s->ready.swap(rest);
     s->busy[k] = true;
     {
         std::lock_guard<std::mutex> g(s->mu);
@@ -405,6 +459,10 @@ int pso_server_create(size_t mem_budget, int64_t chunk_updates, pso_server **out
         const double v = atof(env);
         if (v > 0.0) s->slice_us = v;
     }
+    if (const char *env = getenv("PSO_SERVER_LAUNCH_WAVES")) { // tuning override
+        const int v = atoi(env);
+        if (v > 0) s->launch_waves = v;
+    }
     s->arena = pso::Arena(mem_budget);
     // at most one slot per 64 KiB of budget, within [64, 65536]
     s->max_slots = (int)std::min<size_t>(65536, std::max<size_t>(64, mem_budget / 65536));
@@ -416,6 +474,14 @@ int pso_server_create(size_t mem_budget, int64_t chunk_updates, pso_server **out
         return pso_internal_fail(PSO_EDEVICE, "device query failed");
     }
     s->grid_cap = capacity / STREAMS;
+    {
+        const char *env = getenv("PSO_SERVER_STAGED");
+        int cap_staged = 0;
+        if (!(env && !strcmp(env, "0")) &&
+            pso::batch_capacity(MAX_SERVER_D, SERVER_STAGE_LANES, &cap_staged, SERVER_STAGE_KIB) == hipSuccess &&
+            cap_staged >= STREAMS)
+            s->grid_cap_staged = cap_staged / STREAMS;
+    }
     {
         int dev = 0, khz = 0;
         if (hipGetDevice(&dev) == hipSuccess &&
@@ -471,7 +537,12 @@ int pso_server_submit(pso_server *s, const pso_desc *d, uint64_t *ticket)
     if (d->shift) std::memcpy(r->shift.data(), d->shift, sizeof(float) * d->D);
     r->d.shift = nullptr;
     r->t_submit = Clock::now();
-    r->parts = pso::parts_for((uint64_t)d->N, d->D, s->grid_cap, pso::DEFAULT_BATCH_SHAPE);
+    const uint32_t staged_parts =
+        s->grid_cap_staged > 0
+            ? pso::staged_parts((uint64_t)d->N, d->D, d->fitness_id, SERVER_STAGE_KIB, s->grid_cap_staged)
+            : 0;
+    r->staged = staged_parts > 0;
+    r->parts = r->staged ? staged_parts : pso::parts_for((uint64_t)d->N, d->D, s->grid_cap, pso::DEFAULT_BATCH_SHAPE);
     const size_t bytes = pso::layout_of((uint64_t)d->N, d->D, false).total + pso::gang_bytes(r->parts, d->D);
     std::lock_guard<std::mutex> g(s->mu);
     r->ticket = s->next_ticket++;

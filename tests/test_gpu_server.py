@@ -43,9 +43,20 @@ def check_same(specs, tickets, res):
         assert np.array_equal(r["gbest_pos"], a["gbest_pos"]), sp
 
 
-def test_results_equal_alone_with_staggered_arrivals():
+@pytest.fixture(params=["staged", "streamed"])
+def server_mode(request, monkeypatch):
+    """Requests that fit run in LDS-staged launches by default; the other
+    mode streams every request (PSO_SERVER_STAGED=0)."""
+    if request.param == "streamed":
+        monkeypatch.setenv("PSO_SERVER_STAGED", "0")
+    else:
+        monkeypatch.delenv("PSO_SERVER_STAGED", raising=False)
+    return request.param
+
+
+def test_results_equal_alone_with_staggered_arrivals(server_mode):
     specs = mixed_specs(120, 11, max_iter=300)
-    announce("server: 120 staggered requests")
+    announce(f"server ({server_mode}): 120 staggered requests")
     with pso.Server(1 << 30, chunk_updates=20000) as srv:
         tickets = []
         for k, sp in enumerate(specs):
@@ -112,11 +123,25 @@ def test_submit_from_two_threads():
     check_same(specs[:10], tickets[:10], res)
 
 
-def test_large_requests_split_into_parts():
+def test_large_requests_split_into_parts(server_mode):
     specs = [wl.SwarmSpec("rastrigin", 40000, 24, 40, seed=k, shift_amplitude=1.0) for k in range(3)]
     specs += mixed_specs(20, 13, max_iter=60)
-    announce("server with multi-part requests")
+    announce(f"server ({server_mode}) with multi-part requests")
     with pso.Server(1 << 30, chunk_updates=1 << 21) as srv:
         tickets = [srv.submit(sp) for sp in specs]
         res = wait_all(srv, tickets)
+    check_same(specs, tickets, res)
+
+
+def test_staged_and_streamed_requests_mixed():
+    """Requests too large to stage (their parts would outnumber a staged
+    launch's workgroups) run in streamed launches while the others run
+    staged; every result equals the swarm alone."""
+    specs = [wl.SwarmSpec("sphere", 300000, 32, 12, seed=21, shift_amplitude=1.0),
+             wl.SwarmSpec("ackley", 150001, 40, 10, seed=22, shift_amplitude=1.0)]
+    specs += mixed_specs(40, 14, max_iter=80)
+    announce("server: staged and streamed requests")
+    with pso.Server(1 << 31, chunk_updates=1 << 22) as srv:
+        tickets = [srv.submit(sp) for sp in specs]
+        res = wait_all(srv, tickets, timeout=240.0)
     check_same(specs, tickets, res)
