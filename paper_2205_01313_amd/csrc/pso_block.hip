@@ -16,6 +16,8 @@
 // iteration limit or stop rule, writes the result, and takes the next; every
 // workgroup exits when the counter passes the swarm count.
 #include <algorithm>
+#include <cstdlib>
+#include <cstring>
 
 #include "pso_block.hpp"
 #include "pso_quad.hpp"
@@ -460,83 +462,97 @@ size_t staged_quad_bytes(int D, int fitness)
     return 4 * (sizeof(float) * (3 + staged_words(fitness)) * (size_t)D + sizeof(float) + 1);
 }
 
-template <int FIT, int LANES>
-__device__ void staged_part(const BatchItem &it, uint32_t part, uint32_t fixed_iters, BatchResult *res,
-                            long long chunk, long long iter_cap, float *s_g, float *s_shift, Scratch *sc,
-                            float *s_state, BatchResult *out_state, float *out_pos, uint32_t out, int pos_stride)
+// A staged part's view in LDS: x, v, p, the fitness terms (W words) in rows
+// of `pitch` particles, then pf and the pending marks; local quad q is
+// particle ibase + 4q + k (the part holds quads [q_lo, q_lo + nql)).
+struct Staged {
+    SwarmArgs la;
+    float *t0, *t1;
+    uint32_t nql, pitch, ibase, q_lo;
+};
+
+template <int FIT>
+__device__ __forceinline__ Staged staged_view(const SwarmArgs &a, float *s_state, uint32_t q_lo, uint32_t q_hi)
 {
     constexpr int W = Fitness<FIT>::STAGE_WORDS;
-    static_assert(W == staged_words(FIT), "staged LDS sizing");
-    const SwarmArgs &a = it.a;
-    const int D = a.D;
-    const size_t Np = a.Np;
-    const uint32_t nq = (a.N + 3) / 4, nqi = a.Np / 4;
-    Part P;
-    P.parts = it.parts;
-    P.part = part;
-    P.q_lo = (uint32_t)((unsigned long long)nq * part / it.parts);
-    P.q_hi = (uint32_t)((unsigned long long)nq * (part + 1) / it.parts);
-    P.qi_lo = P.q_lo;
-    P.qi_hi = part + 1 == it.parts ? nqi : P.q_hi;
-    P.gang = it.gang;
-    P.cand_key = it.cand_key;
-    P.cand_pos = it.cand_pos;
-    const uint32_t nql = P.q_hi - P.q_lo, pitch = 4 * nql, ibase = 4 * P.q_lo;
-    for (int d = threadIdx.x; d < D; d += LANES) s_shift[d] = a.shift[d];
-    if (threadIdx.x == 0) {
-        sc->min[0] = NO_KEY;
-        sc->min[1] = NO_KEY;
-    }
-    SwarmLoop L;
-    const bool started = res->started != 0u;
-    __syncthreads();
-    if (!started) {
-        L.stop = false;
-        block_init<FIT, LANES>(a, P, s_shift, s_g, sc, L);
-    } else {
-        L.gkey = res->gkey;
-        L.giter = res->giter;
-        L.t = res->iters;
-        L.stop = res->stop != 0u;
-        for (int d = threadIdx.x; d < D; d += LANES) s_g[d] = a.gpos[d];
-    }
-    // the part's view in LDS: rows of `pitch` particles, local quad q is
-    // particle ibase + 4q + k
-    SwarmArgs la = a;
-    la.x = s_state;
-    la.v = la.x + (size_t)D * pitch;
-    la.p = la.v + (size_t)D * pitch;
-    float *s_t0 = la.p + (size_t)D * pitch, *s_t1 = s_t0 + (size_t)D * pitch;
-    la.pf = s_t0 + (size_t)W * D * pitch;
-    la.pend = reinterpret_cast<uint8_t *>(la.pf + pitch);
-    la.Np = pitch;
-    for (uint32_t e = threadIdx.x; e < (uint32_t)D * nql; e += LANES) {
+    Staged S;
+    S.q_lo = q_lo;
+    S.nql = q_hi - q_lo;
+    S.pitch = 4 * S.nql;
+    S.ibase = 4 * q_lo;
+    const size_t plane = (size_t)a.D * S.pitch;
+    S.la = a;
+    S.la.x = s_state;
+    S.la.v = S.la.x + plane;
+    S.la.p = S.la.v + plane;
+    S.t0 = S.la.p + plane;
+    S.t1 = S.t0 + plane;
+    S.la.pf = S.t0 + (size_t)W * plane;
+    S.la.pend = reinterpret_cast<uint8_t *>(S.la.pf + S.pitch);
+    S.la.Np = S.pitch;
+    return S;
+}
+
+// Device memory -> LDS (ends with a barrier); LDS -> device memory (pending
+// marks included, so the stored state means what the streamed paths store).
+template <int LANES>
+__device__ void staged_load(const SwarmArgs &a, const Staged &S)
+{
+    const uint32_t nql = S.nql;
+    for (uint32_t e = threadIdx.x; e < (uint32_t)a.D * nql; e += LANES) {
         const uint32_t d = e / nql, q = e - d * nql;
-        const size_t g = (size_t)d * Np / 4 + P.q_lo + q, l = (size_t)d * nql + q;
-        reinterpret_cast<f4 *>(la.x)[l] = reinterpret_cast<const f4 *>(a.x)[g];
-        reinterpret_cast<f4 *>(la.v)[l] = reinterpret_cast<const f4 *>(a.v)[g];
-        reinterpret_cast<f4 *>(la.p)[l] = reinterpret_cast<const f4 *>(a.p)[g];
+        const size_t g = (size_t)d * a.Np / 4 + S.q_lo + q, l = (size_t)d * nql + q;
+        reinterpret_cast<f4 *>(S.la.x)[l] = reinterpret_cast<const f4 *>(a.x)[g];
+        reinterpret_cast<f4 *>(S.la.v)[l] = reinterpret_cast<const f4 *>(a.v)[g];
+        reinterpret_cast<f4 *>(S.la.p)[l] = reinterpret_cast<const f4 *>(a.p)[g];
     }
     for (uint32_t q = threadIdx.x; q < nql; q += LANES) {
-        reinterpret_cast<f4 *>(la.pf)[q] = reinterpret_cast<const f4 *>(a.pf)[P.q_lo + q];
-        reinterpret_cast<uint32_t *>(la.pend)[q] = reinterpret_cast<const uint32_t *>(a.pend)[P.q_lo + q];
+        reinterpret_cast<f4 *>(S.la.pf)[q] = reinterpret_cast<const f4 *>(a.pf)[S.q_lo + q];
+        reinterpret_cast<uint32_t *>(S.la.pend)[q] = reinterpret_cast<const uint32_t *>(a.pend)[S.q_lo + q];
     }
     __syncthreads();
+}
 
-    const long long left = it.max_iter - L.t;
-    const long long nd = (long long)a.N * a.D;
-    long long iters = chunk / nd;
-    iters = iters < 1 ? 1 : (iters > iter_cap ? iter_cap : iters);
-    if (fixed_iters > 0) iters = fixed_iters;
-    const long long T = left < iters ? left : iters;
-    const unsigned long long c0 = wall_clock64();
+template <int LANES>
+__device__ void staged_store(const SwarmArgs &a, const Staged &S)
+{
+    const uint32_t nql = S.nql;
+    for (uint32_t e = threadIdx.x; e < (uint32_t)a.D * nql; e += LANES) {
+        const uint32_t d = e / nql, q = e - d * nql;
+        const size_t g = (size_t)d * a.Np / 4 + S.q_lo + q, l = (size_t)d * nql + q;
+        reinterpret_cast<f4 *>(a.x)[g] = reinterpret_cast<const f4 *>(S.la.x)[l];
+        reinterpret_cast<f4 *>(a.v)[g] = reinterpret_cast<const f4 *>(S.la.v)[l];
+        reinterpret_cast<f4 *>(a.p)[g] = reinterpret_cast<const f4 *>(S.la.p)[l];
+    }
+    for (uint32_t q = threadIdx.x; q < nql; q += LANES) {
+        reinterpret_cast<f4 *>(a.pf)[S.q_lo + q] = reinterpret_cast<const f4 *>(S.la.pf)[q];
+        reinterpret_cast<uint32_t *>(a.pend)[S.q_lo + q] = reinterpret_cast<const uint32_t *>(S.la.pend)[q];
+    }
+}
+
+// Up to T iterations of a staged part after L.t, stopping after the first
+// iteration at which the stop rule (tol, fstar) holds (tested before the
+// first one too); a part of several meets the others every iteration.
+// hist (may be null) receives each iteration's gbest key.  Returns this
+// lane's pbest improvements.
+template <int FIT, int LANES>
+__device__ uint32_t staged_iterate(const SwarmArgs &a, const Staged &S, const Part &P, long long T, float tol,
+                                   float fstar, float *s_g, const float *s_shift, Scratch *sc,
+                                   unsigned long long *hist, SwarmLoop &L)
+{
+    constexpr int W = Fitness<FIT>::STAGE_WORDS;
+    const int D = a.D;
+    const SwarmArgs &la = S.la;
+    float *s_t0 = S.t0, *s_t1 = S.t1;
+    const uint32_t pitch = S.pitch, ibase = S.ibase;
     const uint32_t npairs = (uint32_t)(D + 1) / 2;
+    uint32_t n_imp = 0;
     // Without a stop rule every iteration of the launch runs, so a part of
     // several can compute the gbest-independent half of the next iteration's
     // Eq. 1 -- the Philox draws, (w v) + ((c1 r1)(p - x)) into v's slot and
     // c2 r2 into the first term slot, the pending pbest positions copied --
     // while the other parts arrive, and finish it once the gbest is known.
-    const bool split = P.parts > 1 && !(it.tol > 0.0f);
+    const bool split = P.parts > 1 && !(tol > 0.0f);
     auto own_half = [&](uint32_t tn) {
         for (GridWalk<LANES> gw(pitch); gw.row < npairs; gw.next()) {
             const uint32_t pr = gw.row, sidx = gw.col;
@@ -555,7 +571,7 @@ __device__ void staged_part(const BatchItem &it, uint32_t part, uint32_t fixed_i
             }
         }
     };
-    L.stop = L.stop || meets_tol(L.gkey, it.tol, it.fstar);
+    L.stop = L.stop || meets_tol(L.gkey, tol, fstar);
     if (split && T > 0 && !L.stop) own_half((uint32_t)(L.t + 1));
     for (long long n = 0; n < T && !L.stop; ++n) {
         const uint32_t t = (uint32_t)(L.t + 1);
@@ -614,6 +630,7 @@ __device__ void staged_part(const BatchItem &it, uint32_t part, uint32_t fixed_i
                     la.pf[sidx] = f;
                     const unsigned long long kk = make_key(f, i);
                     key = kk < key ? kk : key;
+                    ++n_imp;
                 }
             }
             la.pend[sidx] = imp ? 1 : 0;
@@ -638,23 +655,62 @@ __device__ void staged_part(const BatchItem &it, uint32_t part, uint32_t fixed_i
                 gather_gbest<LANES>(a, P, t, g, owner, s_g);
             }
         }
+        if (hist && threadIdx.x == 0) hist[t & (HIST_CAP - 1)] = L.gkey;
         L.t = t;
-        L.stop = meets_tol(L.gkey, it.tol, it.fstar);
+        L.stop = meets_tol(L.gkey, tol, fstar);
         __syncthreads();
     }
+    return n_imp;
+}
+
+template <int FIT, int LANES>
+__device__ void staged_part(const BatchItem &it, uint32_t part, uint32_t fixed_iters, BatchResult *res,
+                            long long chunk, long long iter_cap, float *s_g, float *s_shift, Scratch *sc,
+                            float *s_state, BatchResult *out_state, float *out_pos, uint32_t out, int pos_stride)
+{
+    static_assert(Fitness<FIT>::STAGE_WORDS == staged_words(FIT), "staged LDS sizing");
+    const SwarmArgs &a = it.a;
+    const int D = a.D;
+    const uint32_t nq = (a.N + 3) / 4, nqi = a.Np / 4;
+    Part P;
+    P.parts = it.parts;
+    P.part = part;
+    P.q_lo = (uint32_t)((unsigned long long)nq * part / it.parts);
+    P.q_hi = (uint32_t)((unsigned long long)nq * (part + 1) / it.parts);
+    P.qi_lo = P.q_lo;
+    P.qi_hi = part + 1 == it.parts ? nqi : P.q_hi;
+    P.gang = it.gang;
+    P.cand_key = it.cand_key;
+    P.cand_pos = it.cand_pos;
+    for (int d = threadIdx.x; d < D; d += LANES) s_shift[d] = a.shift[d];
+    if (threadIdx.x == 0) {
+        sc->min[0] = NO_KEY;
+        sc->min[1] = NO_KEY;
+    }
+    SwarmLoop L;
+    const bool started = res->started != 0u;
+    __syncthreads();
+    if (!started) {
+        L.stop = false;
+        block_init<FIT, LANES>(a, P, s_shift, s_g, sc, L);
+    } else {
+        L.gkey = res->gkey;
+        L.giter = res->giter;
+        L.t = res->iters;
+        L.stop = res->stop != 0u;
+        for (int d = threadIdx.x; d < D; d += LANES) s_g[d] = a.gpos[d];
+    }
+    const Staged S = staged_view<FIT>(a, s_state, P.q_lo, P.q_hi);
+    staged_load<LANES>(a, S);
+    const long long left = it.max_iter - L.t;
+    const long long nd = (long long)a.N * a.D;
+    long long iters = chunk / nd;
+    iters = iters < 1 ? 1 : (iters > iter_cap ? iter_cap : iters);
+    if (fixed_iters > 0) iters = fixed_iters;
+    const unsigned long long c0 = wall_clock64();
+    staged_iterate<FIT, LANES>(a, S, P, left < iters ? left : iters, it.tol, it.fstar, s_g, s_shift, sc, nullptr, L);
     const unsigned long long ticks = wall_clock64() - c0;
-    // the state back to device memory (pending marks included)
-    for (uint32_t e = threadIdx.x; e < (uint32_t)D * nql; e += LANES) {
-        const uint32_t d = e / nql, q = e - d * nql;
-        const size_t g = (size_t)d * Np / 4 + P.q_lo + q, l = (size_t)d * nql + q;
-        reinterpret_cast<f4 *>(a.x)[g] = reinterpret_cast<const f4 *>(la.x)[l];
-        reinterpret_cast<f4 *>(a.v)[g] = reinterpret_cast<const f4 *>(la.v)[l];
-        reinterpret_cast<f4 *>(a.p)[g] = reinterpret_cast<const f4 *>(la.p)[l];
-    }
-    for (uint32_t q = threadIdx.x; q < nql; q += LANES) {
-        reinterpret_cast<f4 *>(a.pf)[P.q_lo + q] = reinterpret_cast<const f4 *>(la.pf)[q];
-        reinterpret_cast<uint32_t *>(a.pend)[P.q_lo + q] = reinterpret_cast<const uint32_t *>(la.pend)[q];
-    }
+    staged_store<LANES>(a, S);
     if (part == 0) {
         for (int d = threadIdx.x; d < D; d += LANES) {
             a.gpos[d] = s_g[d];
@@ -669,6 +725,51 @@ __device__ void staged_part(const BatchItem &it, uint32_t part, uint32_t fixed_i
             res->ticks = ticks > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)ticks;
             if (out_state) out_state[out] = *res;
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// A single swarm's run with its whole state staged in one workgroup's LDS:
+// k_block_run with the staged iteration (the pso_run path for swarms that
+// fit; continues from and updates the control block).
+// ---------------------------------------------------------------------------
+template <int FIT, int LANES>
+__global__ void __launch_bounds__(LANES) k_block_run_staged(SwarmArgs a, long long T)
+{
+    __shared__ Scratch sc;
+    extern __shared__ float s_dyn[]; // gbest position, shift (D floats each, rounded up to 16 bytes), state
+    Ctrl *c = a.ctrl;
+    const int D = a.D;
+    const int head = (D + 3) & ~3;
+    float *s_g = s_dyn, *s_shift = s_dyn + head, *s_state = s_dyn + 2 * head;
+    for (int d = threadIdx.x; d < D; d += LANES) {
+        s_g[d] = a.gpos[d];
+        s_shift[d] = a.shift[d];
+    }
+    if (threadIdx.x == 0) {
+        sc.min[0] = NO_KEY;
+        sc.min[1] = NO_KEY;
+        sc.err = 0;
+    }
+    SwarmLoop L;
+    L.gkey = c->gkey_prev;
+    L.giter = c->giter;
+    L.t = c->t;
+    L.stop = c->stop != 0u;
+    const float tol = c->tol, fstar = c->fstar;
+    const Staged S = staged_view<FIT>(a, s_state, 0, (a.N + 3) / 4);
+    staged_load<LANES>(a, S); // ends with a barrier (s_g, s_shift, sc too)
+    const uint32_t n_imp = staged_iterate<FIT, LANES>(a, S, whole_swarm(a), T, tol, fstar, s_g, s_shift, &sc, a.hist, L);
+    staged_store<LANES>(a, S);
+    if (n_imp) atomicAdd(&c->improved, (unsigned long long)n_imp);
+    for (int d = threadIdx.x; d < D; d += LANES) a.gpos[d] = s_g[d];
+    if (threadIdx.x == 0) {
+        c->gkey = L.gkey;
+        c->gkey_prev = L.gkey;
+        c->pubkey = L.gkey;
+        c->giter = L.giter;
+        c->t = L.t;
+        c->stop = L.stop ? 1u : 0u;
     }
 }
 
@@ -804,8 +905,60 @@ void bind_gang(BatchItem *it, void *region, uint32_t parts)
 // ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
+// LDS bytes of k_block_run_staged for a swarm, or 0 when it does not fit
+// one workgroup (or PSO_BLOCK_STAGED=0 in the environment).
+static int device_lds_max()
+{
+    static const int lds_max = [] {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+            return 0;
+        return v;
+    }();
+    return lds_max;
+}
+
+static size_t block_staged_lds(int fitness, const SwarmArgs &a)
+{
+    const int lds_max = device_lds_max();
+    const char *env = getenv("PSO_BLOCK_STAGED");
+    if (env && !strcmp(env, "0")) return 0;
+    const size_t lds = sizeof(float) * 2 * (((size_t)a.D + 3) & ~(size_t)3) +
+                       (size_t)((a.N + 3) / 4) * staged_quad_bytes(a.D, fitness);
+    return lds + 1024 <= (size_t)lds_max ? lds : 0;
+}
+
+template <int FIT>
+static hipError_t launch_block_staged(const SwarmArgs &a, long long T, size_t lds, hipStream_t stream)
+{
+    // 256 lanes while a swarm's (particle, dimension pair) items fill them,
+    // else 1024
+    const uint64_t items = (uint64_t)4 * ((a.N + 3) / 4) * (uint64_t)((a.D + 1) / 2);
+    const void *f = items <= 256 ? reinterpret_cast<const void *>(k_block_run_staged<FIT, 256>)
+                                 : reinterpret_cast<const void *>(k_block_run_staged<FIT, 1024>);
+    // the most any swarm may ask for, so concurrent callers never lower it
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, device_lds_max() - 1024);
+    if (e != hipSuccess) return e;
+    if (items <= 256)
+        hipLaunchKernelGGL((k_block_run_staged<FIT, 256>), dim3(1), dim3(256), lds, stream, a, T);
+    else
+        hipLaunchKernelGGL((k_block_run_staged<FIT, 1024>), dim3(1), dim3(1024), lds, stream, a, T);
+    return hipGetLastError();
+}
+
 hipError_t launch_block_run(int fitness, const SwarmArgs &a, long long T, hipStream_t stream)
 {
+    if (const size_t lds_s = block_staged_lds(fitness, a)) {
+        switch (fitness) {
+        case F_SPHERE: return launch_block_staged<F_SPHERE>(a, T, lds_s, stream);
+        case F_RASTRIGIN: return launch_block_staged<F_RASTRIGIN>(a, T, lds_s, stream);
+        case F_ROSENBROCK: return launch_block_staged<F_ROSENBROCK>(a, T, lds_s, stream);
+        case F_ACKLEY: return launch_block_staged<F_ACKLEY>(a, T, lds_s, stream);
+        case F_CUBIC: return launch_block_staged<F_CUBIC>(a, T, lds_s, stream);
+        default: return hipErrorInvalidValue;
+        }
+    }
     const size_t lds = 2 * sizeof(float) * a.D;
     switch (fitness) {
     case F_SPHERE: hipLaunchKernelGGL(k_block_run<F_SPHERE>, dim3(1), dim3(RUN_LANES), lds, stream, a, T); break;
