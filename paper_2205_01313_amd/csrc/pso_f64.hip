@@ -164,15 +164,30 @@ __device__ void wg_lexmin(unsigned long long &k, uint32_t &i, unsigned long long
         const uint32_t i2 = __shfl_xor(i, off, 64);
         lexmin(k, i, k2, i2);
     }
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
+    constexpr int NW = LANES / 64; // wavefronts, a power of two
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) {
         s_k[w] = k;
         s_i[w] = i;
     }
     __syncthreads();
-    k = s_k[0];
-    i = s_i[0];
-    for (int u = 1; u < LANES / 64; ++u) lexmin(k, i, s_k[u], s_i[u]);
+    if constexpr (NW > 1) {
+        // every wavefront reduces the NW wavefront minima in its first NW
+        // lanes (one LDS read each, then a butterfly) and broadcasts lane 0's
+        k = lane < NW ? s_k[lane] : ~0ull;
+        i = lane < NW ? s_i[lane] : NO_IDX;
+#pragma unroll
+        for (int off = NW / 2; off >= 1; off >>= 1) {
+            const unsigned long long k2 = __shfl_xor(k, off, 64);
+            const uint32_t i2 = __shfl_xor(i, off, 64);
+            lexmin(k, i, k2, i2);
+        }
+        k = __shfl(k, 0, 64);
+        i = __shfl(i, 0, 64);
+    } else {
+        k = s_k[0];
+        i = s_i[0];
+    }
     __syncthreads();
 }
 
