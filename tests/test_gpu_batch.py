@@ -221,3 +221,27 @@ def test_graph_replays_equal_the_direct_launch(monkeypatch):
             x = torch.ones(1 << 20, device="cuda")
             torch.cuda.synchronize()
             assert float(x.sum()) == float(1 << 20)
+
+
+def test_full_batched_workload_sampled_against_oracle():
+    """The batched workload at full size (4096 swarms, N log-uniform in
+    [32, 8192], D in {2..64}, 500 iterations) in the launch configuration the
+    benchmark times (the default shape: LDS-staged where every swarm fits):
+    sampled swarms -- the largest and smallest state, and one of each fitness
+    function -- equal the oracle bit for bit."""
+    specs = wl.batch_specs()
+    announce("full batched workload, 4096 swarms x 500 iterations")
+    with pso.Batch(specs) as b:
+        assert b.shape["stage_kib"] > 0
+        b.launch()
+        res = b.results()
+    sizes = [sp.N * sp.D for sp in specs]
+    picks = {int(np.argmax(sizes)), int(np.argmin(sizes))}
+    for fit in ("sphere", "rastrigin", "rosenbrock", "ackley"):
+        picks.add(next(k for k, sp in enumerate(specs) if sp.fitness == fit and 20000 < sp.N * sp.D < 60000))
+    for k in sorted(picks):
+        sp, r = specs[k], res[k]
+        o = oracle_swarm(sp, nthreads=16).run_f32(sp.T)
+        assert r["iters"] == sp.T == o["iters"], k
+        assert r["gbest_fit"] == o["gbest_fit"] and r["gbest_iter"] == o["giter"], (k, sp.fitness, sp.N, sp.D)
+        assert np.array_equal(r["gbest_pos"], o["gpos"]), k
