@@ -145,3 +145,19 @@ def test_staged_and_streamed_requests_mixed():
         tickets = [srv.submit(sp) for sp in specs]
         res = wait_all(srv, tickets, timeout=240.0)
     check_same(specs, tickets, res)
+
+
+def test_serving_workload_burst_sampled_against_alone():
+    """Requests of the serving workload (N log-normal, median 512, up to
+    16 384; D in [2, 64]; stop at |gbest| < 1e-4 or 1000 iterations) arriving
+    as one burst, the saturated case of the benchmark: every request
+    completes, and sampled results equal the swarm run alone."""
+    specs = wl.serving_specs(300, seed=5)
+    announce("server: 300-request burst of the serving workload")
+    with pso.Server(4 << 30) as srv:
+        tickets = [srv.submit(sp) for sp in specs]
+        res = wait_all(srv, tickets, timeout=240.0)
+        st = srv.stats()
+    assert st["completed"] == len(specs) and st["rejected"] == 0
+    sample = list(range(0, len(specs), 23))
+    check_same([specs[k] for k in sample], [tickets[k] for k in sample], res)
