@@ -929,6 +929,13 @@ static size_t block_staged_lds(int fitness, const SwarmArgs &a)
     return lds + 1024 <= (size_t)lds_max ? lds : 0;
 }
 
+bool block_run_suits(int fitness, const SwarmArgs &a)
+{
+    const char *env = getenv("PSO_BLOCK_STAGED");
+    if (env && !strcmp(env, "0")) return true; // the unstaged one-workgroup run, for tests
+    return block_staged_lds(fitness, a) > 0;
+}
+
 template <int FIT>
 static hipError_t launch_block_staged(const SwarmArgs &a, long long T, size_t lds, hipStream_t stream)
 {

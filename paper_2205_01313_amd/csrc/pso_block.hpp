@@ -96,8 +96,13 @@ struct BatchEntry {
 };
 
 // Runs up to T more iterations of one swarm in one workgroup, continuing from
-// and updating its control block (stop rule included).
+// and updating its control block (stop rule included): its state staged in
+// LDS where it fits (or PSO_BLOCK_STAGED=0 in the environment), else read
+// from device memory every iteration.
 hipError_t launch_block_run(int fitness, const SwarmArgs &a, long long T, hipStream_t stream);
+// Whether a pso_run of this swarm should take the one-workgroup run: its
+// state fits one workgroup's LDS (always true under PSO_BLOCK_STAGED=0).
+bool block_run_suits(int fitness, const SwarmArgs &a);
 
 // Marks results[0..count) not started (and their gangs unused); clears the
 // work counter.

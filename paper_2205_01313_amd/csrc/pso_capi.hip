@@ -45,9 +45,15 @@ int fail(int code, const char *fmt, ...)
 
 constexpr int32_t MAX_D = 4096;
 
-// A synchronous swarm of at most this many particle-dimensions runs its
-// pso_run iterations in one workgroup (one launch for the whole run) instead
-// of one grid launch per iteration.
+// A synchronous swarm of at most this many particle-dimensions whose state
+// fits one workgroup's LDS runs its pso_run iterations in one workgroup (one
+// launch for the whole run) instead of one grid launch per iteration.  A
+// workgroup reading the state from device memory every iteration loses to
+// the launches wherever the state does not fit (us per iteration, one
+// workgroup / launches: Cubic 1D N = 16 384: 19.0 / 5.3, N = 8192: 9.7 /
+// 5.2; Rastrigin D = 8, N = 2048: 13.7 / 10.7; D = 128, N = 512: 99.8 /
+// 14.0; Ackley D = 32, N = 1024: 26.2 / 9.8), so it runs only under
+// PSO_BLOCK_STAGED=0 (tests compare the two one-workgroup kernels).
 #ifndef PSO_BLOCK_RUN_MAX_ND
 #define PSO_BLOCK_RUN_MAX_ND 65536
 #endif
@@ -291,7 +297,8 @@ int pso_run(pso_swarm *s, int64_t max_iter, float tol, float f_star, float *gbes
     if (max_iter < 0) return fail(PSO_EINVAL, "max_iter < 0");
     if (std::isnan(tol) || std::isnan(f_star)) return fail(PSO_EINVAL, "tol and f_star must not be NaN");
     HIP_TRY(pso::launch_arm(s->args, tol, f_star, s->stream));
-    const bool block_path = s->variant == PSO_SYNC && int64_t(s->N) * s->D <= BLOCK_RUN_MAX_ND;
+    const bool block_path = s->variant == PSO_SYNC && int64_t(s->N) * s->D <= BLOCK_RUN_MAX_ND &&
+                            pso::block_run_suits(s->fitness, s->args);
     if (s->variant == PSO_PERSISTENT) {
         int rc = persistent_launch(s, max_iter);
         if (rc) return rc;
