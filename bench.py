@@ -250,8 +250,9 @@ def batched_leg(pso, torch, wl, stream, subset=96):
     functions with shifts, 500 iterations) in one persistent launch, its
     shape (lanes, workgroups, part size, LDS staging) picked by the
     autotuner, and the streamed kernel's time on the same batch; and a
-    spread subset run both as a batch and as a plain loop of pso_run calls
-    (one swarm after another, allocation outside the timed loop)."""
+    spread subset run as a batch, as the plain loop (one swarm after
+    another, one launch per iteration) and as a loop of pso_run calls
+    (allocation outside the timed loops; all three give the same results)."""
     specs = wl.batch_specs()
     with pso.Batch(specs, stream=stream) as b:
         default_shape = b.shape
@@ -279,18 +280,34 @@ def batched_leg(pso, torch, wl, stream, subset=96):
         rb = b.results()
     swarms = [pso.Swarm(sp.fitness, sp.N, sp.D, sp.box, sp.w, sp.c1, sp.c2, sp.vmax, sp.seed, shift=sp.shift)
               for sp in sub]
+    # the plain loop: one swarm after another, one launch per iteration
+    for sw in swarms:
+        sw.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for sw, sp in zip(swarms, sub):
+        sw.step(sp.T)
+        sw.sync()
+    ms_plain = (time.perf_counter() - t0) * 1e3
+    rs = [sw.best() for sw in swarms]
+    # and one pso_run per swarm (one staged workgroup for the small swarms)
+    for sw in swarms:
+        sw.reset()
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     rp = [sw.run(sp.T) for sw, sp in zip(swarms, sub)]
-    ms_plain = (time.perf_counter() - t0) * 1e3
+    ms_run = (time.perf_counter() - t0) * 1e3
     for sw in swarms:
         sw.close()
-    same = all(a["gbest_fit"] == c["gbest_fit"] and (a["gbest_pos"] == c["gbest_pos"]).all() for a, c in zip(rb, rp))
+    same = all(a["gbest_fit"] == c["gbest_fit"] == d["gbest_fit"] and (a["gbest_pos"] == c["gbest_pos"]).all()
+               and (a["gbest_pos"] == d["gbest_pos"]).all() for a, c, d in zip(rb, rp, rs))
     return dict(swarms=len(specs), iterations=500, ms=ms, value=updates / (ms / 1e3), unit="particle·dim updates/s",
                 autotuned_shape=shape, autotune_s=tune_s, default_shape=default_shape,
                 streamed_ms=ms_streamed, streamed_shape=dict(lanes=128, grid=0, part_work=1 << 17, stage_kib=0),
                 streamed_equal_results=bool(same_streamed),
                 subset=len(sub), subset_batched_ms=ms_sub, subset_plain_loop_ms=ms_plain,
-                batched_vs_plain_speedup=ms_plain / ms_sub, equal_results=bool(same))
+                batched_vs_plain_speedup=ms_plain / ms_sub, subset_pso_run_loop_ms=ms_run,
+                batched_vs_pso_run_loop_speedup=ms_run / ms_sub, equal_results=bool(same))
 
 
 def serving_leg(pso, wl, rates=(2000, 10000, 50000), count=2000, budget=32 << 30, chunk=0):

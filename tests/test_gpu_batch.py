@@ -227,8 +227,8 @@ def test_full_batched_workload_sampled_against_oracle():
     """The batched workload at full size (4096 swarms, N log-uniform in
     [32, 8192], D in {2..64}, 500 iterations) in the launch configuration the
     benchmark times (the default shape: LDS-staged where every swarm fits):
-    sampled swarms -- the largest and smallest state, and one of each fitness
-    function -- equal the oracle bit for bit."""
+    a 256-swarm subset -- every 16th swarm, plus the largest and smallest
+    state -- equals the oracle bit for bit."""
     specs = wl.batch_specs()
     announce("full batched workload, 4096 swarms x 500 iterations")
     with pso.Batch(specs) as b:
@@ -236,9 +236,7 @@ def test_full_batched_workload_sampled_against_oracle():
         b.launch()
         res = b.results()
     sizes = [sp.N * sp.D for sp in specs]
-    picks = {int(np.argmax(sizes)), int(np.argmin(sizes))}
-    for fit in ("sphere", "rastrigin", "rosenbrock", "ackley"):
-        picks.add(next(k for k, sp in enumerate(specs) if sp.fitness == fit and 20000 < sp.N * sp.D < 60000))
+    picks = set(range(0, len(specs), 16)) | {int(np.argmax(sizes)), int(np.argmin(sizes))}
     for k in sorted(picks):
         sp, r = specs[k], res[k]
         o = oracle_swarm(sp, nthreads=16).run_f32(sp.T)
