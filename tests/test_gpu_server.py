@@ -9,7 +9,7 @@ import pytest
 
 import paper_2205_01313_amd as pso
 from paper_2205_01313_amd import workloads as wl
-from tests.gpu_util import announce, gpu_swarm
+from tests.gpu_util import announce, gpu_swarm, oracle_swarm
 from tests.test_gpu_batch import mixed_specs
 
 pytestmark = pytest.mark.gpu
@@ -151,7 +151,8 @@ def test_serving_workload_burst_sampled_against_alone():
     """Requests of the serving workload (N log-normal, median 512, up to
     16 384; D in [2, 64]; stop at |gbest| < 1e-4 or 1000 iterations) arriving
     as one burst, the saturated case of the benchmark: every request
-    completes, and sampled results equal the swarm run alone."""
+    completes, sampled results equal the swarm run alone, and the oracle
+    replays half of that sample."""
     specs = wl.serving_specs(300, seed=5)
     announce("server: 300-request burst of the serving workload")
     with pso.Server(4 << 30) as srv:
@@ -161,3 +162,9 @@ def test_serving_workload_burst_sampled_against_alone():
     assert st["completed"] == len(specs) and st["rejected"] == 0
     sample = list(range(0, len(specs), 23))
     check_same([specs[k] for k in sample], [tickets[k] for k in sample], res)
+    # and the oracle replays part of the sample
+    for k in sample[::2]:
+        sp, r = specs[k], res[tickets[k]]
+        o = oracle_swarm(sp, nthreads=16).run_f32(sp.T, tol=sp.tol, f_star=sp.f_star)
+        assert r["iters"] == o["iters"] and r["gbest_fit"] == o["gbest_fit"], (k, sp.fitness, sp.N, sp.D)
+        assert r["gbest_iter"] == o["giter"] and np.array_equal(r["gbest_pos"], o["gpos"]), k
