@@ -343,8 +343,8 @@ typedef struct pso_server_counters {
  * (allocated now).  Each launch gives each of its swarms the iterations
  * that fit a 2 ms slice at the swarm's own measured speed (4 on its first
  * launch), at most chunk_updates particle-dimension updates' worth (<= 0: no
- * such cap).  A request whose state fits runs in LDS-staged launches (its
- * state in LDS during each launch), others in streamed ones; a launch is of
+ * such cap).  A request with D <= 64 whose state fits runs in LDS-staged
+ * launches (its state in LDS during each launch), others in streamed ones; a launch is of
  * one kind and takes the longest-waiting ready swarms of that kind, at most
  * 8 parts per workgroup (PSO_SERVER_STAGED=0 in the environment streams
  * every request). */

@@ -81,14 +81,16 @@ constexpr uint32_t FIRST_ITERS = 4;
 constexpr int LAUNCH_WAVES_DEFAULT = 8;
 constexpr uint32_t MAX_SLICE_ITERS = 4096;
 constexpr int MAX_SERVER_D = 4096; // LDS of a launch is sized for the largest D it lists
-// LDS-staged launches: one 1024-lane workgroup per compute unit with 126 KiB
+// LDS-staged launches: one 1024-lane workgroup per compute unit with 158 KiB
 // of staged state, which leaves room for the gbest position and shift of
-// any D up to MAX_SERVER_D in the 160 KiB.  A request whose staged parts fit
-// a launch runs staged (its state in LDS for each launch), others streamed;
-// each launch is of one kind, the kind of the longest-waiting ready request.
-// PSO_SERVER_STAGED=0 in the environment streams every request.
+// D <= SERVER_STAGE_MAX_D in the 160 KiB.  A request of such D whose staged
+// parts fit a launch runs staged (its state in LDS for each launch), others
+// streamed; each launch is of one kind, the kind of the longest-waiting
+// ready request.  PSO_SERVER_STAGED=0 in the environment streams every
+// request.
 constexpr int SERVER_STAGE_LANES = 1024;
-constexpr int SERVER_STAGE_KIB = 126;
+constexpr int SERVER_STAGE_KIB = 158;
+constexpr int SERVER_STAGE_MAX_D = 64;
 
 } // namespace
 
@@ -478,7 +480,7 @@ int pso_server_create(size_t mem_budget, int64_t chunk_updates, pso_server **out
         const char *env = getenv("PSO_SERVER_STAGED");
         int cap_staged = 0;
         if (!(env && !strcmp(env, "0")) &&
-            pso::batch_capacity(MAX_SERVER_D, SERVER_STAGE_LANES, &cap_staged, SERVER_STAGE_KIB) == hipSuccess &&
+            pso::batch_capacity(SERVER_STAGE_MAX_D, SERVER_STAGE_LANES, &cap_staged, SERVER_STAGE_KIB) == hipSuccess &&
             cap_staged >= STREAMS)
             s->grid_cap_staged = cap_staged / STREAMS;
     }
@@ -538,7 +540,7 @@ int pso_server_submit(pso_server *s, const pso_desc *d, uint64_t *ticket)
     r->d.shift = nullptr;
     r->t_submit = Clock::now();
     const uint32_t staged_parts =
-        s->grid_cap_staged > 0
+        s->grid_cap_staged > 0 && d->D <= SERVER_STAGE_MAX_D
             ? pso::staged_parts((uint64_t)d->N, d->D, d->fitness_id, SERVER_STAGE_KIB, s->grid_cap_staged)
             : 0;
     r->staged = staged_parts > 0;

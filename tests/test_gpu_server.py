@@ -135,10 +135,11 @@ def test_large_requests_split_into_parts(server_mode):
 
 def test_staged_and_streamed_requests_mixed():
     """Requests too large to stage (their parts would outnumber a staged
-    launch's workgroups) run in streamed launches while the others run
-    staged; every result equals the swarm alone."""
+    launch's workgroups) or too wide (D > 64) run in streamed launches while
+    the others run staged; every result equals the swarm alone."""
     specs = [wl.SwarmSpec("sphere", 300000, 32, 12, seed=21, shift_amplitude=1.0),
-             wl.SwarmSpec("ackley", 150001, 40, 10, seed=22, shift_amplitude=1.0)]
+             wl.SwarmSpec("ackley", 150001, 40, 10, seed=22, shift_amplitude=1.0),
+             wl.SwarmSpec("rastrigin", 3000, 100, 20, seed=23, shift_amplitude=1.0)]
     specs += mixed_specs(40, 14, max_iter=80)
     announce("server: staged and streamed requests")
     with pso.Server(1 << 31, chunk_updates=1 << 22) as srv:
