@@ -130,7 +130,11 @@ int pso_step(pso_swarm *s);
  * Blocks until done, then writes the gbest fitness, the gbest position
  * (D floats, host), the iteration at which the gbest last changed (0 = at
  * initialisation) and the number of iterations this call ran.  Any output
- * pointer may be NULL. */
+ * pointer may be NULL.  A synchronous swarm with N*D <= 65536 whose state
+ * fits one workgroup's LDS runs the whole call as one launch of one
+ * workgroup (its state staged in LDS); others take one launch per
+ * iteration (PSO_PERSISTENT: one persistent launch).  Every path computes
+ * the same bits. */
 int pso_run(pso_swarm *s, int64_t max_iter, float tol, float f_star, float *gbest_value,
             float *gbest_pos_host, int64_t *gbest_iter, int64_t *iters_done);
 
