@@ -286,7 +286,8 @@ int pso_batch_run(const pso_desc *descs, int64_t count, pso_result *results);
  * many parts as its state needs, at most 512 and at most the grid.  A new
  * batch takes the shape pso_batch_autotune chose earlier in this process for
  * the same swarm sizes and iteration limits on the same device, else 1024
- * lanes with 158 KiB staged if every swarm fits that, else 256 lanes, the
+ * lanes with 158 KiB staged (less for D above 64: the LDS also holds
+ * 2 x D floats) if every swarm fits that, else 256 lanes, the
  * full capacity, 2^17 updates per part, streamed.  The co-resident capacity
  * is three quarters of the occupancy bound streamed and all but 8 compute
  * units' worth staged: a batch sharing the device with other long-running
@@ -317,8 +318,8 @@ int pso_batch_set_shape(pso_batch *b, const pso_batch_shape *shape);
  * picked by measurement on the device).  Times probe_iters iterations of the
  * whole batch under each candidate shape -- streamed: 64/128/256 lanes x
  * 2^15/2^17 updates per part x all or half of the co-resident workgroups;
- * LDS-staged: 512/1024 lanes x 78/158 KiB per workgroup, where the swarms
- * fit -- each after an untimed Step 1, keeps the fastest, records it for
+ * LDS-staged: 512/1024 lanes x 78/158 KiB per workgroup (less for D above
+ * 64), where the swarms fit -- each after an untimed Step 1, keeps the fastest, records it for
  * later batches of the same signature, and writes it to *chosen (may be
  * NULL).  Leaves the batch ready for pso_batch_launch (which restarts it).
  * Synchronous; costs about 16 x (probe_iters + 1) iterations of the batch.

@@ -51,7 +51,7 @@ struct BatchShape {
 constexpr BatchShape DEFAULT_BATCH_SHAPE = {256, 0, 1 << 17, 0}; // grid 0: the co-resident capacity
 // A batch's shape before any autotuning when every swarm fits it (else the
 // streamed default): one 1024-lane workgroup per compute unit with 158 KiB
-// of staged state.
+// of staged state (less where the batch's widest D needs more LDS room).
 constexpr BatchShape DEFAULT_STAGED_SHAPE = {1024, 0, 0, 158};
 
 bool batch_lanes_supported(int lanes, bool staged = false);

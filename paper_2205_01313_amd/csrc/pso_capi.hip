@@ -524,19 +524,47 @@ void batch_free(pso_batch *b)
     delete b;
 }
 
+// Staged KiB per workgroup that leave room, in a compute unit's LDS shared
+// by `per_cu` workgroups, for each workgroup's gbest position and shift of
+// maxD floats and its static LDS; at most 158 (per_cu = 1) or 78 (2).
+int staged_kib_fitting(int maxD, int per_cu)
+{
+    static const int lds_max = [] {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+            return 0;
+        return v;
+    }();
+    const long long head = (long long)pso::batch_dynamic_lds(maxD, 1) - 1024; // gbest position and shift
+    const long long kib = ((long long)lds_max / per_cu - 1024 - head) / 1024;
+    return (int)std::max(0LL, std::min<long long>(kib, per_cu == 1 ? 158 : 78));
+}
+
+// The staged shape a new batch takes before any autotuning: one 1024-lane
+// workgroup per compute unit with as much staged state as fits.
+pso::BatchShape default_staged_shape(int maxD)
+{
+    pso::BatchShape sh = pso::DEFAULT_STAGED_SHAPE;
+    sh.stage_kib = staged_kib_fitting(maxD, 1);
+    return sh;
+}
+
 // The shapes the autotuner tries: streamed, lanes per workgroup x part size
 // x co-resident workgroups (all of them, or half: a smaller working set);
 // LDS-staged, lanes x staged KiB per workgroup (two or one workgroups per
-// compute unit's 160 KiB; smaller parts meet too often: 38 KiB was 3x
-// slower on the 4096-swarm batch).
-std::vector<pso::BatchShape> tuner_candidates()
+// compute unit's 160 KiB, less the room each needs for maxD-float vectors;
+// smaller parts meet too often: 38 KiB was 3x slower on the 4096-swarm
+// batch).
+std::vector<pso::BatchShape> tuner_candidates(int maxD)
 {
     std::vector<pso::BatchShape> c;
     for (int lanes : {64, 128, 256})
         for (long long pw : {1LL << 15, 1LL << 17})
             for (int half : {0, 1}) c.push_back(pso::BatchShape{lanes, half ? -2 : 0, pw, 0});
     for (int lanes : {512, 1024})
-        for (int kib : {78, 158}) c.push_back(pso::BatchShape{lanes, 0, 0, kib});
+        for (int per_cu : {2, 1})
+            if (const int kib = staged_kib_fitting(maxD, per_cu)) c.push_back(pso::BatchShape{lanes, 0, 0, kib});
     return c;
 }
 
@@ -634,7 +662,7 @@ int pso_batch_create(const pso_desc *descs, int64_t count, void *hip_stream, pso
         maxD = std::max(maxD, (int)descs[i].D);
     }
     // gang regions are sized for the most parts any tuner shape gives
-    const std::vector<pso::BatchShape> cands = tuner_candidates();
+    const std::vector<pso::BatchShape> cands = tuner_candidates(maxD);
     std::vector<int> cand_grid(cands.size());
     for (size_t c = 0; c < cands.size(); ++c)
         if (shape_grid(maxD, cands[c], &cand_grid[c]) != hipSuccess) return fail(PSO_EDEVICE, "device query failed");
@@ -729,7 +757,7 @@ int pso_batch_create(const pso_desc *descs, int64_t count, void *hip_stream, pso
     }
     // a shape the autotuner chose for the same workload on this device, else
     // the staged default where every swarm fits it, else the streamed one
-    pso::BatchShape sh = pso::DEFAULT_STAGED_SHAPE;
+    pso::BatchShape sh = default_staged_shape(maxD);
     bool tuned = false;
     int dev = 0;
     (void)hipGetDevice(&dev);
@@ -808,7 +836,7 @@ int pso_batch_autotune(pso_batch *b, int64_t probe_iters, pso_batch_shape *chose
     float best_ms = -1.0f;
     pso::BatchShape best = b->shape;
     int rc = PSO_OK;
-    for (const pso::BatchShape &sh : tuner_candidates()) {
+    for (const pso::BatchShape &sh : tuner_candidates(b->maxD)) {
         // Step 1 and one iteration untimed, then probe_iters timed iterations;
         // a staged shape that this batch's swarms do not fit is skipped
         if ((rc = batch_configure(b, sh))) {

@@ -243,3 +243,41 @@ def test_full_batched_workload_sampled_against_oracle():
         assert r["iters"] == sp.T == o["iters"], k
         assert r["gbest_fit"] == o["gbest_fit"] and r["gbest_iter"] == o["giter"], (k, sp.fitness, sp.N, sp.D)
         assert np.array_equal(r["gbest_pos"], o["gpos"]), k
+
+
+@pytest.mark.parametrize("seed", [41, 42])
+def test_random_batches_staged_equal_streamed(seed):
+    """Random batches -- N from 1 to 20 000 (N*D <= 400 000), D from 1 to
+    200, every fitness, iteration limits from 0 to 80, a stop rule on a
+    third of the swarms --
+    give the same bits under the staged default (1024 lanes, as much staged
+    state as fits beside the widest swarm's vectors), a staged shape of two
+    workgroups per compute unit, and the streamed shape."""
+    rng = np.random.default_rng(seed)
+    specs = []
+    for k in range(120):
+        fit = wl.FITNESS_NAMES[int(rng.integers(0, 5))]
+        N = int(np.exp(rng.uniform(0, np.log(20000))))
+        D = int(np.exp(rng.uniform(0, np.log(200))))
+        if fit == "rosenbrock":
+            D = max(D, 2)
+        N = min(N, 400000 // D)  # every swarm fits a staged launch's workgroups
+        sp = wl.SwarmSpec(fit, N, D, int(rng.integers(0, 81)), seed=int(rng.integers(0, 2**40)),
+                          shift_amplitude=float(rng.uniform(0, 3)))
+        if k % 3 == 0:
+            sp.tol, sp.f_star = float(10.0 ** rng.uniform(-3, 1)), 0.0
+        specs.append(sp)
+    announce(f"random batch seed={seed}: staged vs streamed")
+    out = []
+    with pso.Batch(specs) as b:
+        full = b.shape["stage_kib"]  # the default: as much staged state as fits beside 2 x 200 floats
+        assert 150 <= full < 158
+        for lanes, pw, kib in ((1024, 0, full), (512, 0, full // 2), (256, 1 << 17, 0)):
+            b.set_shape(lanes, 0, pw, stage_kib=kib)
+            b.launch()
+            out.append(b.results())
+    for res in out[1:]:
+        for sp, r, q in zip(specs, res, out[0]):
+            assert r["gbest_fit"] == q["gbest_fit"] or (np.isnan(r["gbest_fit"]) and np.isnan(q["gbest_fit"])), sp
+            assert r["gbest_iter"] == q["gbest_iter"] and r["iters"] == q["iters"], sp
+            assert np.array_equal(r["gbest_pos"], q["gbest_pos"]), sp
