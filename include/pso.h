@@ -283,7 +283,8 @@ int pso_batch_run(const pso_desc *descs, int64_t count, pso_result *results);
  * large swarm is split over several workgroups (part_work >= 1).
  * stage_kib > 0 keeps each part's state in stage_kib KiB of LDS for a whole
  * launch (lanes 256, 512 or 1024; part_work is ignored): a swarm is split into as
- * many parts as its state needs, at most 512 and at most the grid.  A new
+ * many parts as its state needs, at most 512 and at most the grid; swarms
+ * that would need more stream, in a second kernel of the same launch.  A new
  * batch takes the shape pso_batch_autotune chose earlier in this process for
  * the same swarm sizes and iteration limits on the same device, else 1024
  * lanes with 158 KiB staged (less for D above 64: the LDS also holds
@@ -306,9 +307,7 @@ int pso_batch_get_shape(pso_batch *b, pso_batch_shape *shape);
 
 /* Sets the shape for the following launches (synchronises the batch's
  * stream).  EINVAL for unsupported lanes, grid < 0, part_work < 1 (streamed),
- * stage_kib < 0, more staged KiB than a workgroup's LDS, or a swarm whose
- * staged parts would exceed 512, the grid or the parts the batch's gang
- * regions were sized for (those of the autotuner's shapes); a grid above the
+ * stage_kib < 0 or more staged KiB than a workgroup's LDS; a grid above the
  * co-resident capacity is reduced to it, so every launch stays
  * deadlock-free.  Between launches only: the batch's state is restarted by
  * the next pso_batch_launch anyway. */

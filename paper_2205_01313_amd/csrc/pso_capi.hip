@@ -483,6 +483,8 @@ struct pso_batch {
     pso::BatchItem *d_items = nullptr;
     pso::BatchEntry *d_entries = nullptr;
     uint32_t n_entries = 0;
+    uint32_t n_first = 0;  // entries of the first kernel (all of them unless some swarms stream after it)
+    int grid_rest = 0;     // workgroups of the second (streamed) kernel
     pso::BatchResult *d_results = nullptr;
     unsigned int *d_next = nullptr;
     unsigned int *d_err = nullptr;
@@ -598,26 +600,34 @@ int batch_configure(pso_batch *b, const pso::BatchShape &sh)
     int grid = 0;
     HIP_TRY(shape_grid(b->maxD, sh, &grid));
     if (grid < 1) return fail(PSO_EINVAL, "batch shape: %d KiB of staged state per workgroup exceed the LDS", sh.stage_kib);
+    // Under a staged shape, a swarm whose staged parts would be too many
+    // (more than 512, than the grid, or than its gang region holds) streams:
+    // the launch runs the staged kernel over the staged swarms, then the
+    // streamed kernel (256 lanes, parts of 2^17 updates, its own co-resident
+    // grid) over those.  Entries of the staged swarms come first.
+    const pso::BatchShape stream_sh = staged ? pso::BatchShape{256, 0, 1LL << 17, 0} : sh;
+    int grid_s = grid;
+    if (staged) HIP_TRY(shape_grid(b->maxD, stream_sh, &grid_s));
     std::vector<uint32_t> parts(b->count);
+    std::vector<char> streamed(b->count, 0);
     for (int64_t i = 0; i < b->count; ++i) {
         if (staged) {
             parts[i] = pso::staged_parts(b->N[i], b->D[i], b->items[i].fitness, sh.stage_kib, grid);
-            if (parts[i] == 0 || parts[i] > b->max_parts[i])
-                return fail(PSO_EINVAL, "batch shape: swarm %lld (N=%llu, D=%d) does not fit %d KiB of LDS per "
-                                        "workgroup in the parts this batch provides",
-                            (long long)i, (unsigned long long)b->N[i], b->D[i], sh.stage_kib);
-        } else {
-            parts[i] = std::min(pso::parts_for(b->N[i], b->D[i], grid, sh), b->max_parts[i]);
+            if (parts[i] > 0 && parts[i] <= b->max_parts[i]) continue;
+            streamed[i] = 1;
         }
+        parts[i] = std::min(pso::parts_for(b->N[i], b->D[i], grid_s, stream_sh), b->max_parts[i]);
     }
-    uint64_t n_entries = 0;
+    uint64_t n_entries = 0, n_first = 0;
     for (int64_t i = 0; i < b->count; ++i) {
         pso::bind_gang(&b->items[i], b->gang[i], parts[i]);
         n_entries += parts[i];
+        if (!streamed[i]) n_first += parts[i];
     }
     std::vector<uint32_t> order(b->count);
     for (int64_t i = 0; i < b->count; ++i) order[i] = (uint32_t)i;
     std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) {
+        if (streamed[x] != streamed[y]) return streamed[x] < streamed[y];
         const double wx = double(b->N[x]) * b->D[x] * double(b->max_iter[x] + 1) / parts[x];
         const double wy = double(b->N[y]) * b->D[y] * double(b->max_iter[y] + 1) / parts[y];
         return wx > wy;
@@ -630,7 +640,9 @@ int batch_configure(pso_batch *b, const pso::BatchShape &sh)
     HIP_TRY(hipMemcpy(b->d_items, b->items.data(), sizeof(pso::BatchItem) * b->count, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(b->d_entries, entries.data(), sizeof(pso::BatchEntry) * n_entries, hipMemcpyHostToDevice));
     b->n_entries = (uint32_t)n_entries;
-    b->grid = (int)std::min<uint64_t>(n_entries, (uint64_t)grid);
+    b->n_first = (uint32_t)n_first;
+    b->grid = (int)std::min<uint64_t>(n_first, (uint64_t)grid);
+    b->grid_rest = (int)std::min<uint64_t>(n_entries - n_first, (uint64_t)grid_s);
     b->shape = sh;
     drop_graph(b); // the captured launch had the old grid and lanes
     return PSO_OK;
@@ -639,9 +651,14 @@ int batch_configure(pso_batch *b, const pso::BatchShape &sh)
 int batch_launch_iters(pso_batch *b, long long iter_cap, bool reset)
 {
     if (reset) HIP_TRY(pso::launch_batch_reset(b->d_items, b->d_results, (uint32_t)b->count, b->d_next, b->stream));
-    HIP_TRY(pso::launch_batch(b->d_items, b->d_entries, b->d_results, b->n_entries, b->d_next, b->maxD, b->grid,
-                              b->shape.lanes, (long long)1 << 62, iter_cap, b->stream, nullptr, nullptr, b->d_err,
-                              b->shape.stage_kib));
+    if (b->n_first > 0)
+        HIP_TRY(pso::launch_batch(b->d_items, b->d_entries, b->d_results, b->n_first, b->d_next, b->maxD, b->grid,
+                                  b->shape.lanes, (long long)1 << 62, iter_cap, b->stream, nullptr, nullptr, b->d_err,
+                                  b->shape.stage_kib));
+    if (b->n_entries > b->n_first) // the swarms too large to stage, streamed
+        HIP_TRY(pso::launch_batch(b->d_items, b->d_entries + b->n_first, b->d_results, b->n_entries - b->n_first,
+                                  b->d_next, b->maxD, b->grid_rest, 256, (long long)1 << 62, iter_cap, b->stream,
+                                  nullptr, nullptr, b->d_err, 0));
     return PSO_OK;
 }
 

@@ -177,13 +177,12 @@ def test_lds_staged_shapes_equal_streamed_and_oracle(lanes, kib):
 
 
 def test_lds_staged_shape_rejections():
-    """A staged budget too small for one particle quad of the widest swarm,
-    more KiB than the LDS holds, or unsupported lanes: EINVAL, and the batch
-    keeps working under its previous shape."""
+    """More staged KiB than the LDS holds, unsupported lanes or a negative
+    budget: EINVAL, and the batch keeps working under its previous shape."""
     specs = [wl.SwarmSpec("rastrigin", 100, 64, 5, seed=1), wl.SwarmSpec("sphere", 50, 2, 5, seed=2)]
     with pso.Batch(specs) as b:
         before = b.shape
-        for lanes, kib in ((256, 1), (256, 100000), (128, 38), (256, -1)):
+        for lanes, kib in ((256, 100000), (128, 38), (256, -1)):
             with pytest.raises(pso.PsoError) as e:
                 b.set_shape(lanes, 0, 0, stage_kib=kib)
             assert e.value.code == pso.PSO_EINVAL
@@ -281,3 +280,31 @@ def test_random_batches_staged_equal_streamed(seed):
             assert r["gbest_fit"] == q["gbest_fit"] or (np.isnan(r["gbest_fit"]) and np.isnan(q["gbest_fit"])), sp
             assert r["gbest_iter"] == q["gbest_iter"] and r["iters"] == q["iters"], sp
             assert np.array_equal(r["gbest_pos"], q["gbest_pos"]), sp
+
+
+def test_staged_launch_streams_swarms_too_large_to_stage():
+    """Under a staged shape, swarms whose staged parts would outnumber the
+    workgroups (or are too wide for a tiny budget) stream in a second kernel
+    of the same launch, after the staged ones: every result equals the
+    streamed shape's and, on a sample, the oracle."""
+    specs = [wl.SwarmSpec("rastrigin", 400000, 40, 6, seed=51, shift_amplitude=1.0),
+             wl.SwarmSpec("ackley", 120001, 64, 8, seed=52, shift_amplitude=1.0)]
+    specs += mixed_specs(40, 53, max_iter=40)
+    announce("staged launch with streamed swarms")
+    with pso.Batch(specs) as b:
+        b.set_shape(256, 0, 1 << 17)
+        b.launch()
+        ref = b.results()
+        outs = []
+        for lanes, kib in ((1024, 150), (512, 1)):  # 1 KiB: only the smallest swarms stage
+            b.set_shape(lanes, 0, 0, stage_kib=kib)
+            b.launch()
+            outs.append(b.results())
+    for res in outs:
+        for sp, r, q in zip(specs, res, ref):
+            assert r["gbest_fit"] == q["gbest_fit"] and r["gbest_iter"] == q["gbest_iter"], sp
+            assert r["iters"] == q["iters"] and np.array_equal(r["gbest_pos"], q["gbest_pos"]), sp
+    for k in (0, 1, 5):
+        sp = specs[k]
+        o = oracle_swarm(sp, 16).run_f32(sp.T, tol=getattr(sp, "tol", 0.0), f_star=getattr(sp, "f_star", 0.0))
+        assert ref[k]["gbest_fit"] == o["gbest_fit"] and np.array_equal(ref[k]["gbest_pos"], o["gpos"]), sp
