@@ -1,20 +1,22 @@
-// pso_block.hip -- one workgroup runs one whole swarm (Step 1 and all its
-// iterations) with workgroup barriers only.
+// pso_block.hip -- a workgroup runs a whole swarm, or one part of it, for
+// many iterations with workgroup barriers only.
 //
 // For a swarm small enough for one compute unit, a launch per iteration
 // costs more than the iteration itself, and the paper's answer -- removing
 // the second kernel (Sec. 3.2) -- still leaves one launch per iteration.
 // Here the iteration loop runs inside the workgroup: the gbest minimum is a
-// wavefront butterfly plus an LDS atomicMin, the gbest position lives in LDS,
-// and the state stays in the same per-swarm layout as the grid kernels (it is
-// cache-resident for small swarms).  The per-particle work is the same
-// init_quad / iterate_quad as the grid kernels, so a swarm computes the same
-// bits whichever kernel runs it.
+// wavefront butterfly plus an LDS atomicMin and the gbest position lives in
+// LDS.  The state either stays in device memory in the grid kernels' layout
+// (streamed: the same init_quad / iterate_quad) or is staged into LDS for
+// the whole launch (staged: per-(particle, dimension pair) items, the same
+// per-element Eq. 1 / Eq. 2 functions, fitness terms folded in dimension
+// order), so a swarm computes the same bits whichever kernel runs it.
 //
-// The batched kernel is persistent: each workgroup takes the next swarm from
-// an atomic work counter (swarms are queued largest first), runs it to its
-// iteration limit or stop rule, writes the result, and takes the next; every
-// workgroup exits when the counter passes the swarm count.
+// The batched kernels are persistent: each workgroup takes the next entry (a
+// swarm, or one part of a large one) from an atomic work counter (largest
+// per-part work first), runs it to its iteration limit or stop rule, writes
+// the result, and takes the next; the parts of a swarm meet once per
+// iteration; every workgroup exits when the counter passes the entry count.
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
