@@ -162,7 +162,10 @@ def deep_leg(pso, torch, wl, stream):
     """Deep workloads (D=128, N=65536, 2000 iterations): Rosenbrock, and
     Ackley with a shift; updates/s and the step kernel's share of the HBM
     roofline on algorithmic bytes.  Their 100 MB state fits the 256 MiB
-    Infinity Cache, so the fraction can exceed what HBM alone would allow."""
+    Infinity Cache, so the fraction can exceed what HBM alone would allow.
+    The binary32 result's error: its gbest position re-evaluated in binary64,
+    and the same run in binary64."""
+    import numpy as np
     out = {}
     for spec in (wl.deep_rosenbrock(0), wl.deep_ackley(0)):
         ws = torch.empty(pso.pso_workspace_bytes(spec.N, spec.D), dtype=torch.uint8, device="cuda")
@@ -187,11 +190,14 @@ def deep_leg(pso, torch, wl, stream):
             t0 = time.perf_counter()
             r64 = g64.run(spec.T)
             s64 = time.perf_counter() - t0
+            # the binary32 gbest position re-evaluated in binary64
+            f32_at64 = float(g64.eval(np.asarray(best["gbest_pos"], np.float64)[None, :])[0])
         f32 = float(best["gbest_fit"])
         f64 = float(r64["gbest_fit"])
         out[spec.fitness] = dict(value=spec.N * spec.D * spec.T / (ms / 1e3), unit="particle·dim updates/s",
                                  us_per_iteration=us, hbm_frac=alg / (us * 1e-6) / 1e9 / HBM_PEAK_GBS,
                                  pbest_improvement_rate=rho, gbest=f32, gbest_f64=f64,
+                                 gbest_pos_reevaluated_f64=f32_at64, fitness_eval_err=abs(f32 - f32_at64),
                                  abs_err_vs_f64=abs(f32 - f64), rel_err_vs_f64=abs(f32 - f64) / max(abs(f64), 1e-300),
                                  f64_run_s=s64)
     return out

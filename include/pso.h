@@ -216,6 +216,14 @@ int pso64_get_state(pso_swarm64 *s, double *x, double *v, double *p, double *pf,
                     int64_t *t);
 
 /* Frees the swarm.  NULL -> EINVAL. */
+/* The swarm's fitness function, with its shift, in binary64 at M points
+ * (host, row-major M x D doubles) -> values (host, M doubles): the same
+ * operation sequence as the binary64 swarm evaluates (Eq. 3 and the test
+ * functions of Sec. 5, in dimension order).  Used to re-evaluate a binary32
+ * result in binary64.  Synchronous; allocates a device buffer for the call.
+ * M < 0 or NULL pointers (with M > 0) -> EINVAL. */
+int pso64_eval(pso_swarm64 *s, const double *points, int64_t M, double *values);
+
 int pso64_destroy(pso_swarm64 *s);
 
 /* ------------------------------------------------------------------------ */

@@ -200,6 +200,14 @@ class Swarm64:
                                pos.ctypes.data_as(dp), ctypes.byref(git), ctypes.byref(done)), "pso64_run")
         return dict(gbest_fit=val.value, gbest_pos=pos, gbest_iter=git.value, iters=done.value)
 
+    def eval(self, points):
+        """The swarm's fitness (binary64, with its shift) at points (M x D)."""
+        pts = np.ascontiguousarray(np.asarray(points, np.float64).reshape(-1, self.D))
+        out = np.empty(pts.shape[0])
+        dp = ctypes.POINTER(ctypes.c_double)
+        _check(lib().pso64_eval(self.h, pts.ctypes.data_as(dp), pts.shape[0], out.ctypes.data_as(dp)), "pso64_eval")
+        return out
+
     def state(self):
         N, D = self.N, self.D
         out = dict(x=np.empty(D * N), v=np.empty(D * N), p=np.empty(D * N), pf=np.empty(N))

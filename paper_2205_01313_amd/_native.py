@@ -75,6 +75,7 @@ SIGNATURES = {
     "pso64_step": (c_int, [c_vp]),
     "pso64_run": (c_int, [c_vp, c_i64, c_f64, c_f64, P(c_f64), P(c_f64), P(c_i64), P(c_i64)]),
     "pso64_get_state": (c_int, [c_vp, P(c_f64), P(c_f64), P(c_f64), P(c_f64), P(c_i64), P(c_i64)]),
+    "pso64_eval": (c_int, [c_vp, P(c_f64), c_i64, P(c_f64)]),
     "pso64_destroy": (c_int, [c_vp]),
     "pso_set_max_lead": (c_int, [c_vp, c_i64]),
     "pso_batch_get_shape": (c_int, [c_vp, P(PsoBatchShape)]),

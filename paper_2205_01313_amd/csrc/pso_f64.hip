@@ -540,6 +540,31 @@ static inline dim3 grid64(const Swarm64Args &a) { return dim3((a.N + BLOCK64 - 1
     default: return hipErrorInvalidValue;                                                                          \
     }
 
+// The binary64 fitness of the swarm's function (with its shift) at M points
+// (row-major M x D), one lane per point, in dimension order.
+template <int FIT>
+__global__ void k_eval64(Swarm64Args a, const double *pts, uint64_t M, double *out)
+{
+    const uint64_t m = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M) return;
+    Fitness64<FIT> fit;
+    for (int d = 0; d < a.D; ++d) fit.add(pts[m * (uint64_t)a.D + d] - a.shift[d], d);
+    out[m] = fit.value(a.D);
+}
+
+template <int FIT>
+static void eval64_f(const Swarm64Args &a, const double *pts, uint64_t M, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_eval64<FIT>, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, a, pts, M, out);
+}
+
+hipError_t launch64_eval(int fitness, const Swarm64Args &a, const double *pts, uint64_t M, double *out,
+                         hipStream_t stream)
+{
+    PSO64_DISPATCH(eval64_f, a, pts, M, out, stream);
+    return hipGetLastError();
+}
+
 template <int FIT>
 static void init64_f(const Swarm64Args &a, hipStream_t s)
 {
@@ -833,6 +858,26 @@ int pso64_get_state(pso_swarm64 *s, double *x, double *v, double *p, double *pf,
     HIP64_TRY(hipMemcpy(&c, s->a.ctrl, sizeof c, hipMemcpyDeviceToHost));
     if (gbest_index) *gbest_index = c.gidx;
     if (t) *t = c.t;
+    return PSO_OK;
+}
+
+int pso64_eval(pso_swarm64 *s, const double *points, int64_t M, double *values)
+{
+    if (!s) return pso_internal_fail(PSO_EINVAL, "swarm is NULL");
+    if (M < 0 || M > (int64_t(1) << 30)) return pso_internal_fail(PSO_EINVAL, "M=%lld out of range", (long long)M);
+    if (M == 0) return PSO_OK;
+    if (!points || !values) return pso_internal_fail(PSO_EINVAL, "points or values is NULL");
+    const size_t in_bytes = sizeof(double) * (size_t)M * (size_t)s->D, out_bytes = sizeof(double) * (size_t)M;
+    void *buf = nullptr;
+    if (hipMalloc(&buf, in_bytes + out_bytes) != hipSuccess)
+        return pso_internal_fail(PSO_ENOMEM, "hipMalloc of %zu bytes failed", in_bytes + out_bytes);
+    double *d_pts = static_cast<double *>(buf), *d_out = d_pts + (size_t)M * (size_t)s->D;
+    hipError_t e = hipMemcpyAsync(d_pts, points, in_bytes, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = pso::launch64_eval(s->fitness, s->a, d_pts, (uint64_t)M, d_out, s->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(values, d_out, out_bytes, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    (void)hipFree(buf);
+    if (e != hipSuccess) return pso_internal_fail(PSO_EDEVICE, "pso64_eval: %s", hipGetErrorString(e));
     return PSO_OK;
 }
 

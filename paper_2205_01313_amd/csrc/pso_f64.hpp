@@ -54,6 +54,9 @@ hipError_t launch64_init(int fitness, const Swarm64Args &a, hipStream_t stream);
 hipError_t launch64_step(int fitness, const Swarm64Args &a, hipStream_t stream);
 hipError_t launch64_block_run(int fitness, const Swarm64Args &a, long long T, hipStream_t stream);
 hipError_t launch64_arm(const Swarm64Args &a, double tol, double fstar, hipStream_t stream);
+// out[m] = F(pts[m]) in binary64 for M device-resident points (row-major M x D).
+hipError_t launch64_eval(int fitness, const Swarm64Args &a, const double *pts, uint64_t M, double *out,
+                         hipStream_t stream);
 // Up to T iterations by a persistent gang of co-resident workgroups that meet
 // once per iteration (bit-identical to T grid steps); ctrl->gang_arrive must
 // be zero.  *launched = false if the swarm needs more workgroups than can be

@@ -73,3 +73,4 @@ def test_pure_host_entry_points_without_gpu(libpath):
     assert lib.pso64_create(0, 0, 2, b, 0.7, 1.4, 1.4, 0.2, 0, ctypes.byref(h64)) == _native.PSO_EINVAL
     assert lib.pso64_destroy(None) == _native.PSO_EINVAL
     assert lib.pso64_step(None) == _native.PSO_EINVAL
+    assert lib.pso64_eval(None, None, 1, None) == _native.PSO_EINVAL

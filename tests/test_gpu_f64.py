@@ -143,3 +143,24 @@ def test_transcendental_functions_close_then_invariants(fit):
     gi = st["gbest_idx"]
     assert st["pf"][gi] == st["pf"].min() and gi == int(np.flatnonzero(st["pf"] == st["pf"].min())[0])
     assert st["t"] == T
+
+
+@pytest.mark.parametrize("fit", ["sphere", "rastrigin", "rosenbrock", "ackley", "cubic"])
+def test_eval_matches_oracle(fit):
+    """pso64_eval (the binary64 fitness with the swarm's shift, used to
+    re-evaluate binary32 results): bit for bit against the oracle's binary64
+    fitness for the functions of +, -, *, / only, within 1e-12 relative for
+    those that call cos and exp."""
+    D = 1 if fit == "cubic" else 37
+    spec = wl.SwarmSpec(fit, 10, D, 1, seed=77, shift_amplitude=3.0)
+    rng = np.random.default_rng(3)
+    pts = rng.uniform(spec.lo, spec.hi, (500, D))
+    pts[0] = spec.shift.astype(np.float64)  # the optimum (Rosenbrock: near it)
+    with gpu64(spec) as g:
+        got = g.eval(pts)
+        assert g.eval(np.zeros((0, D))).shape == (0,)
+    ref = oracle_swarm(spec).fitness_f64(pts)
+    if fit in ("rastrigin", "ackley"):
+        np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-12)
+    else:
+        assert np.array_equal(got.view(np.uint64), ref.view(np.uint64))
