@@ -234,9 +234,12 @@ __device__ void publish_async(const SwarmArgs &a, unsigned long long m, unsigned
         const size_t gi = (uint32_t)m;
         for (int d = threadIdx.x; d < a.D; d += BLOCK)
             __hip_atomic_store(&a.gpos[d], a.x[(size_t)d * a.Np + gi], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
         __syncthreads();
         if (threadIdx.x == 0) {
+            // one release fence for the workgroup, as in publish_sync: the
+            // barrier orders every lane's position stores before it (a fence
+            // per wavefront writes the L2 back once per wavefront)
+            __threadfence();
             __hip_atomic_store(&c->pubkey, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const unsigned int s = __hip_atomic_load(&c->seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&c->seq, s + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT); // even: done
