@@ -62,34 +62,88 @@ def counters_from_profiles(kernel: str):
     return ent
 
 
-def cpu_baseline(spec, iters: int):
-    """The oracle (binary32 mode, OpenMP over particles) on the first `iters`
-    iterations of the same swarm; rate excludes initialisation."""
+def host_cpu():
+    """The host's CPU model, its logical CPUs, those this process may run on,
+    and the OpenMP thread setting."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except AttributeError:
+        allowed = os.cpu_count() or 1
+    return dict(cpu_model=model, logical_cpus=os.cpu_count(), cpus_allowed=allowed,
+                omp_num_threads=os.environ.get("OMP_NUM_THREADS"))
+
+
+def oracle_threads() -> int:
+    """Threads for the oracle: every CPU this process may run on, at most the
+    OpenMP setting of the environment (the CPU share of the machine)."""
+    n = host_cpu()["cpus_allowed"]
+    omp = os.environ.get("OMP_NUM_THREADS")
+    if omp and omp.isdigit() and int(omp) > 0:
+        n = min(n, int(omp))
+    return max(1, n)
+
+
+def cpu_baseline(spec, iters: int, gpu_run=None):
+    """The oracle (binary32 mode, OpenMP over particles on the CPU share of
+    the host) on the first `iters` iterations of the same swarm, init
+    excluded from the rate.  With gpu_run (the GPU's last timed solve of the
+    same swarm: per-iteration gbest keys, gbest position, iteration of the
+    last change, final state), the two runs are compared: every iteration's
+    gbest key and the final state, bit for bit.  Then, on one core, the same
+    problem at N = 65536 for 20 iterations in the synchronous mode and in the
+    literal order of Alg. 1 (gbest updated inside the particle loop, the
+    serial CPU baseline of the paper's tables)."""
+    import numpy as np
+
     import oracle
 
-    threads = min(16, os.cpu_count() or 1)
+    threads = oracle_threads()
     sw = oracle.Swarm(spec.fitness, spec.N, spec.D, spec.lo, spec.hi, spec.w, spec.c1, spec.c2, spec.vmax,
                       spec.seed, nthreads=threads)
     st = sw.init_f32()
+    hist = [st["gkey"]]
+    giter = 0
     t0 = time.perf_counter()
     for t in range(1, iters + 1):
-        sw.step_f32(st, t)
+        if sw.step_f32(st, t):
+            giter = t
+        hist.append(st["gkey"])
     dt = time.perf_counter() - t0
-    # one core (the paper's serial baseline is single-threaded): the same
-    # problem at N = 65536 for 20 iterations, a rate per update
+    out = dict(value=spec.N * spec.D * iters / dt, unit="particle·dim updates/s", cores=threads, kind="oracle",
+               sample=f"first {iters} iterations of the same swarm (N={spec.N}, D={spec.D}), init excluded, "
+                      f"{dt:.1f} s", host=host_cpu())
+    if gpu_run is not None and iters == len(gpu_run["hist"]) - 1:
+        hist = np.asarray(hist, np.uint64)
+        eq = dict(history=bool(np.array_equal(hist, gpu_run["hist"])),
+                  gbest_key=int(hist[-1]) == int(gpu_run["gkey"]),
+                  gbest_iter=giter == int(gpu_run["giter"]),
+                  gbest_pos=bool(np.array_equal(st["gpos"].view(np.uint32), gpu_run["gpos"].view(np.uint32))))
+        for k in ("x", "v", "p", "pf"):
+            eq[k] = bool(np.array_equal(st[k].view(np.uint32), gpu_run[k].view(np.uint32)))
+        out["oracle_equal"] = all(eq.values())
+        out["oracle_compare"] = eq
     n1, it1 = 65536, 20
-    sw1 = oracle.Swarm(spec.fitness, n1, spec.D, spec.lo, spec.hi, spec.w, spec.c1, spec.c2, spec.vmax, spec.seed,
-                       nthreads=1)
-    st1 = sw1.init_f32()
-    t1 = time.perf_counter()
-    for t in range(1, it1 + 1):
-        sw1.step_f32(st1, t)
-    dt1 = time.perf_counter() - t1
-    return dict(value=spec.N * spec.D * iters / dt, unit="particle·dim updates/s", cores=threads, kind="oracle",
-                sample=f"first {iters} iterations of the same swarm (N={spec.N}, D={spec.D}), init excluded, "
-                       f"{dt:.1f} s",
-                single_core=dict(value=n1 * spec.D * it1 / dt1, cores=1,
-                                 sample=f"N={n1}, D={spec.D}, {it1} iterations, {dt1:.1f} s"))
+    for name, serial in (("single_core", False), ("single_core_serial_alg1", True)):
+        sw1 = oracle.Swarm(spec.fitness, n1, spec.D, spec.lo, spec.hi, spec.w, spec.c1, spec.c2, spec.vmax,
+                           spec.seed, nthreads=1)
+        st1 = sw1.init_f32()
+        t1 = time.perf_counter()
+        for t in range(1, it1 + 1):
+            sw1.step_f32(st1, t, serial_immediate=serial)
+        dt1 = time.perf_counter() - t1
+        out[name] = dict(value=n1 * spec.D * it1 / dt1, cores=1,
+                         sample=f"N={n1}, D={spec.D}, {it1} iterations, {dt1:.1f} s"
+                                + (", gbest updated inside the particle loop" if serial else ""))
+    return out
 
 
 def timed_events(torch, stream, fn):
@@ -99,6 +153,18 @@ def timed_events(torch, stream, fn):
     b.record(stream)
     torch.cuda.synchronize()
     return a.elapsed_time(b)
+
+
+def copy_ceiling(torch, stream, nbytes=1 << 30, reps=5):
+    """Device-to-device copy of nbytes (read nbytes + write nbytes), larger
+    than the 256 MiB Infinity Cache so that HBM carries it: the bandwidth a
+    plain streaming kernel reaches on this device (median of reps copies)."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ms = sorted(timed_events(torch, stream, lambda: dst.copy_(src)) for _ in range(reps))
+    del src, dst
+    return dict(bytes_per_copy=2 * nbytes, ms_median=ms[reps // 2], gbs=2 * nbytes / (ms[reps // 2] * 1e-3) / 1e9)
 
 
 def async_leg(pso, torch, wl, spec, ws, stream, seeds=32):
@@ -381,10 +447,13 @@ def main():
     ap.add_argument("--legs", default="main,async,small,deep,latency,paper,batched,serving",
                     help="comma list of legs beyond the main line: async, small, deep, latency, paper, batched, "
                          "serving")
-    ap.add_argument("--pmc-probe", nargs="?", const="step", choices=["step", "batch"],
+    ap.add_argument("--pmc-probe", nargs="?", const="step",
+                    choices=["step", "batch", "deep_rosenbrock", "deep_ackley"],
                     help="for rocprofv3 counter runs: 'step' (default) = init + 20 step launches, then a 256 MiB "
                          "torch copy (calibration kernel of known size); 'batch' = one untimed and one timed launch "
-                         "of the 4096-swarm batch (128 lanes, full grid, 2^17 per part); prints one line")
+                         "of the 4096-swarm batch (1024 lanes, 158 KiB staged); 'deep_rosenbrock' / 'deep_ackley' "
+                         "= the D=128, N=65536 workload: init, 100 untimed and 200 timed step launches (the split "
+                         "step), then the same copies; prints one line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the path is single-GPU (--gpus {args.gpus} is not supported)",
@@ -422,7 +491,30 @@ def main():
         print(json.dumps({"pmc_probe": "batch", "ms": ms,
                           "updates": int(sum(sp.N * sp.D * r["iters"] for sp, r in zip(specs, res)))}), flush=True)
         return
-    if args.pmc_probe:
+    if args.pmc_probe in ("deep_rosenbrock", "deep_ackley"):
+        sw.close()
+        dspec = wl.deep_rosenbrock(0) if args.pmc_probe == "deep_rosenbrock" else wl.deep_ackley(0)
+        dws = torch.empty(pso.pso_workspace_bytes(dspec.N, dspec.D), dtype=torch.uint8, device=dev)
+        with pso.Swarm(dspec.fitness, dspec.N, dspec.D, dspec.box, dspec.w, dspec.c1, dspec.c2, dspec.vmax,
+                       dspec.seed, shift=dspec.shift, workspace=dws, stream=stream) as g:
+            for _ in range(100):
+                pso.pso_step(g.h)
+            torch.cuda.synchronize()
+            n0 = g.counters()["pbest_improvements"]
+            ms = timed_events(torch, stream, lambda: [pso.pso_step(g.h) for _ in range(200)])
+            rho = (g.counters()["pbest_improvements"] - n0) / (dspec.N * 200)
+        src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        alg = dspec.N * dspec.D * (20.0 + 4.0 * rho) + dspec.N * (4.0 + 4.0 * rho)
+        print(json.dumps({"pmc_probe": args.pmc_probe, "step_launches": 300, "timed_launches": 200,
+                          "us_per_launch": ms * 1e3 / 200, "pbest_improvement_rate": rho,
+                          "alg_bytes_per_launch": alg, "copy_bytes": COPY_BYTES,
+                          "source_digest": source_digest()}), flush=True)
+        return
+    if args.pmc_probe == "step":
         sw.reset()
         for _ in range(20):
             pso.pso_step(sw.h)
@@ -464,6 +556,14 @@ def main():
     best = sw.best()
     # pbest improvements of the last timed solve (counted inside the step kernel)
     rho = sw.counters()["pbest_improvements"] / (spec.N * spec.T)
+    # the last timed solve, for the comparison with the oracle (outside the
+    # timed region)
+    gpu_run = None
+    if not args.no_cpu_baseline and args.cpu_iters == spec.T:
+        st = sw.state()
+        gpu_run = dict(hist=sw.history(0, spec.T + 1), gkey=st["gkey"], giter=st["giter"], gpos=st["gpos"],
+                       x=st["x"], v=st["v"], p=st["p"], pf=st["pf"])
+        del st
     sw.close()
 
     ms_per_step = total_ms / args.steps
@@ -483,6 +583,7 @@ def main():
     valu_busy = (counters["valu_insts_per_dispatch"] * 4 / SIMDS / (launch_us * CLOCK_MHZ)
                  if counters and "valu_insts_per_dispatch" in counters else None)
 
+    ceiling = copy_ceiling(torch, stream)
     out = {
         "metric": "particle·dim updates/s incl. fitness",
         "value": value,
@@ -502,7 +603,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": kernel, "avg_launch_us": launch_us, "alg_bytes_per_launch": alg_bytes,
-                     "pbest_improvement_rate": rho, "valu_busy_frac": valu_busy},
+                     "pbest_improvement_rate": rho, "valu_busy_frac": valu_busy,
+                     "measured_copy_ceiling": ceiling, "frac_of_measured_copy": achieved / ceiling["gbs"]},
         "gbest": {"value": float(best["gbest_fit"]), "iteration": int(best["gbest_iter"])},
         "solve_ms": {"median": solve_ms[len(solve_ms) // 2], "trimmed_mean": sum(trimmed) / len(trimmed),
                      "min": solve_ms[0], "max": solve_ms[-1]},
@@ -525,7 +627,10 @@ def main():
     if "serving" in legs:
         out["serving"] = serving_leg(pso, wl)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(spec, args.cpu_iters)
+        out["cpu_baseline"] = cpu_baseline(spec, args.cpu_iters, gpu_run)
+        if "oracle_equal" in out["cpu_baseline"]:
+            out["oracle_equal"] = out["cpu_baseline"]["oracle_equal"]
+        del gpu_run
     print(json.dumps(out), flush=True)
 
 

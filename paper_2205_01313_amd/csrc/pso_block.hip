@@ -1080,4 +1080,35 @@ hipError_t batch_capacity(int maxD, int lanes, int *workgroups, int stage_kib)
     return hipSuccess;
 }
 
+// Staged KiB per workgroup that leave room, in a compute unit's LDS shared
+// by `per_cu` workgroups, for each workgroup's gbest position and shift of
+// maxD floats and its static LDS; at most 158 (per_cu = 1) or 78 (2).
+int staged_kib_fitting(int maxD, int per_cu)
+{
+    const long long head = (long long)batch_dynamic_lds(maxD, 1) - 1024; // gbest position and shift
+    const long long kib = ((long long)device_lds_max() / per_cu - 1024 - head) / 1024;
+    return (int)std::max(0LL, std::min<long long>(kib, per_cu == 1 ? 158 : 78));
+}
+
+// Workgroups of a shape: grid > 0 as given (at most the capacity), 0 the
+// capacity, -k the capacity / k.
+hipError_t shape_grid(int maxD, const BatchShape &sh, int *grid)
+{
+    int cap = 0;
+    hipError_t e = batch_capacity(maxD, sh.lanes, &cap, sh.stage_kib);
+    if (e != hipSuccess) return e;
+    if (cap < 1) { // a staged shape whose LDS does not fit a workgroup
+        *grid = 0;
+        return hipSuccess;
+    }
+    *grid = sh.grid > 0 ? std::min(sh.grid, cap) : sh.grid < 0 ? std::max(1, cap / -sh.grid) : cap;
+    return hipSuccess;
+}
+
+hipError_t launch_clear_u32(unsigned int *p, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_counter_reset, dim3(1), dim3(64), 0, stream, p);
+    return hipGetLastError();
+}
+
 } // namespace pso

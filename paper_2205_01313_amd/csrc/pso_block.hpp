@@ -132,4 +132,15 @@ hipError_t batch_capacity(int maxD, int lanes, int *workgroups, int stage_kib = 
 // LDS bytes a workgroup of the batched kernel takes dynamically.
 size_t batch_dynamic_lds(int maxD, int stage_kib);
 
+// Staged KiB per workgroup that leave room, in a compute unit's LDS shared
+// by per_cu workgroups, for each workgroup's gbest position and shift of
+// maxD floats: at most 158 (per_cu = 1) or 78 (per_cu = 2); 0 if none fit.
+int staged_kib_fitting(int maxD, int per_cu);
+// Workgroups a launch of this shape takes: grid > 0 as given (at most the
+// co-resident capacity), 0 the capacity, -k the capacity / k; 0 if a staged
+// shape's LDS does not fit a workgroup.
+hipError_t shape_grid(int maxD, const BatchShape &sh, int *grid);
+// Sets one device word to zero with a kernel (stream-ordered; no memset).
+hipError_t launch_clear_u32(unsigned int *p, hipStream_t stream);
+
 } // namespace pso

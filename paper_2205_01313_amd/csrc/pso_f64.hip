@@ -23,6 +23,7 @@
 #include "pso.h"
 #include "pso_device.hpp"
 #include "pso_f64.hpp"
+#include "pso_guard.hpp"
 
 int pso_internal_fail(int code, const char *fmt, ...);
 int pso_internal_check_desc(const pso_desc *d);
@@ -729,163 +730,179 @@ extern "C" {
 int pso64_create(int fitness_id, int64_t N, int32_t D, const float bounds[2], float w, float c1, float c2,
                  float vmax, uint64_t seed, pso_swarm64 **out)
 {
-    if (!out) return pso_internal_fail(PSO_EINVAL, "out is NULL");
-    *out = nullptr;
-    if (!bounds) return pso_internal_fail(PSO_EINVAL, "bounds is NULL");
-    pso_desc d{};
-    d.fitness_id = fitness_id;
-    d.D = D;
-    d.N = N;
-    d.bounds[0] = bounds[0];
-    d.bounds[1] = bounds[1];
-    d.w = w;
-    d.c1 = c1;
-    d.c2 = c2;
-    d.vmax = vmax;
-    d.seed = seed;
-    int rc = pso_internal_check_desc(&d);
-    if (rc) return rc;
-    pso_swarm64 *s = new (std::nothrow) pso_swarm64();
-    if (!s) return pso_internal_fail(PSO_ENOMEM, "host allocation failed");
-    s->fitness = fitness_id;
-    s->N = (uint64_t)N;
-    s->D = D;
-    s->L = pso::layout64_of(s->N, D);
-    if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
-        s->stream = nullptr;
-        free64(s);
-        return pso_internal_fail(PSO_EDEVICE, "hipStreamCreate failed");
-    }
-    if (hipMalloc(&s->mem, s->L.total) != hipSuccess) {
-        s->mem = nullptr;
-        free64(s);
-        return pso_internal_fail(PSO_ENOMEM, "hipMalloc of %zu bytes failed", s->L.total);
-    }
-    s->a = pso::bind64(s->mem, s->L, s->N, D);
-    s->a.lo = bounds[0];
-    s->a.hi = bounds[1];
-    s->a.w = w;
-    s->a.c1 = c1;
-    s->a.c2 = c2;
-    s->a.vmax = vmax;
-    s->a.k0 = (uint32_t)seed;
-    s->a.k1 = (uint32_t)(seed >> 32);
-    if (hipMemset(const_cast<double *>(s->a.shift), 0, sizeof(double) * D) != hipSuccess ||
-        (rc = reinit64(s)) != PSO_OK) {
-        free64(s);
-        return rc ? rc : pso_internal_fail(PSO_EDEVICE, "shift initialisation failed");
-    }
-    *out = s;
-    return PSO_OK;
+    return pso::guarded([&]() -> int {
+        if (!out) return pso_internal_fail(PSO_EINVAL, "out is NULL");
+        *out = nullptr;
+        if (!bounds) return pso_internal_fail(PSO_EINVAL, "bounds is NULL");
+        pso_desc d{};
+        d.fitness_id = fitness_id;
+        d.D = D;
+        d.N = N;
+        d.bounds[0] = bounds[0];
+        d.bounds[1] = bounds[1];
+        d.w = w;
+        d.c1 = c1;
+        d.c2 = c2;
+        d.vmax = vmax;
+        d.seed = seed;
+        int rc = pso_internal_check_desc(&d);
+        if (rc) return rc;
+        pso_swarm64 *s = new (std::nothrow) pso_swarm64();
+        if (!s) return pso_internal_fail(PSO_ENOMEM, "host allocation failed");
+        s->fitness = fitness_id;
+        s->N = (uint64_t)N;
+        s->D = D;
+        s->L = pso::layout64_of(s->N, D);
+        if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
+            s->stream = nullptr;
+            free64(s);
+            return pso_internal_fail(PSO_EDEVICE, "hipStreamCreate failed");
+        }
+        if (hipMalloc(&s->mem, s->L.total) != hipSuccess) {
+            s->mem = nullptr;
+            free64(s);
+            return pso_internal_fail(PSO_ENOMEM, "hipMalloc of %zu bytes failed", s->L.total);
+        }
+        s->a = pso::bind64(s->mem, s->L, s->N, D);
+        s->a.lo = bounds[0];
+        s->a.hi = bounds[1];
+        s->a.w = w;
+        s->a.c1 = c1;
+        s->a.c2 = c2;
+        s->a.vmax = vmax;
+        s->a.k0 = (uint32_t)seed;
+        s->a.k1 = (uint32_t)(seed >> 32);
+        if (hipMemset(const_cast<double *>(s->a.shift), 0, sizeof(double) * D) != hipSuccess ||
+            (rc = reinit64(s)) != PSO_OK) {
+            free64(s);
+            return rc ? rc : pso_internal_fail(PSO_EDEVICE, "shift initialisation failed");
+        }
+        *out = s;
+        return PSO_OK;
+    });
 }
 
 int pso64_set_shift(pso_swarm64 *s, const float *shift)
 {
-    if (!s || !shift) return pso_internal_fail(PSO_EINVAL, "swarm or shift is NULL");
-    std::vector<double> sh(s->D);
-    for (int d = 0; d < s->D; ++d) {
-        if (!std::isfinite(shift[d])) return pso_internal_fail(PSO_EINVAL, "shift[%d] is not finite", d);
-        sh[d] = shift[d];
-    }
-    HIP64_TRY(hipStreamSynchronize(s->stream));
-    HIP64_TRY(hipMemcpy(const_cast<double *>(s->a.shift), sh.data(), sizeof(double) * s->D, hipMemcpyHostToDevice));
-    return reinit64(s);
+    return pso::guarded([&]() -> int {
+        if (!s || !shift) return pso_internal_fail(PSO_EINVAL, "swarm or shift is NULL");
+        std::vector<double> sh(s->D);
+        for (int d = 0; d < s->D; ++d) {
+            if (!std::isfinite(shift[d])) return pso_internal_fail(PSO_EINVAL, "shift[%d] is not finite", d);
+            sh[d] = shift[d];
+        }
+        HIP64_TRY(hipStreamSynchronize(s->stream));
+        HIP64_TRY(hipMemcpy(const_cast<double *>(s->a.shift), sh.data(), sizeof(double) * s->D, hipMemcpyHostToDevice));
+        return reinit64(s);
+    });
 }
 
 int pso64_reset(pso_swarm64 *s)
 {
-    if (!s) return pso_internal_fail(PSO_EINVAL, "swarm is NULL");
-    return reinit64(s);
+    return pso::guarded([&]() -> int {
+        if (!s) return pso_internal_fail(PSO_EINVAL, "swarm is NULL");
+        return reinit64(s);
+    });
 }
 
 int pso64_step(pso_swarm64 *s)
 {
-    if (!s) return pso_internal_fail(PSO_EINVAL, "swarm is NULL");
-    HIP64_TRY(pso::launch64_step(s->fitness, s->a, s->stream));
-    return PSO_OK;
+    return pso::guarded([&]() -> int {
+        if (!s) return pso_internal_fail(PSO_EINVAL, "swarm is NULL");
+        HIP64_TRY(pso::launch64_step(s->fitness, s->a, s->stream));
+        return PSO_OK;
+    });
 }
 
 int pso64_run(pso_swarm64 *s, int64_t max_iter, double tol, double f_star, double *gbest_value, double *gbest_pos,
               int64_t *gbest_iter, int64_t *iters_done)
 {
-    if (!s) return pso_internal_fail(PSO_EINVAL, "swarm is NULL");
-    if (max_iter < 0) return pso_internal_fail(PSO_EINVAL, "max_iter < 0");
-    pso::Ctrl64 c{};
-    HIP64_TRY(hipStreamSynchronize(s->stream));
-    HIP64_TRY(hipMemcpy(&c, s->a.ctrl, sizeof c, hipMemcpyDeviceToHost));
-    const long long t0 = c.t;
-    HIP64_TRY(pso::launch64_arm(s->a, tol, f_star, s->stream));
-    const uint64_t nd = s->N * (uint64_t)s->D;
-    const char *path = getenv("PSO64_PATH"); // tests of every path: block, gang, grid
-    bool done_gang = false;
-    if (path ? !strcmp(path, "block") : nd <= block64_max_nd()) {
-        HIP64_TRY(pso::launch64_block_run(s->fitness, s->a, max_iter, s->stream));
-        done_gang = true;
-    } else if (path ? !strcmp(path, "gang") : s->D <= GANG64_MAX_D) {
-        HIP64_TRY(hipMemsetAsync(&s->a.ctrl->gang_arrive, 0, sizeof(unsigned long long), s->stream));
-        HIP64_TRY(pso::launch64_gang(s->fitness, s->a, max_iter, s->stream, &done_gang));
-    }
-    if (!done_gang) {
-        // chunks of launches; every launch returns at once after the stop rule holds
-        for (int64_t done = 0; done < max_iter;) {
-            const int64_t n = std::min<int64_t>(256, max_iter - done);
-            for (int64_t k = 0; k < n; ++k) HIP64_TRY(pso::launch64_step(s->fitness, s->a, s->stream));
-            done += n;
-            HIP64_TRY(hipStreamSynchronize(s->stream));
-            HIP64_TRY(hipMemcpy(&c, s->a.ctrl, sizeof c, hipMemcpyDeviceToHost));
-            if (c.stop) break;
+    return pso::guarded([&]() -> int {
+        if (!s) return pso_internal_fail(PSO_EINVAL, "swarm is NULL");
+        if (max_iter < 0) return pso_internal_fail(PSO_EINVAL, "max_iter < 0");
+        pso::Ctrl64 c{};
+        HIP64_TRY(hipStreamSynchronize(s->stream));
+        HIP64_TRY(hipMemcpy(&c, s->a.ctrl, sizeof c, hipMemcpyDeviceToHost));
+        const long long t0 = c.t;
+        HIP64_TRY(pso::launch64_arm(s->a, tol, f_star, s->stream));
+        const uint64_t nd = s->N * (uint64_t)s->D;
+        const char *path = getenv("PSO64_PATH"); // tests of every path: block, gang, grid
+        bool done_gang = false;
+        if (path ? !strcmp(path, "block") : nd <= block64_max_nd()) {
+            HIP64_TRY(pso::launch64_block_run(s->fitness, s->a, max_iter, s->stream));
+            done_gang = true;
+        } else if (path ? !strcmp(path, "gang") : s->D <= GANG64_MAX_D) {
+            HIP64_TRY(hipMemsetAsync(&s->a.ctrl->gang_arrive, 0, sizeof(unsigned long long), s->stream));
+            HIP64_TRY(pso::launch64_gang(s->fitness, s->a, max_iter, s->stream, &done_gang));
         }
-    }
-    HIP64_TRY(hipStreamSynchronize(s->stream));
-    HIP64_TRY(hipMemcpy(&c, s->a.ctrl, sizeof c, hipMemcpyDeviceToHost));
-    if (c.err) return pso_internal_fail(PSO_EDEVICE, "a gang wait gave up (device error bits 0x%x)", c.err);
-    if (gbest_value) HIP64_TRY(hipMemcpy(gbest_value, s->a.pf + c.gidx, sizeof(double), hipMemcpyDeviceToHost));
-    if (gbest_pos) HIP64_TRY(hipMemcpy(gbest_pos, s->a.gpos, sizeof(double) * s->D, hipMemcpyDeviceToHost));
-    if (gbest_iter) *gbest_iter = c.giter;
-    if (iters_done) *iters_done = c.t - t0;
-    return PSO_OK;
+        if (!done_gang) {
+            // chunks of launches; every launch returns at once after the stop rule holds
+            for (int64_t done = 0; done < max_iter;) {
+                const int64_t n = std::min<int64_t>(256, max_iter - done);
+                for (int64_t k = 0; k < n; ++k) HIP64_TRY(pso::launch64_step(s->fitness, s->a, s->stream));
+                done += n;
+                HIP64_TRY(hipStreamSynchronize(s->stream));
+                HIP64_TRY(hipMemcpy(&c, s->a.ctrl, sizeof c, hipMemcpyDeviceToHost));
+                if (c.stop) break;
+            }
+        }
+        HIP64_TRY(hipStreamSynchronize(s->stream));
+        HIP64_TRY(hipMemcpy(&c, s->a.ctrl, sizeof c, hipMemcpyDeviceToHost));
+        if (c.err) return pso_internal_fail(PSO_EDEVICE, "a gang wait gave up (device error bits 0x%x)", c.err);
+        if (gbest_value) HIP64_TRY(hipMemcpy(gbest_value, s->a.pf + c.gidx, sizeof(double), hipMemcpyDeviceToHost));
+        if (gbest_pos) HIP64_TRY(hipMemcpy(gbest_pos, s->a.gpos, sizeof(double) * s->D, hipMemcpyDeviceToHost));
+        if (gbest_iter) *gbest_iter = c.giter;
+        if (iters_done) *iters_done = c.t - t0;
+        return PSO_OK;
+    });
 }
 
 int pso64_get_state(pso_swarm64 *s, double *x, double *v, double *p, double *pf, int64_t *gbest_index, int64_t *t)
 {
-    if (!s) return pso_internal_fail(PSO_EINVAL, "swarm is NULL");
-    HIP64_TRY(hipStreamSynchronize(s->stream));
-    int rc;
-    if ((rc = rows_to_host(s, s->a.x, x)) || (rc = rows_to_host(s, s->a.v, v)) || (rc = rows_to_host(s, s->a.p, p)))
-        return rc;
-    if (pf) HIP64_TRY(hipMemcpy(pf, s->a.pf, sizeof(double) * s->N, hipMemcpyDeviceToHost));
-    pso::Ctrl64 c{};
-    HIP64_TRY(hipMemcpy(&c, s->a.ctrl, sizeof c, hipMemcpyDeviceToHost));
-    if (gbest_index) *gbest_index = c.gidx;
-    if (t) *t = c.t;
-    return PSO_OK;
+    return pso::guarded([&]() -> int {
+        if (!s) return pso_internal_fail(PSO_EINVAL, "swarm is NULL");
+        HIP64_TRY(hipStreamSynchronize(s->stream));
+        int rc;
+        if ((rc = rows_to_host(s, s->a.x, x)) || (rc = rows_to_host(s, s->a.v, v)) || (rc = rows_to_host(s, s->a.p, p)))
+            return rc;
+        if (pf) HIP64_TRY(hipMemcpy(pf, s->a.pf, sizeof(double) * s->N, hipMemcpyDeviceToHost));
+        pso::Ctrl64 c{};
+        HIP64_TRY(hipMemcpy(&c, s->a.ctrl, sizeof c, hipMemcpyDeviceToHost));
+        if (gbest_index) *gbest_index = c.gidx;
+        if (t) *t = c.t;
+        return PSO_OK;
+    });
 }
 
 int pso64_eval(pso_swarm64 *s, const double *points, int64_t M, double *values)
 {
-    if (!s) return pso_internal_fail(PSO_EINVAL, "swarm is NULL");
-    if (M < 0 || M > (int64_t(1) << 30)) return pso_internal_fail(PSO_EINVAL, "M=%lld out of range", (long long)M);
-    if (M == 0) return PSO_OK;
-    if (!points || !values) return pso_internal_fail(PSO_EINVAL, "points or values is NULL");
-    const size_t in_bytes = sizeof(double) * (size_t)M * (size_t)s->D, out_bytes = sizeof(double) * (size_t)M;
-    void *buf = nullptr;
-    if (hipMalloc(&buf, in_bytes + out_bytes) != hipSuccess)
-        return pso_internal_fail(PSO_ENOMEM, "hipMalloc of %zu bytes failed", in_bytes + out_bytes);
-    double *d_pts = static_cast<double *>(buf), *d_out = d_pts + (size_t)M * (size_t)s->D;
-    hipError_t e = hipMemcpyAsync(d_pts, points, in_bytes, hipMemcpyHostToDevice, s->stream);
-    if (e == hipSuccess) e = pso::launch64_eval(s->fitness, s->a, d_pts, (uint64_t)M, d_out, s->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(values, d_out, out_bytes, hipMemcpyDeviceToHost, s->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-    (void)hipFree(buf);
-    if (e != hipSuccess) return pso_internal_fail(PSO_EDEVICE, "pso64_eval: %s", hipGetErrorString(e));
-    return PSO_OK;
+    return pso::guarded([&]() -> int {
+        if (!s) return pso_internal_fail(PSO_EINVAL, "swarm is NULL");
+        if (M < 0 || M > (int64_t(1) << 30)) return pso_internal_fail(PSO_EINVAL, "M=%lld out of range", (long long)M);
+        if (M == 0) return PSO_OK;
+        if (!points || !values) return pso_internal_fail(PSO_EINVAL, "points or values is NULL");
+        const size_t in_bytes = sizeof(double) * (size_t)M * (size_t)s->D, out_bytes = sizeof(double) * (size_t)M;
+        void *buf = nullptr;
+        if (hipMalloc(&buf, in_bytes + out_bytes) != hipSuccess)
+            return pso_internal_fail(PSO_ENOMEM, "hipMalloc of %zu bytes failed", in_bytes + out_bytes);
+        double *d_pts = static_cast<double *>(buf), *d_out = d_pts + (size_t)M * (size_t)s->D;
+        hipError_t e = hipMemcpyAsync(d_pts, points, in_bytes, hipMemcpyHostToDevice, s->stream);
+        if (e == hipSuccess) e = pso::launch64_eval(s->fitness, s->a, d_pts, (uint64_t)M, d_out, s->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(values, d_out, out_bytes, hipMemcpyDeviceToHost, s->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+        (void)hipFree(buf);
+        if (e != hipSuccess) return pso_internal_fail(PSO_EDEVICE, "pso64_eval: %s", hipGetErrorString(e));
+        return PSO_OK;
+    });
 }
 
 int pso64_destroy(pso_swarm64 *s)
 {
-    if (!s) return pso_internal_fail(PSO_EINVAL, "swarm is NULL");
-    free64(s);
-    return PSO_OK;
+    return pso::guarded([&]() -> int {
+        if (!s) return pso_internal_fail(PSO_EINVAL, "swarm is NULL");
+        free64(s);
+        return PSO_OK;
+    });
 }
 
 } // extern "C"

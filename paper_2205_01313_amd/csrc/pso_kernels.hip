@@ -44,6 +44,9 @@
 #ifndef PSO_BLOCK
 #define PSO_BLOCK 256
 #endif
+#ifndef PSO_STEP_ONE_K
+#define PSO_STEP_ONE_K 8 // dimension pairs loaded ahead by the one-particle-per-lane step
+#endif
 
 // Bytes of the streamed state that may be kept resident in the memory-side
 // cache (MI355X: 256 MiB of Infinity Cache in front of HBM).  Three quarters
@@ -408,6 +411,43 @@ __global__ void PSO_STEP_ATTR k_step(SwarmArgs a)
         __syncthreads();
     }
     if (arrive_last(c, &flag)) epilogue<VAR>(a, t, false);
+}
+
+// ---------------------------------------------------------------------------
+// One particle per lane, for swarms with too few particles to give every SIMD
+// several wavefronts at four per lane: the rows of the next K dimension pairs
+// are loaded ahead (iterate_one), the aggregation is that of k_step.
+// ---------------------------------------------------------------------------
+template <int FIT, int DC, int K, int POL>
+__global__ void PSO_STEP_ATTR k_step_one(SwarmArgs a)
+{
+    __shared__ unsigned long long wg_min;
+    __shared__ unsigned int wg_count;
+    __shared__ int flag;
+    extern __shared__ float s_dyn[]; // gbest position (D floats), then shift (D floats)
+    Ctrl *c = a.ctrl;
+    if (c->stop) return;
+    const int D = DC > 0 ? DC : a.D;
+    float *s_g = s_dyn, *s_shift = s_dyn + D;
+    const uint32_t t = (uint32_t)(c->t + 1);
+    for (int d = threadIdx.x; d < D; d += BLOCK) {
+        s_g[d] = a.gpos[d];
+        s_shift[d] = a.shift[d];
+    }
+    if (threadIdx.x == 0) {
+        wg_min = NO_KEY;
+        wg_count = 0;
+    }
+    const unsigned long long thr = c->gkey_prev;
+    __syncthreads();
+    const uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
+    uint32_t n_imp = 0;
+    const unsigned long long key = iterate_one<FIT, DC, K, POL>(a, D, i, i < a.N, t, s_g, s_shift, &n_imp);
+    count_improvements(c, n_imp, &wg_count);
+    const unsigned long long m = workgroup_min(key, thr, &wg_min);
+    flush_count(c, &wg_count);
+    publish_sync(c, m, thr);
+    if (arrive_last(c, &flag)) epilogue<VAR_SYNC>(a, t, false);
 }
 
 // ---------------------------------------------------------------------------
@@ -853,10 +893,37 @@ static void launch_split(const SwarmArgs &a, uint32_t L, uint32_t C, hipStream_t
     hipLaunchKernelGGL((k_step_split<FIT, POL>), grid, dim3(BLOCK), lds, stream, a, L, C);
 }
 
+// One particle per lane (k_step_one) for the shapes where it is the faster
+// synchronous step; PSO_STEP_ONE=1 in the environment forces it wherever the
+// variant allows, =0 disables it.
+static bool one_shape(const SwarmArgs &a)
+{
+    const char *env = getenv("PSO_STEP_ONE");
+    const int mode = env ? atoi(env) : -1;
+    if (mode >= 0) return mode == 1;
+    return false;
+}
+
+template <int FIT, int POL>
+static void launch_one(const SwarmArgs &a, hipStream_t stream)
+{
+    constexpr int K = PSO_STEP_ONE_K;
+    const size_t lds = 2 * sizeof(float) * a.D;
+    const dim3 grid((a.N + BLOCK - 1) / BLOCK);
+    switch (PSO_STEP_EXACT_D ? a.D : 0) {
+    case 128: hipLaunchKernelGGL((k_step_one<FIT, 128, K, POL>), grid, dim3(BLOCK), lds, stream, a); break;
+    default: hipLaunchKernelGGL((k_step_one<FIT, 0, K, POL>), grid, dim3(BLOCK), lds, stream, a); break;
+    }
+}
+
 template <int FIT, int VAR, int POL>
 static void launch_step_fvp(const SwarmArgs &a, hipStream_t stream)
 {
     uint32_t L = 0, C = 0;
+    if (VAR == VAR_SYNC && one_shape(a)) {
+        launch_one<FIT, POL>(a, stream);
+        return;
+    }
     if (VAR == VAR_SYNC && split_shape(a, Fitness<FIT>::STAGE_WORDS, &L, &C)) {
         launch_split<FIT, POL>(a, L, C, stream);
         return;

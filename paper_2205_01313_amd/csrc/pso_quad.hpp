@@ -264,6 +264,106 @@ __device__ __forceinline__ unsigned long long iterate_quad(const SwarmArgs &a, i
     return key;
 }
 
+// Steps 2-4 of iteration t for one particle i (i < N) per lane: the form of
+// the step for swarms with too few particles to give every SIMD several
+// wavefronts at four particles per lane.  A lane walks its particle's
+// dimensions in order (the fitness is the same sequential sum, in
+// registers), with the rows of the next K dimension pairs always loaded
+// ahead (a ring of K slots), so one wavefront per SIMD keeps enough loads in
+// flight.  Consecutive lanes read consecutive particles of a row (256 bytes
+// per wavefront).  The deferred pbest positions work as in iterate_quad: an
+// improved particle is marked in pend and its position left in x; the next
+// iteration rewrites p for every lane of a 64-byte group (16 lanes) holding
+// a marked particle.  Must be called by all active lanes of the wavefront
+// together (it ballots).  Returns the particle's new pbest key (NO_KEY if it
+// did not improve).
+__device__ __forceinline__ bool group16_dirty(bool pend)
+{
+    const unsigned long long dirty = __ballot(pend);
+    return ((dirty >> ((threadIdx.x & 63) & ~15u)) & 0xFFFFull) != 0;
+}
+
+template <int FIT, int DC, int K, int POL>
+__device__ __forceinline__ unsigned long long iterate_one(const SwarmArgs &a, int D, uint32_t i, bool active,
+                                                          uint32_t t, const float *s_g, const float *s_shift,
+                                                          uint32_t *n_improved)
+{
+    constexpr bool KX = (POL & KEEP_X) != 0, KV = (POL & KEEP_V) != 0, KP = (POL & KEEP_P) != 0;
+    const size_t Np = a.Np;
+    const float pf_old = active ? a.pf[i] : 0.0f;
+    const bool pend = active && a.pend[i] != 0;
+    const bool line_dirty = group16_dirty(pend);
+    Fitness<FIT> fit;
+    const int npairs = (D + 1) / 2;
+    float rx[K][2], rv[K][2], rp[K][2];
+    auto load_pair = [&](int pr, int s) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int d = 2 * pr + h;
+            if (d < D) {
+                const size_t at = (size_t)d * Np + i;
+                rx[s][h] = KX ? a.x[at] : __builtin_nontemporal_load(a.x + at);
+                rv[s][h] = KV ? a.v[at] : __builtin_nontemporal_load(a.v + at);
+                rp[s][h] = KP ? a.p[at] : __builtin_nontemporal_load(a.p + at);
+            }
+        }
+    };
+    if (active) {
+#pragma unroll
+        for (int s = 0; s < K; ++s)
+            if (s < npairs) load_pair(s, s);
+        for (int b = 0; b < npairs; b += K) {
+#pragma unroll
+            for (int s = 0; s < K; ++s) {
+                const int pr = b + s;
+                if (pr < npairs) {
+                    float cx[2], cv[2], cp[2];
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        cx[h] = rx[s][h];
+                        cv[h] = rv[s][h];
+                        cp[h] = rp[s][h];
+                    }
+                    if (pr + K < npairs) load_pair(pr + K, s);
+                    const U4 u = philox4x32_10(a.k0, a.k1, (uint32_t)pr, i, t, TAG_VEL);
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int d = 2 * pr + h;
+                        if (d < D) {
+                            const float ps = pend ? cx[h] : cp[h];
+                            const float r1 = unit_float(word_r1(u, h));
+                            const float r2 = unit_float(word_r2(u, h));
+                            const float vn = velocity_eq1(a, cx[h], cv[h], ps, s_g[d], r1, r2);
+                            const float xn = position_eq2(a, cx[h], vn);
+                            const size_t at = (size_t)d * Np + i;
+                            if (KX) a.x[at] = xn; else __builtin_nontemporal_store(xn, a.x + at);
+                            if (KV) a.v[at] = vn; else __builtin_nontemporal_store(vn, a.v + at);
+                            if (line_dirty) {
+                                if (KP) a.p[at] = ps; else __builtin_nontemporal_store(ps, a.p + at);
+                            }
+                            fit.add(xn - s_shift[d], d);
+                        }
+                    }
+                }
+            }
+        }
+    }
+    // Step 4: strict improvement; NaN never improves.
+    unsigned long long key = NO_KEY;
+    uint32_t imp = 0;
+    if (active) {
+        const float f = fit.value(D);
+        if (f < pf_old) {
+            imp = 1;
+            a.pf[i] = f;
+            key = make_key(f, i);
+        }
+        if ((imp != 0) != pend) a.pend[i] = (uint8_t)imp;
+    }
+    if (n_improved) *n_improved = imp;
+    return key;
+}
+
 // Folds the staged fitness terms of one particle (column idx of the
 // [dimension][particle] term arrays, row pitch `pitch`) in dimension order.
 // The loads of eight dimensions are issued before their additions, so the

@@ -29,6 +29,7 @@
 #include "pso.h"
 #include "pso_arena.hpp"
 #include "pso_block.hpp"
+#include "pso_guard.hpp"
 #include "pso_device.hpp"
 #include "pso_kernels.hpp"
 
@@ -138,12 +139,14 @@ struct pso_server {
     std::vector<int> ready;              // started or new swarms not in flight
     std::vector<int> fresh;              // slots whose item/state must be uploaded
     std::vector<int> fresh_gang;         // of those, slots whose gang counter must be cleared
+    std::vector<char> pending_upload;    // per slot: admitted, its upload not yet enqueued
     pso::GangSync *h_gang0 = nullptr;    // pinned zeroed GangSync
     std::vector<int> inflight[STREAMS];  // slots of each in-flight launch
     bool busy[STREAMS] = {};
     std::thread th;
     std::atomic<bool> quit{false};
     std::atomic<int> device_error{0};
+    std::atomic<int> order_error{0};     // a launch listed a slot whose upload was not enqueued first
     // statistics (guarded by mu)
     uint64_t submitted = 0, completed = 0, rejected = 0, launches = 0;
     size_t peak_used = 0;
@@ -231,16 +234,20 @@ bool launch_ready(pso_server *s, int k)
             rest.push_back(slot);
         }
     }
-    // upload the items, fresh loop states and shift vectors of the new swarms
-    // this launch runs (others wait for the launch, on either stream, that
-    // runs them: an upload is ordered before its own launch only)
+    // Upload the items, fresh loop states and shift vectors of the new swarms
+    // this launch runs -- the slots in `sel`, nothing else.  An upload is
+    // ordered before the launch on its own stream only, so a fresh slot left
+    // for a later launch keeps its upload pending until that launch (on
+    // either stream) takes it.
+    std::vector<char> in_sel(s->max_slots, 0);
+    for (int slot : sel) in_sel[slot] = 1;
     std::vector<int> fresh_rest, gang_rest;
     for (int slot : s->fresh) {
-        Req *r = s->slot_req[slot];
-        if (r->staged != staged) {
+        if (!in_sel[slot]) {
             fresh_rest.push_back(slot);
             continue;
         }
+        Req *r = s->slot_req[slot];
         if (hipMemcpyAsync(&s->d_items[slot], &s->h_items[slot], sizeof(pso::BatchItem), hipMemcpyHostToDevice, st) !=
                 hipSuccess ||
             hipMemcpyAsync(&s->d_state[slot], &s->h_state[slot], sizeof(pso::BatchResult), hipMemcpyHostToDevice, st) !=
@@ -248,9 +255,10 @@ bool launch_ready(pso_server *s, int k)
             hipMemcpyAsync(const_cast<float *>(s->h_items[slot].a.shift), r->shift.data(), sizeof(float) * r->d.D,
                            hipMemcpyHostToDevice, st) != hipSuccess)
             return false;
+        s->pending_upload[slot] = 0;
     }
     for (int slot : s->fresh_gang) {
-        if (s->slot_req[slot]->staged != staged) {
+        if (!in_sel[slot]) {
             gang_rest.push_back(slot);
             continue;
         }
@@ -260,6 +268,12 @@ bool launch_ready(pso_server *s, int k)
     }
     s->fresh.swap(fresh_rest);
     s->fresh_gang.swap(gang_rest);
+    // every slot of this launch has its upload ordered before the launch
+    for (int slot : sel)
+        if (s->pending_upload[slot]) {
+            s->order_error.store(1);
+            return false;
+        }
     s->ready.swap(sel); // the launch's swarms, until they move to inflight
     // largest per-part work first; a swarm's parts are consecutive
     std::stable_sort(s->ready.begin(), s->ready.end(), [&](int x, int y) {
@@ -381,7 +395,23 @@ bool collect(pso_server *s, int k)
     return true;
 }
 
+void server_pass_loop(pso_server *s);
+
+// The scheduler thread: a failure inside it (a host allocation that throws)
+// stops the server as a device error does -- submit and poll then report
+// it -- instead of ending the process.
 void server_loop(pso_server *s)
+{
+    try {
+        server_pass_loop(s);
+    } catch (...) {
+        s->device_error.store(1);
+        std::lock_guard<std::mutex> g(s->mu);
+        s->cv.notify_all();
+    }
+}
+
+void server_pass_loop(pso_server *s)
 {
     while (!s->quit.load()) {
         bool progressed = false;
@@ -407,6 +437,7 @@ void server_loop(pso_server *s)
                 s->h_items[r->slot] = make_item(s, *r);
                 s->h_state[r->slot] = pso::BatchResult{pso::NO_KEY, 0, 0, 0u, 0u};
                 s->fresh.push_back(r->slot);
+                s->pending_upload[r->slot] = 1;
                 if (r->parts > 1) s->fresh_gang.push_back(r->slot);
                 s->ready.push_back(r->slot);
                 progressed = true;
@@ -450,175 +481,200 @@ extern "C" {
 
 int pso_server_create(size_t mem_budget, int64_t chunk_updates, pso_server **out)
 {
-    if (!out) return pso_internal_fail(PSO_EINVAL, "out is NULL");
-    *out = nullptr;
-    if (mem_budget < 4096) return pso_internal_fail(PSO_EINVAL, "mem_budget too small");
-    pso_server *s = new (std::nothrow) pso_server();
-    if (!s) return pso_internal_fail(PSO_ENOMEM, "host allocation failed");
-    s->budget = mem_budget;
-    s->chunk = chunk_updates > 0 ? chunk_updates : (1LL << 40);
-    if (const char *env = getenv("PSO_SERVER_SLICE_US")) { // tuning override
-        const double v = atof(env);
-        if (v > 0.0) s->slice_us = v;
-    }
-    if (const char *env = getenv("PSO_SERVER_LAUNCH_WAVES")) { // tuning override
-        const int v = atoi(env);
-        if (v > 0) s->launch_waves = v;
-    }
-    s->arena = pso::Arena(mem_budget);
-    // at most one slot per 64 KiB of budget, within [64, 65536]
-    s->max_slots = (int)std::min<size_t>(65536, std::max<size_t>(64, mem_budget / 65536));
-    // two launches may run at once: each gets half of the co-resident
-    // workgroups, so every launch's grid stays fully resident
-    int capacity = 0;
-    if (pso::batch_capacity(MAX_SERVER_D, pso::DEFAULT_BATCH_SHAPE.lanes, &capacity) != hipSuccess || capacity < 2) {
-        server_free(s);
-        return pso_internal_fail(PSO_EDEVICE, "device query failed");
-    }
-    s->grid_cap = capacity / STREAMS;
-    {
-        const char *env = getenv("PSO_SERVER_STAGED");
-        int cap_staged = 0;
-        if (!(env && !strcmp(env, "0")) &&
-            pso::batch_capacity(SERVER_STAGE_MAX_D, SERVER_STAGE_LANES, &cap_staged, SERVER_STAGE_KIB) == hipSuccess &&
-            cap_staged >= STREAMS)
-            s->grid_cap_staged = cap_staged / STREAMS;
-    }
-    {
-        int dev = 0, khz = 0;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
-            s->ticks_per_us = khz / 1000.0;
-    }
-    bool ok = hipMalloc(&s->base, mem_budget) == hipSuccess &&
-              hipMalloc(&s->d_items, sizeof(pso::BatchItem) * s->max_slots) == hipSuccess &&
-              hipMalloc(&s->d_state, sizeof(pso::BatchResult) * s->max_slots) == hipSuccess &&
-              hipMalloc(&s->d_err, sizeof(unsigned int)) == hipSuccess &&
-              hipMemset(s->d_err, 0, sizeof(unsigned int)) == hipSuccess &&
-              hipHostMalloc(reinterpret_cast<void **>(&s->h_gang0), sizeof(pso::GangSync), hipHostMallocDefault) ==
-                  hipSuccess &&
-              hipHostMalloc(reinterpret_cast<void **>(&s->h_items), sizeof(pso::BatchItem) * s->max_slots,
-                            hipHostMallocDefault) == hipSuccess &&
-              hipHostMalloc(reinterpret_cast<void **>(&s->h_state), sizeof(pso::BatchResult) * s->max_slots,
-                            hipHostMallocDefault) == hipSuccess;
-    for (int k = 0; ok && k < STREAMS; ++k) {
-        ok = hipMalloc(&s->d_entries[k], sizeof(pso::BatchEntry) * s->max_slots) == hipSuccess &&
-             hipMalloc(&s->d_next[k], sizeof(unsigned int)) == hipSuccess &&
-             hipMalloc(&s->d_out[k], sizeof(pso::BatchResult) * s->max_slots) == hipSuccess &&
-             hipHostMalloc(reinterpret_cast<void **>(&s->h_out[k]), sizeof(pso::BatchResult) * s->max_slots,
-                           hipHostMallocDefault) == hipSuccess &&
-             hipHostMalloc(reinterpret_cast<void **>(&s->h_entries[k]), sizeof(pso::BatchEntry) * s->max_slots,
-                           hipHostMallocDefault) == hipSuccess &&
-             hipHostMalloc(reinterpret_cast<void **>(&s->h_err[k]), sizeof(unsigned int), hipHostMallocDefault) ==
-                 hipSuccess &&
-             hipStreamCreateWithFlags(&s->st[k], hipStreamNonBlocking) == hipSuccess &&
-             hipEventCreateWithFlags(&s->ev[k], hipEventDisableTiming) == hipSuccess;
-    }
-    if (!ok) {
-        server_free(s);
-        return pso_internal_fail(PSO_ENOMEM, "device or pinned allocation for the server failed");
-    }
-    std::memset(s->h_gang0, 0, sizeof(pso::GangSync));
-    for (int k = 0; k < STREAMS; ++k) s->cap_entries[k] = (size_t)s->max_slots;
-    s->slot_req.assign(s->max_slots, nullptr);
-    for (int k = s->max_slots - 1; k >= 0; --k) s->free_slots.push_back(k);
-    s->th = std::thread(server_loop, s);
-    *out = s;
-    return PSO_OK;
+    return pso::guarded([&]() -> int {
+        if (!out) return pso_internal_fail(PSO_EINVAL, "out is NULL");
+        *out = nullptr;
+        if (mem_budget < 4096) return pso_internal_fail(PSO_EINVAL, "mem_budget too small");
+        pso_server *s = new (std::nothrow) pso_server();
+        if (!s) return pso_internal_fail(PSO_ENOMEM, "host allocation failed");
+        s->budget = mem_budget;
+        s->chunk = chunk_updates > 0 ? chunk_updates : (1LL << 40);
+        if (const char *env = getenv("PSO_SERVER_SLICE_US")) { // tuning override
+            const double v = atof(env);
+            if (v > 0.0) s->slice_us = v;
+        }
+        if (const char *env = getenv("PSO_SERVER_LAUNCH_WAVES")) { // tuning override
+            const int v = atoi(env);
+            if (v > 0) s->launch_waves = v;
+        }
+        s->arena = pso::Arena(mem_budget);
+        // at most one slot per 64 KiB of budget, within [64, 65536]
+        s->max_slots = (int)std::min<size_t>(65536, std::max<size_t>(64, mem_budget / 65536));
+        // two launches may run at once: each gets half of the co-resident
+        // workgroups, so every launch's grid stays fully resident
+        int capacity = 0;
+        if (pso::batch_capacity(MAX_SERVER_D, pso::DEFAULT_BATCH_SHAPE.lanes, &capacity) != hipSuccess || capacity < 2) {
+            server_free(s);
+            return pso_internal_fail(PSO_EDEVICE, "device query failed");
+        }
+        s->grid_cap = capacity / STREAMS;
+        {
+            const char *env = getenv("PSO_SERVER_STAGED");
+            int cap_staged = 0;
+            if (!(env && !strcmp(env, "0")) &&
+                pso::batch_capacity(SERVER_STAGE_MAX_D, SERVER_STAGE_LANES, &cap_staged, SERVER_STAGE_KIB) == hipSuccess &&
+                cap_staged >= STREAMS)
+                s->grid_cap_staged = cap_staged / STREAMS;
+        }
+        {
+            int dev = 0, khz = 0;
+            if (hipGetDevice(&dev) == hipSuccess &&
+                hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
+                s->ticks_per_us = khz / 1000.0;
+        }
+        bool ok = hipMalloc(&s->base, mem_budget) == hipSuccess &&
+                  hipMalloc(&s->d_items, sizeof(pso::BatchItem) * s->max_slots) == hipSuccess &&
+                  hipMalloc(&s->d_state, sizeof(pso::BatchResult) * s->max_slots) == hipSuccess &&
+                  hipMalloc(&s->d_err, sizeof(unsigned int)) == hipSuccess &&
+                  hipMemset(s->d_err, 0, sizeof(unsigned int)) == hipSuccess &&
+                  hipHostMalloc(reinterpret_cast<void **>(&s->h_gang0), sizeof(pso::GangSync), hipHostMallocDefault) ==
+                      hipSuccess &&
+                  hipHostMalloc(reinterpret_cast<void **>(&s->h_items), sizeof(pso::BatchItem) * s->max_slots,
+                                hipHostMallocDefault) == hipSuccess &&
+                  hipHostMalloc(reinterpret_cast<void **>(&s->h_state), sizeof(pso::BatchResult) * s->max_slots,
+                                hipHostMallocDefault) == hipSuccess;
+        for (int k = 0; ok && k < STREAMS; ++k) {
+            ok = hipMalloc(&s->d_entries[k], sizeof(pso::BatchEntry) * s->max_slots) == hipSuccess &&
+                 hipMalloc(&s->d_next[k], sizeof(unsigned int)) == hipSuccess &&
+                 hipMalloc(&s->d_out[k], sizeof(pso::BatchResult) * s->max_slots) == hipSuccess &&
+                 hipHostMalloc(reinterpret_cast<void **>(&s->h_out[k]), sizeof(pso::BatchResult) * s->max_slots,
+                               hipHostMallocDefault) == hipSuccess &&
+                 hipHostMalloc(reinterpret_cast<void **>(&s->h_entries[k]), sizeof(pso::BatchEntry) * s->max_slots,
+                               hipHostMallocDefault) == hipSuccess &&
+                 hipHostMalloc(reinterpret_cast<void **>(&s->h_err[k]), sizeof(unsigned int), hipHostMallocDefault) ==
+                     hipSuccess &&
+                 hipStreamCreateWithFlags(&s->st[k], hipStreamNonBlocking) == hipSuccess &&
+                 hipEventCreateWithFlags(&s->ev[k], hipEventDisableTiming) == hipSuccess;
+        }
+        if (!ok) {
+            server_free(s);
+            return pso_internal_fail(PSO_ENOMEM, "device or pinned allocation for the server failed");
+        }
+        std::memset(s->h_gang0, 0, sizeof(pso::GangSync));
+        for (int k = 0; k < STREAMS; ++k) s->cap_entries[k] = (size_t)s->max_slots;
+        s->slot_req.assign(s->max_slots, nullptr);
+        s->pending_upload.assign(s->max_slots, 0);
+        for (int k = s->max_slots - 1; k >= 0; --k) s->free_slots.push_back(k);
+        try {
+            s->th = std::thread(server_loop, s);
+        } catch (...) {
+            server_free(s);
+            throw;
+        }
+        *out = s;
+        return PSO_OK;
+    });
 }
 
 int pso_server_submit(pso_server *s, const pso_desc *d, uint64_t *ticket)
 {
-    if (!s || !d || !ticket) return pso_internal_fail(PSO_EINVAL, "NULL argument");
-    int rc = pso_internal_check_desc(d);
-    if (rc) return rc;
-    if (s->device_error.load()) return pso_internal_fail(PSO_EDEVICE, "server stopped after a device error");
-    auto r = std::make_unique<Req>();
-    r->d = *d;
-    r->shift.assign(d->D, 0.0f);
-    if (d->shift) std::memcpy(r->shift.data(), d->shift, sizeof(float) * d->D);
-    r->d.shift = nullptr;
-    r->t_submit = Clock::now();
-    const uint32_t staged_parts =
-        s->grid_cap_staged > 0 && d->D <= SERVER_STAGE_MAX_D
-            ? pso::staged_parts((uint64_t)d->N, d->D, d->fitness_id, SERVER_STAGE_KIB, s->grid_cap_staged)
-            : 0;
-    r->staged = staged_parts > 0;
-    r->parts = r->staged ? staged_parts : pso::parts_for((uint64_t)d->N, d->D, s->grid_cap, pso::DEFAULT_BATCH_SHAPE);
-    const size_t bytes = pso::layout_of((uint64_t)d->N, d->D, false).total + pso::gang_bytes(r->parts, d->D);
-    std::lock_guard<std::mutex> g(s->mu);
-    r->ticket = s->next_ticket++;
-    *ticket = r->ticket;
-    s->adm.push(pso::Pending{r->ticket, bytes});
-    s->reqs[r->ticket] = std::move(r);
-    ++s->submitted;
-    s->cv.notify_all();
-    return PSO_OK;
+    return pso::guarded([&]() -> int {
+        if (!s || !d || !ticket) return pso_internal_fail(PSO_EINVAL, "NULL argument");
+        int rc = pso_internal_check_desc(d);
+        if (rc) return rc;
+        if (s->device_error.load()) return pso_internal_fail(PSO_EDEVICE, "server stopped after a device error");
+        auto r = std::make_unique<Req>();
+        r->d = *d;
+        r->shift.assign(d->D, 0.0f);
+        if (d->shift) std::memcpy(r->shift.data(), d->shift, sizeof(float) * d->D);
+        r->d.shift = nullptr;
+        r->t_submit = Clock::now();
+        const uint32_t staged_parts =
+            s->grid_cap_staged > 0 && d->D <= SERVER_STAGE_MAX_D
+                ? pso::staged_parts((uint64_t)d->N, d->D, d->fitness_id, SERVER_STAGE_KIB, s->grid_cap_staged)
+                : 0;
+        r->staged = staged_parts > 0;
+        r->parts = r->staged ? staged_parts : pso::parts_for((uint64_t)d->N, d->D, s->grid_cap, pso::DEFAULT_BATCH_SHAPE);
+        const size_t bytes = pso::layout_of((uint64_t)d->N, d->D, false).total + pso::gang_bytes(r->parts, d->D);
+        std::lock_guard<std::mutex> g(s->mu);
+        // the request is listed before it is queued, and a failure to queue
+        // it unlists it, so the scheduler never admits an unlisted ticket
+        const uint64_t t = s->next_ticket;
+        r->ticket = t;
+        auto ins = s->reqs.emplace(t, std::move(r));
+        try {
+            s->adm.push(pso::Pending{t, bytes});
+        } catch (...) {
+            s->reqs.erase(ins.first);
+            throw;
+        }
+        ++s->next_ticket;
+        *ticket = t;
+        ++s->submitted;
+        s->cv.notify_all();
+        return PSO_OK;
+    });
 }
 
 int pso_server_poll(pso_server *s, uint64_t ticket, pso_result *result, double *latency_ms)
 {
-    if (!s) return pso_internal_fail(PSO_EINVAL, "server is NULL");
-    std::lock_guard<std::mutex> g(s->mu);
-    auto it = s->reqs.find(ticket);
-    if (it == s->reqs.end()) return pso_internal_fail(PSO_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
-    Req *r = it->second.get();
-    if (r->status == PSO_EAGAIN) {
-        if (s->device_error.load()) return pso_internal_fail(PSO_EDEVICE, "server stopped after a device error");
-        return PSO_EAGAIN;
-    }
-    const int status = r->status;
-    if (result) {
-        result->status = status;
-        if (status == PSO_OK) {
-            result->gbest_value = pso::key_fitness(r->res.gkey);
-            result->gbest_iter = r->res.giter;
-            result->iters = r->res.iters;
-            if (result->gbest_pos) std::memcpy(result->gbest_pos, r->gpos.data(), sizeof(float) * r->d.D);
+    return pso::guarded([&]() -> int {
+        if (!s) return pso_internal_fail(PSO_EINVAL, "server is NULL");
+        std::lock_guard<std::mutex> g(s->mu);
+        auto it = s->reqs.find(ticket);
+        if (it == s->reqs.end()) return pso_internal_fail(PSO_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+        Req *r = it->second.get();
+        if (r->status == PSO_EAGAIN) {
+            if (s->device_error.load()) return pso_internal_fail(PSO_EDEVICE, "server stopped after a device error");
+            return PSO_EAGAIN;
         }
-    }
-    if (latency_ms) *latency_ms = ms_since(r->t_submit, r->t_done);
-    s->reqs.erase(it);
-    if (status != PSO_OK) return pso_internal_fail(status, "request %llu needs more device memory than the budget",
-                                                   (unsigned long long)ticket);
-    return PSO_OK;
+        const int status = r->status;
+        if (result) {
+            result->status = status;
+            if (status == PSO_OK) {
+                result->gbest_value = pso::key_fitness(r->res.gkey);
+                result->gbest_iter = r->res.giter;
+                result->iters = r->res.iters;
+                if (result->gbest_pos) std::memcpy(result->gbest_pos, r->gpos.data(), sizeof(float) * r->d.D);
+            }
+        }
+        if (latency_ms) *latency_ms = ms_since(r->t_submit, r->t_done);
+        s->reqs.erase(it);
+        if (status != PSO_OK) return pso_internal_fail(status, "request %llu needs more device memory than the budget",
+                                                       (unsigned long long)ticket);
+        return PSO_OK;
+    });
 }
 
 int pso_server_stats(pso_server *s, pso_server_counters *out)
 {
-    if (!s || !out) return pso_internal_fail(PSO_EINVAL, "NULL argument");
-    std::lock_guard<std::mutex> g(s->mu);
-    out->submitted = s->submitted;
-    out->completed = s->completed;
-    out->rejected = s->rejected;
-    out->queued = s->adm.queued();
-    out->launches = s->launches;
-    out->mem_budget = s->budget;
-    out->mem_used = s->arena.used();
-    out->mem_peak = s->peak_used;
-    std::vector<double> l = s->latencies;
-    out->p50_ms = out->p99_ms = out->max_ms = 0.0;
-    if (!l.empty()) {
-        std::sort(l.begin(), l.end());
-        auto q = [&](double f) { return l[std::min(l.size() - 1, (size_t)(f * (l.size() - 1) + 0.5))]; };
-        out->p50_ms = q(0.50);
-        out->p99_ms = q(0.99);
-        out->max_ms = l.back();
-    }
-    return PSO_OK;
+    return pso::guarded([&]() -> int {
+        if (!s || !out) return pso_internal_fail(PSO_EINVAL, "NULL argument");
+        std::lock_guard<std::mutex> g(s->mu);
+        out->submitted = s->submitted;
+        out->completed = s->completed;
+        out->rejected = s->rejected;
+        out->queued = s->adm.queued();
+        out->launches = s->launches;
+        out->mem_budget = s->budget;
+        out->mem_used = s->arena.used();
+        out->mem_peak = s->peak_used;
+        std::vector<double> l = s->latencies;
+        out->p50_ms = out->p99_ms = out->max_ms = 0.0;
+        if (!l.empty()) {
+            std::sort(l.begin(), l.end());
+            auto q = [&](double f) { return l[std::min(l.size() - 1, (size_t)(f * (l.size() - 1) + 0.5))]; };
+            out->p50_ms = q(0.50);
+            out->p99_ms = q(0.99);
+            out->max_ms = l.back();
+        }
+        return PSO_OK;
+    });
 }
 
 int pso_server_destroy(pso_server *s)
 {
-    if (!s) return pso_internal_fail(PSO_EINVAL, "server is NULL");
-    s->quit.store(true);
-    {
-        std::lock_guard<std::mutex> g(s->mu);
-        s->cv.notify_all();
-    }
-    if (s->th.joinable()) s->th.join();
-    server_free(s);
-    return PSO_OK;
+    return pso::guarded([&]() -> int {
+        if (!s) return pso_internal_fail(PSO_EINVAL, "server is NULL");
+        s->quit.store(true);
+        {
+            std::lock_guard<std::mutex> g(s->mu);
+            s->cv.notify_all();
+        }
+        if (s->th.joinable()) s->th.join();
+        server_free(s);
+        return PSO_OK;
+    });
 }
 
 } // extern "C"

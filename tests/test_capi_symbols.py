@@ -74,3 +74,17 @@ def test_pure_host_entry_points_without_gpu(libpath):
     assert lib.pso64_destroy(None) == _native.PSO_EINVAL
     assert lib.pso64_step(None) == _native.PSO_EINVAL
     assert lib.pso64_eval(None, None, 1, None) == _native.PSO_EINVAL
+
+
+def test_batch_limits_rejected_before_any_allocation(libpath):
+    """Counts beyond a batch's limits fail with a status, on the host, before
+    anything is allocated or any device is touched."""
+    import ctypes
+    from paper_2205_01313_amd import _native
+    lib = _native.load()
+    descs = (_native.PsoDesc * 1)()
+    h = ctypes.c_void_p()
+    assert lib.pso_batch_create(descs, 0, None, ctypes.byref(h)) == _native.PSO_EINVAL
+    assert lib.pso_batch_create(descs, (1 << 24) + 1, None, ctypes.byref(h)) == _native.PSO_EINVAL
+    assert lib.pso_batch_create(descs, 1 << 31, None, ctypes.byref(h)) == _native.PSO_EINVAL
+    assert b"count" in lib.pso_last_error()

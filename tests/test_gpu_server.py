@@ -169,3 +169,34 @@ def test_serving_workload_burst_sampled_against_alone():
         o = oracle_swarm(sp, nthreads=16).run_f32(sp.T, tol=sp.tol, f_star=sp.f_star)
         assert r["iters"] == o["iters"] and r["gbest_fit"] == o["gbest_fit"], (k, sp.fitness, sp.N, sp.D)
         assert r["gbest_iter"] == o["giter"] and np.array_equal(r["gbest_pos"], o["gpos"]), k
+
+
+def test_burst_beyond_two_launches_uploads_before_each_launch(monkeypatch):
+    """One part per workgroup per launch (PSO_SERVER_LAUNCH_WAVES=1) and a
+    burst whose staged parts exceed both streams' launches together: most
+    admitted swarms wait for a later launch, on either stream, and each must
+    still start from its own uploaded item and loop state.  Every result
+    equals the same batch run in one launch (itself equal to each swarm
+    alone), and a sample equals the swarm alone."""
+    monkeypatch.setenv("PSO_SERVER_LAUNCH_WAVES", "1")
+    rng = np.random.default_rng(77)
+    specs = []
+    for k in range(700):
+        fit = wl.FITNESS_NAMES[int(rng.integers(0, 4))]
+        D = int(rng.integers(2, 17))
+        sp = wl.SwarmSpec(fit, int(rng.integers(32, 600)), D, int(rng.integers(20, 120)), seed=1000 + k,
+                          shift_amplitude=2.0)
+        specs.append(sp)
+    announce("server: 700-request burst, one part per workgroup per launch")
+    with pso.Server(1 << 30) as srv:
+        tickets = [srv.submit(sp) for sp in specs]
+        res = wait_all(srv, tickets, timeout=240.0)
+        st = srv.stats()
+    assert st["completed"] == len(specs) and st["launches"] > 2
+    ref = pso.pso_batch_run(specs)
+    for sp, t, b in zip(specs, tickets, ref):
+        r = res[t]
+        assert r["gbest_fit"] == b["gbest_fit"] and r["iters"] == b["iters"], sp
+        assert r["gbest_iter"] == b["gbest_iter"] and np.array_equal(r["gbest_pos"], b["gbest_pos"]), sp
+    sample = list(range(0, len(specs), 35))
+    check_same([specs[k] for k in sample], [tickets[k] for k in sample], res)

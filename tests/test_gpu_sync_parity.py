@@ -60,17 +60,23 @@ def test_golden_rastrigin_trajectory():
     assert r["gbest_iter"] == giter
 
 
-def test_large_rastrigin_full_size_first_iterations():
-    """Rastrigin D=32, N=2^20 (the benchmark's workload) for 6 iterations: the
-    whole state, bit for bit."""
-    spec = wl.large_rastrigin(seed=0)
-    run_both(spec, 6, nthreads=16)
+@pytest.mark.parametrize("seed", [0, 1])
+def test_large_rastrigin_full_run(seed):
+    """The benchmark's workload in full -- Rastrigin D=32, N=2^20, all 200
+    iterations (Alg. 1 Steps 2-5 with the per-iteration gbest of Sec. 2.2)
+    -- for seeds 0 and 1: the gbest key of every iteration, the iteration of
+    the last change and the final x, v, pbest position, pbest fitness and
+    gbest position, bit for bit."""
+    spec = wl.large_rastrigin(seed=seed)
+    run_both(spec, spec.T, nthreads=16)
 
 
 @pytest.mark.parametrize("mk", [wl.deep_rosenbrock, wl.deep_ackley])
-def test_deep_d128_full_size_first_iterations(mk):
-    spec = mk(seed=3)
-    run_both(spec, 4, nthreads=16)
+def test_deep_d128_full_run(mk):
+    """Rosenbrock and shifted Ackley, D=128, N=65536, all 2000 iterations
+    (the split step): the whole trajectory and the final state, bit for bit."""
+    spec = mk(seed=0)
+    run_both(spec, spec.T, nthreads=16)
 
 
 @pytest.mark.parametrize("split", ["0", "1"])
@@ -85,6 +91,32 @@ def test_split_and_plain_steps_equal_oracle(monkeypatch, split, fit, N, D):
     T = 30
     spec = wl.SwarmSpec(fit, N, D, T, seed=N + 7 * D, shift_amplitude=2.0)
     announce(f"split={split} {fit} N={N} D={D} T={T}")
+    o = oracle_swarm(spec, 8).run_f32(T)
+    with gpu_swarm(spec) as g:
+        g.step(T)
+        hist = g.history(0, T + 1)
+        st = g.state()
+        b = g.best()
+    bad = np.flatnonzero(hist != o["hist"])
+    assert bad.size == 0, f"gbest key differs first at iteration {bad[0]}"
+    assert b["gbest_iter"] == o["giter"] and st["t"] == T
+    assert_state_equal(st, o, N, D)
+
+
+@pytest.mark.parametrize("fit", wl.FITNESS_NAMES)
+@pytest.mark.parametrize("N,D", [(4099, 16), (2050, 17), (3001, 33), (1025, 130), (701, 200), (129, 512),
+                                 (1000, 128), (70, 3)])
+def test_one_particle_per_lane_step_equals_oracle(monkeypatch, fit, N, D):
+    """The step with one particle per lane and the rows of the next dimension
+    pairs loaded ahead (forced with PSO_STEP_ONE=1): bit-exact against the
+    oracle over ragged particle counts and odd D, including a D fixed at
+    compile time (128) and a prefetch ring longer than the dimension pairs."""
+    if fit == "rosenbrock" and D < 2:
+        pytest.skip("Rosenbrock needs D >= 2")
+    monkeypatch.setenv("PSO_STEP_ONE", "1")
+    T = 30
+    spec = wl.SwarmSpec(fit, N, D, T, seed=3 * N + D, shift_amplitude=2.0)
+    announce(f"one particle per lane {fit} N={N} D={D} T={T}")
     o = oracle_swarm(spec, 8).run_f32(T)
     with gpu_swarm(spec) as g:
         g.step(T)
@@ -228,3 +260,42 @@ def test_two_kernel_reduction_comparator_equals_oracle(variant, fit, N, D):
     assert np.array_equal(h, o["hist"])
     assert r["gbest_iter"] == o["giter"]
     assert_state_equal(st, o, spec.N, spec.D)
+
+
+@pytest.mark.parametrize("fit,N,D", [("cubic", 16384, 1), ("rastrigin", 30000, 5), ("ackley", 5000, 40)])
+def test_run_graph_replays_equal_oracle_and_direct_launches(monkeypatch, fit, N, D):
+    """pso_run replays a captured graph of step launches: several pso_run
+    calls (each several replays plus direct launches), eager pso_step work
+    and host synchronisations between them, with and without the stop rule;
+    after each call the whole gbest trajectory so far equals the oracle's, and
+    the final state equals the same calls with every step launched directly
+    (PSO_RUN_GRAPH=0)."""
+    spec = wl.SwarmSpec(fit, N, D, 200, seed=N + D, shift_amplitude=1.0)
+    announce(f"run graph {fit} N={N} D={D}")
+    o = oracle_swarm(spec, 16).run_f32(129)
+    states = {}
+    for mode in ("1", "0"):
+        monkeypatch.setenv("PSO_RUN_GRAPH", mode)
+        with gpu_swarm(spec) as g:
+            t = 0
+            for n, eager in ((37, 3), (40, 0), (17, 5), (24, 3)):
+                r = g.run(n)
+                t += n
+                assert r["iters"] == n
+                assert np.array_equal(g.history(0, t + 1), o["hist"][: t + 1]), (mode, t)
+                g.step(eager)
+                g.sync()
+                t += eager
+                assert np.array_equal(g.history(0, t + 1), o["hist"][: t + 1]), (mode, t)
+            states[mode] = g.state()
+            assert states[mode]["t"] == 129
+        assert_state_equal(states[mode], o, N, D)
+    # the stop rule over replays: the same stopping iteration as the oracle
+    monkeypatch.setenv("PSO_RUN_GRAPH", "1")
+    f_star = float(o["gbest_fit"])
+    tol = abs(f_star) * 1e-5 + 1e-6
+    os_ = oracle_swarm(spec, 16).run_f32(200, tol=tol, f_star=f_star)
+    assert os_["iters"] <= 129
+    with gpu_swarm(spec) as g:
+        r = g.run(200, tol=tol, f_star=f_star)
+    assert r["iters"] == os_["iters"] and r["gbest_fit"] == os_["gbest_fit"]
