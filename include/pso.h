@@ -46,6 +46,8 @@ extern "C" {
 #define PSO_EDEVICE (-3) /* the HIP runtime or a kernel reported an error */
 #define PSO_EAGAIN (-4)  /* a result is not ready yet (server polling) */
 #define PSO_ESTATE (-5)  /* the call does not fit the object's current state */
+#define PSO_ECANCELED (-6) /* a server request was cancelled (pso_server_cancel) */
+#define PSO_ETIMEDOUT (-7) /* a server request did not finish by its deadline */
 
 /* Fitness functions, all minimised over f(x) = F(x - shift). */
 #define PSO_SPHERE 0     /* sum z^2 */
@@ -349,6 +351,7 @@ typedef struct pso_server_counters {
     uint64_t submitted, completed, rejected, queued, launches;
     size_t mem_budget, mem_used, mem_peak; /* device bytes of swarm state */
     double p50_ms, p99_ms, max_ms;         /* submit-to-completion latency of completed requests */
+    uint64_t cancelled, timed_out;         /* requests ended by pso_server_cancel / their deadline */
 } pso_server_counters;
 
 /* Starts a server with mem_budget bytes of device memory for swarm state
@@ -368,9 +371,27 @@ int pso_server_submit(pso_server *srv, const pso_desc *desc, uint64_t *ticket);
 
 /* PSO_EAGAIN while the request is queued or running.  Once it is done, fills
  * *result (result->gbest_pos as for batches) and the submit-to-completion
- * latency, forgets the ticket and returns PSO_OK -- or PSO_ENOMEM if the
- * request needs more memory than the whole budget.  Unknown ticket: EINVAL. */
+ * latency, forgets the ticket and returns PSO_OK -- or, also forgetting the
+ * ticket, PSO_ENOMEM if the request needs more memory than the whole budget,
+ * PSO_ECANCELED or PSO_ETIMEDOUT if it was cancelled or passed its deadline
+ * (the latency is then submit-to-drop).  Unknown ticket: EINVAL. */
 int pso_server_poll(pso_server *srv, uint64_t ticket, pso_result *result, double *latency_ms);
+
+/* Cancels a request.  A request still waiting for memory leaves the queue at
+ * once; an admitted one leaves at the scheduler's next decision about it --
+ * before its next launch, or when its running launch ends (if that launch
+ * finishes it, its result stands) -- and its memory returns to the budget.
+ * pso_server_poll then reports PSO_ECANCELED.  Unknown ticket: EINVAL; a
+ * request that has already finished (or was rejected): ESTATE. */
+int pso_server_cancel(pso_server *srv, uint64_t ticket);
+
+/* Gives a request a deadline timeout_ms after its submission (> 0 and
+ * finite).  A request not finished by then is dropped as pso_server_cancel
+ * drops it, and pso_server_poll reports PSO_ETIMEDOUT; the result of a launch
+ * that finishes it before the drop stands.  The scheduler checks deadlines
+ * every pass (about every 50 us while idle).  Unknown ticket: EINVAL;
+ * finished request: ESTATE. */
+int pso_server_set_deadline(pso_server *srv, uint64_t ticket, double timeout_ms);
 
 /* Counters, memory use and latency percentiles since the server started. */
 int pso_server_stats(pso_server *srv, pso_server_counters *stats);

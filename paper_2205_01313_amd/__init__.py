@@ -12,9 +12,9 @@ import ctypes
 import numpy as np
 
 from . import _native
-from ._native import (PSO_ACKLEY, PSO_ASYNC, PSO_CUBIC, PSO_EAGAIN, PSO_EDEVICE, PSO_EINVAL,  # noqa: F401
-                      PSO_ENOMEM, PSO_ESTATE, PSO_OK, PSO_PERSISTENT, PSO_RASTRIGIN, PSO_REDUCE, PSO_REDUCE_UNROLLED,
-                      PSO_ROSENBROCK, PSO_SPHERE, PSO_SYNC)
+from ._native import (PSO_ACKLEY, PSO_ASYNC, PSO_CUBIC, PSO_EAGAIN, PSO_ECANCELED, PSO_EDEVICE,  # noqa: F401
+                      PSO_EINVAL, PSO_ENOMEM, PSO_ESTATE, PSO_ETIMEDOUT, PSO_OK, PSO_PERSISTENT, PSO_RASTRIGIN,
+                      PSO_REDUCE, PSO_REDUCE_UNROLLED, PSO_ROSENBROCK, PSO_SPHERE, PSO_SYNC)
 
 FITNESS = {"sphere": PSO_SPHERE, "rastrigin": PSO_RASTRIGIN, "rosenbrock": PSO_ROSENBROCK,
            "ackley": PSO_ACKLEY, "cubic": PSO_CUBIC}
@@ -331,6 +331,12 @@ class Server:
         _check(rc, "pso_server_poll")
         return dict(gbest_fit=np.float32(res.gbest_value), gbest_pos=pos, gbest_iter=res.gbest_iter,
                     iters=res.iters, latency_ms=lat.value)
+
+    def cancel(self, ticket):
+        _check(lib().pso_server_cancel(self.h, int(ticket)), "pso_server_cancel")
+
+    def set_deadline(self, ticket, timeout_ms):
+        _check(lib().pso_server_set_deadline(self.h, int(ticket), float(timeout_ms)), "pso_server_set_deadline")
 
     def stats(self):
         c = _native.PsoServerCounters()

@@ -9,6 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpso.so")
 
 PSO_OK, PSO_EINVAL, PSO_ENOMEM, PSO_EDEVICE, PSO_EAGAIN, PSO_ESTATE = 0, -1, -2, -3, -4, -5
+PSO_ECANCELED, PSO_ETIMEDOUT = -6, -7
 PSO_SPHERE, PSO_RASTRIGIN, PSO_ROSENBROCK, PSO_ACKLEY, PSO_CUBIC = 0, 1, 2, 3, 4
 PSO_SYNC, PSO_ASYNC, PSO_REDUCE, PSO_REDUCE_UNROLLED, PSO_PERSISTENT = 0, 1, 2, 3, 4
 
@@ -43,7 +44,8 @@ class PsoServerCounters(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("rejected", ctypes.c_uint64),
                 ("queued", ctypes.c_uint64), ("launches", ctypes.c_uint64), ("mem_budget", ctypes.c_size_t),
                 ("mem_used", ctypes.c_size_t), ("mem_peak", ctypes.c_size_t), ("p50_ms", ctypes.c_double),
-                ("p99_ms", ctypes.c_double), ("max_ms", ctypes.c_double)]
+                ("p99_ms", ctypes.c_double), ("max_ms", ctypes.c_double), ("cancelled", ctypes.c_uint64),
+                ("timed_out", ctypes.c_uint64)]
 
 
 # name -> (restype, argtypes), in the order of include/pso.h
@@ -84,6 +86,8 @@ SIGNATURES = {
     "pso_server_create": (c_int, [c_size, c_i64, P(c_vp)]),
     "pso_server_submit": (c_int, [c_vp, P(PsoDesc), P(c_u64)]),
     "pso_server_poll": (c_int, [c_vp, c_u64, P(PsoResult), P(ctypes.c_double)]),
+    "pso_server_cancel": (c_int, [c_vp, c_u64]),
+    "pso_server_set_deadline": (c_int, [c_vp, c_u64, ctypes.c_double]),
     "pso_server_stats": (c_int, [c_vp, P(PsoServerCounters)]),
     "pso_server_destroy": (c_int, [c_vp]),
 }

@@ -19,6 +19,7 @@
 #include <condition_variable>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <new>
@@ -50,7 +51,10 @@ struct Req {
     pso_desc d{};
     std::vector<float> shift;
     Clock::time_point t_submit, t_done;
-    int status = PSO_EAGAIN; // PSO_OK when done, PSO_ENOMEM when rejected
+    int status = PSO_EAGAIN; // PSO_OK when done, PSO_ENOMEM rejected, PSO_ECANCELED / PSO_ETIMEDOUT dropped
+    // set by pso_server_cancel or a passed deadline while the request is
+    // admitted: the scheduler drops it at its next scheduling point
+    std::atomic<int> drop_code{0};
     size_t off = 0;
     int slot = -1;
     uint32_t parts = 1;
@@ -149,8 +153,14 @@ struct pso_server {
     std::atomic<int> order_error{0};     // a launch listed a slot whose upload was not enqueued first
     // statistics (guarded by mu)
     uint64_t submitted = 0, completed = 0, rejected = 0, launches = 0;
+    uint64_t cancelled = 0, timed_out = 0;
     size_t peak_used = 0;
     std::vector<double> latencies;
+    std::multimap<Clock::time_point, uint64_t> deadlines; // (deadline, ticket), guarded by mu
+    // the server's clock (submit and completion times, deadlines); a unit
+    // test of the host scheduler replaces it by a fake one
+    std::atomic<Clock::time_point (*)()> clock{&Clock::now};
+    Clock::time_point now() const { return clock.load()(); }
 };
 
 namespace {
@@ -204,6 +214,53 @@ pso::BatchItem make_item(pso_server *s, const Req &r)
     it.fstar = r.d.f_star;
     pso::bind_gang(&it, static_cast<char *>(s->base) + r.off + L.total, r.parts);
     return it;
+}
+
+// Ends an admitted request that was cancelled or passed its deadline and is
+// not in flight: its memory and slot return to the pool, a pending upload is
+// forgotten, and a poll then reports the code.  Scheduler thread.
+void drop_slot(pso_server *s, int slot)
+{
+    Req *r = s->slot_req[slot];
+    s->pending_upload[slot] = 0;
+    s->fresh.erase(std::remove(s->fresh.begin(), s->fresh.end(), slot), s->fresh.end());
+    s->fresh_gang.erase(std::remove(s->fresh_gang.begin(), s->fresh_gang.end(), slot), s->fresh_gang.end());
+    std::lock_guard<std::mutex> g(s->mu);
+    const int code = r->drop_code.load();
+    r->status = code;
+    r->t_done = s->now();
+    ++(code == PSO_ETIMEDOUT ? s->timed_out : s->cancelled);
+    s->arena.release(r->off);
+    s->slot_req[slot] = nullptr;
+    s->free_slots.push_back(slot);
+    s->cv.notify_all();
+}
+
+// Requests whose deadline has passed: a queued one leaves the queue now, an
+// admitted one is marked for drop_slot.  Under s->mu; true if any expired.
+bool expire_deadlines(pso_server *s)
+{
+    bool any = false;
+    const auto now = s->now();
+    while (!s->deadlines.empty() && s->deadlines.begin()->first <= now) {
+        const uint64_t t = s->deadlines.begin()->second;
+        s->deadlines.erase(s->deadlines.begin());
+        auto it = s->reqs.find(t);
+        if (it == s->reqs.end()) continue;
+        Req *r = it->second.get();
+        if (r->status != PSO_EAGAIN) continue;
+        any = true;
+        if (r->slot < 0 && s->adm.cancel(t)) {
+            r->status = PSO_ETIMEDOUT;
+            r->t_done = now;
+            ++s->timed_out;
+            s->cv.notify_all();
+        } else {
+            int none = 0;
+            r->drop_code.compare_exchange_strong(none, PSO_ETIMEDOUT);
+        }
+    }
+    return any;
 }
 
 // Launches one chunk on stream k over ready swarms of one kind (staged or
@@ -363,6 +420,8 @@ bool collect(pso_server *s, int k)
         r->prev_iters = r->res.iters;
         if (r->res.stop || r->res.iters >= r->d.max_iter)
             done_j.push_back(j);
+        else if (r->drop_code.load())
+            drop_slot(s, slot); // cancelled or past its deadline, not finished by this launch
         else
             s->ready.push_back(slot);
     }
@@ -373,9 +432,9 @@ bool collect(pso_server *s, int k)
             hipStreamSynchronize(st) != hipSuccess)
             return false;
     }
-    const auto now = Clock::now();
     {
         std::lock_guard<std::mutex> g(s->mu);
+        const auto now = s->now();
         for (int j : done_j) {
             const int slot = s->inflight[k][j];
             Req *r = s->slot_req[slot];
@@ -424,7 +483,7 @@ void server_pass_loop(pso_server *s)
             for (uint64_t t : rejected) {
                 Req *r = s->reqs[t].get();
                 r->status = PSO_ENOMEM;
-                r->t_done = Clock::now();
+                r->t_done = s->now();
                 ++s->rejected;
                 progressed = true;
             }
@@ -444,6 +503,20 @@ void server_pass_loop(pso_server *s)
             }
             s->peak_used = std::max(s->peak_used, s->arena.used());
             if (!rejected.empty()) s->cv.notify_all();
+            if (expire_deadlines(s)) progressed = true;
+        }
+        // admitted requests cancelled or past their deadline and not in
+        // flight leave now; those in flight leave when their launch ends
+        for (size_t j = 0; j < s->ready.size();) {
+            const int slot = s->ready[j];
+            if (s->slot_req[slot]->drop_code.load()) {
+                s->ready[j] = s->ready.back();
+                s->ready.pop_back();
+                drop_slot(s, slot);
+                progressed = true;
+            } else {
+                ++j;
+            }
         }
         // collect finished launches, then launch on free streams
         for (int k = 0; k < STREAMS; ++k) {
@@ -578,7 +651,7 @@ int pso_server_submit(pso_server *s, const pso_desc *d, uint64_t *ticket)
         r->shift.assign(d->D, 0.0f);
         if (d->shift) std::memcpy(r->shift.data(), d->shift, sizeof(float) * d->D);
         r->d.shift = nullptr;
-        r->t_submit = Clock::now();
+        r->t_submit = s->now();
         const uint32_t staged_parts =
             s->grid_cap_staged > 0 && d->D <= SERVER_STAGE_MAX_D
                 ? pso::staged_parts((uint64_t)d->N, d->D, d->fitness_id, SERVER_STAGE_KIB, s->grid_cap_staged)
@@ -630,8 +703,55 @@ int pso_server_poll(pso_server *s, uint64_t ticket, pso_result *result, double *
         }
         if (latency_ms) *latency_ms = ms_since(r->t_submit, r->t_done);
         s->reqs.erase(it);
-        if (status != PSO_OK) return pso_internal_fail(status, "request %llu needs more device memory than the budget",
-                                                       (unsigned long long)ticket);
+        if (status == PSO_ENOMEM)
+            return pso_internal_fail(status, "request %llu needs more device memory than the budget",
+                                     (unsigned long long)ticket);
+        if (status == PSO_ECANCELED) return pso_internal_fail(status, "request %llu was cancelled", (unsigned long long)ticket);
+        if (status == PSO_ETIMEDOUT)
+            return pso_internal_fail(status, "request %llu passed its deadline", (unsigned long long)ticket);
+        return PSO_OK;
+    });
+}
+
+int pso_server_cancel(pso_server *s, uint64_t ticket)
+{
+    return pso::guarded([&]() -> int {
+        if (!s) return pso_internal_fail(PSO_EINVAL, "server is NULL");
+        std::lock_guard<std::mutex> g(s->mu);
+        auto it = s->reqs.find(ticket);
+        if (it == s->reqs.end()) return pso_internal_fail(PSO_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+        Req *r = it->second.get();
+        if (r->status != PSO_EAGAIN)
+            return pso_internal_fail(PSO_ESTATE, "request %llu has already finished", (unsigned long long)ticket);
+        if (r->slot < 0 && s->adm.cancel(ticket)) { // still queued: leaves now
+            r->status = PSO_ECANCELED;
+            r->t_done = s->now();
+            ++s->cancelled;
+        } else { // admitted: the scheduler drops it
+            int none = 0;
+            r->drop_code.compare_exchange_strong(none, PSO_ECANCELED);
+        }
+        s->cv.notify_all();
+        return PSO_OK;
+    });
+}
+
+int pso_server_set_deadline(pso_server *s, uint64_t ticket, double timeout_ms)
+{
+    return pso::guarded([&]() -> int {
+        if (!s) return pso_internal_fail(PSO_EINVAL, "server is NULL");
+        if (!(timeout_ms > 0.0) || !(timeout_ms < 1e12))
+            return pso_internal_fail(PSO_EINVAL, "timeout_ms must be positive and finite");
+        std::lock_guard<std::mutex> g(s->mu);
+        auto it = s->reqs.find(ticket);
+        if (it == s->reqs.end()) return pso_internal_fail(PSO_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+        Req *r = it->second.get();
+        if (r->status != PSO_EAGAIN)
+            return pso_internal_fail(PSO_ESTATE, "request %llu has already finished", (unsigned long long)ticket);
+        const auto at = r->t_submit + std::chrono::duration_cast<Clock::duration>(
+                                          std::chrono::duration<double, std::milli>(timeout_ms));
+        s->deadlines.emplace(at, ticket);
+        s->cv.notify_all();
         return PSO_OK;
     });
 }
@@ -644,6 +764,8 @@ int pso_server_stats(pso_server *s, pso_server_counters *out)
         out->submitted = s->submitted;
         out->completed = s->completed;
         out->rejected = s->rejected;
+        out->cancelled = s->cancelled;
+        out->timed_out = s->timed_out;
         out->queued = s->adm.queued();
         out->launches = s->launches;
         out->mem_budget = s->budget;

@@ -200,3 +200,52 @@ def test_burst_beyond_two_launches_uploads_before_each_launch(monkeypatch):
         assert r["gbest_iter"] == b["gbest_iter"] and np.array_equal(r["gbest_pos"], b["gbest_pos"]), sp
     sample = list(range(0, len(specs), 35))
     check_same([specs[k] for k in sample], [tickets[k] for k in sample], res)
+
+
+def wait_code(srv, ticket, timeout=60.0):
+    """Polls until the request ends; returns (status code, result or None)."""
+    t0 = time.time()
+    while True:
+        try:
+            r = srv.poll(ticket)
+        except pso.PsoError as e:
+            return e.code, None
+        if r is not None:
+            return pso.PSO_OK, r
+        assert time.time() - t0 < timeout
+        time.sleep(0.001)
+
+
+def test_cancel_and_deadlines_free_memory_and_others_continue():
+    """A request that would run far longer than the test is cancelled while
+    running; one waiting for memory behind it is cancelled at once; another
+    passes its deadline while waiting; afterwards the budget is free and a
+    new request's result equals the swarm alone."""
+    big = wl.SwarmSpec("rastrigin", 200000, 32, 10 ** 7, seed=3)
+    need = pso.pso_workspace_bytes(big.N, big.D)
+    announce("server: cancel and deadlines")
+    with pso.Server(int(need * 1.5)) as srv:
+        t_run = srv.submit(big)
+        while srv.stats()["launches"] < 2:
+            time.sleep(0.001)
+        t_wait = srv.submit(big)  # waits for memory
+        t_q = srv.submit(big)
+        srv.cancel(t_q)
+        assert wait_code(srv, t_q)[0] == pso.PSO_ECANCELED
+        srv.set_deadline(t_wait, 30.0)
+        assert wait_code(srv, t_wait)[0] == pso.PSO_ETIMEDOUT
+        srv.cancel(t_run)
+        assert wait_code(srv, t_run)[0] == pso.PSO_ECANCELED
+        with pytest.raises(pso.PsoError) as e:
+            srv.cancel(t_run)  # forgotten after the poll
+        assert e.value.code == pso.PSO_EINVAL
+        st = srv.stats()
+        assert st["cancelled"] == 2 and st["timed_out"] == 1 and st["mem_used"] == 0
+        small = wl.SwarmSpec("ackley", 3000, 12, 150, seed=9, shift_amplitude=2.0)
+        t = srv.submit(small)
+        code, r = wait_code(srv, t)
+        assert code == pso.PSO_OK
+        with pytest.raises(pso.PsoError) as e:
+            srv.cancel(t)  # finished and polled: unknown
+        assert e.value.code == pso.PSO_EINVAL
+    check_same([small], [t], {t: r})
