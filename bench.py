@@ -34,7 +34,7 @@ CLOCK_MHZ = 2400.0
 
 # Sources that define the grid step kernel: a counter summary taken on other
 # sources is stale.
-STEP_SOURCES = ["pso_device.hpp", "pso_quad.hpp", "pso_kernels.hpp", "pso_kernels.hip"]
+STEP_SOURCES = ["pso_device.hpp", "pso_aggregate.hpp", "pso_quad.hpp", "pso_kernels.hpp", "pso_kernels.hip"]
 
 
 def source_digest() -> str:

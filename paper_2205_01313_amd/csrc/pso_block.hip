@@ -21,6 +21,7 @@
 #include <cstdlib>
 #include <cstring>
 
+#include "pso_aggregate.hpp"
 #include "pso_block.hpp"
 #include "pso_quad.hpp"
 
@@ -51,20 +52,6 @@ __device__ __forceinline__ bool meets_tol(unsigned long long key, float tol, flo
     return tol > 0.0f && __builtin_fabsf(key_fitness(key) - fstar) < tol;
 }
 
-// Workgroup minimum of candidate keys (key < thr) into *slot (NO_KEY before
-// the call); ends with a barrier and returns the minimum in every lane.
-__device__ __forceinline__ unsigned long long block_min(unsigned long long key, unsigned long long thr,
-                                                        unsigned long long *slot)
-{
-    const bool cand = key < thr;
-    if (__ballot(cand)) {
-        const unsigned long long m = wave_min_u64(cand ? key : NO_KEY);
-        if ((threadIdx.x & 63) == 0) atomicMin(slot, m);
-    }
-    __syncthreads();
-    return *slot;
-}
-
 // The share of a swarm one workgroup runs: particle quads [q_lo, q_hi)
 // (4q < N), padded quads [qi_lo, qi_hi) initialised by it (4q < Np), and for
 // a swarm of several parts, their meeting point.
@@ -90,7 +77,7 @@ __device__ __forceinline__ Part whole_swarm(const SwarmArgs &a)
 
 // Workgroup-shared scratch of the per-swarm loop.
 struct Scratch {
-    unsigned long long min[2]; // block_min slots, alternating by step
+    unsigned long long min[2]; // workgroup_min slots, alternating by step
     unsigned long long bkey;   // broadcast of the combined key
     unsigned int owner;        // broadcast of the part owning it
     unsigned int err;          // a wait gave up
@@ -219,7 +206,7 @@ __device__ void block_init(const SwarmArgs &a, const Part &P, const float *s_shi
         const unsigned long long k = init_quad<FIT, PSO_SWARM_POLICY>(a, D, q, s_shift);
         key = k < key ? k : key;
     }
-    const unsigned long long m = block_min(key, NO_KEY, &sc->min[0]);
+    const unsigned long long m = workgroup_min(key, NO_KEY, &sc->min[0]);
     if (threadIdx.x == 0) sc->min[1] = NO_KEY;
     uint32_t owner;
     const unsigned long long g = gang_min<LANES>(a, P, 0, m, sc, &owner);
@@ -251,7 +238,7 @@ __device__ void block_iterate(const SwarmArgs &a, const Part &P, long long T, fl
             key = k < key ? k : key;
             n_imp += n;
         }
-        const unsigned long long m = block_min(key, L.gkey, &sc->min[t & 1]);
+        const unsigned long long m = workgroup_min(key, L.gkey, &sc->min[t & 1]);
         if (threadIdx.x == 0) sc->min[(t + 1) & 1] = NO_KEY;
         uint32_t owner;
         const unsigned long long g = gang_min<LANES>(a, P, t, m, sc, &owner);
@@ -637,7 +624,7 @@ __device__ uint32_t staged_iterate(const SwarmArgs &a, const Staged &S, const Pa
             }
             la.pend[sidx] = imp ? 1 : 0;
         }
-        const unsigned long long m = block_min(key, L.gkey, &sc->min[t & 1]);
+        const unsigned long long m = workgroup_min(key, L.gkey, &sc->min[t & 1]);
         if (threadIdx.x == 0) sc->min[(t + 1) & 1] = NO_KEY;
         unsigned long long g = m;
         uint32_t owner = 0;
