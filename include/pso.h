@@ -285,6 +285,33 @@ int pso_batch_destroy(pso_batch *b);
 /* pso_batch_create + pso_batch_launch + pso_batch_results + destroy. */
 int pso_batch_run(const pso_desc *descs, int64_t count, pso_result *results);
 
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc, such as tight serving loops or harnesses that forbid it):
+ * pso_batch_run without any allocation.  Every device buffer the batch
+ * needs (each swarm's state, the descriptors, the work queue, the results
+ * and counters) is carved out of one fixed array of PSO_STATIC_SCRATCH_BYTES
+ * that the library keeps on each device it runs on, from its first use there
+ * until the process ends; host staging is fixed-size as well.  Results are
+ * bit for bit those of pso_batch_run (same kernels, the default batch shape;
+ * the autotuner and graph capture are not used).
+ *   descs, count  as pso_batch_run; count <= PSO_STATIC_MAX_SWARMS.
+ *   results       caller host memory, count entries (gbest_pos as in
+ *                 pso_batch_results).
+ *   hip_stream    a hipStream_t on the current device, or NULL for its null
+ *                 stream; the call synchronises it before returning.
+ * Errors: PSO_EINVAL for a bad descriptor, count out of range or more than
+ * PSO_STATIC_MAX_ENTRIES work-queue entries; PSO_ENOMEM when the swarms'
+ * state and bookkeeping exceed the scratch (nothing is launched then);
+ * PSO_EDEVICE for a HIP error.  Calls in one process are serialised by the
+ * library; each call overwrites the scratch of the current device, whose
+ * contents are the last call's afterwards.  Work of another process, or
+ * kernels of this one still reading a previous call's state, must not
+ * overlap a call on the same device. */
+#define PSO_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+#define PSO_STATIC_MAX_SWARMS 1024
+#define PSO_STATIC_MAX_ENTRIES 16384u
+int pso_batch_run_static(const pso_desc *descs, int64_t count, pso_result *results, void *hip_stream);
+
 /* Tiles and schedule of a batch's launches (they change the time, never the
  * results).  stage_kib = 0 streams each swarm's state from device memory
  * every iteration: lanes per workgroup (64, 128 or 256), co-resident

@@ -367,6 +367,33 @@ def pso_batch_run(specs):
         return b.results()
 
 
+def _run_descs(fn, specs, *extra):
+    specs = list(specs)
+    arr, keep = _descs(specs)
+    n = len(specs)
+    res = (_native.PsoResult * n)()
+    pos = [np.empty(int(sp.D), np.float32) for sp in specs]
+    for k in range(n):
+        res[k].gbest_pos = pos[k].ctypes.data
+    _check(getattr(lib(), fn)(arr, n, res, *extra), fn)
+    del keep
+    return [dict(gbest_fit=np.float32(res[k].gbest_value), gbest_iter=res[k].gbest_iter, iters=res[k].iters,
+                 gbest_pos=pos[k]) for k in range(n)]
+
+
+def pso_batch_run_c(specs):
+    """The C call pso_batch_run (create, launch, results, destroy in one)."""
+    return _run_descs("pso_batch_run", specs)
+
+
+def pso_batch_run_static(specs, stream=None):
+    """pso_batch_run_static: the same batch with every device buffer in the
+    library's fixed per-device scratch (no allocation); `stream` is a torch
+    stream or None for the device's null stream."""
+    sp = None if stream is None else ctypes.c_void_p(int(stream.cuda_stream))
+    return _run_descs("pso_batch_run_static", specs, sp)
+
+
 class Swarm:
     """One swarm on the GPU: owns its handle; parameters as in Table 1."""
 

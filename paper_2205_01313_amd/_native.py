@@ -71,6 +71,7 @@ SIGNATURES = {
     "pso_batch_results": (c_int, [c_vp, P(PsoResult)]),
     "pso_batch_destroy": (c_int, [c_vp]),
     "pso_batch_run": (c_int, [P(PsoDesc), c_i64, P(PsoResult)]),
+    "pso_batch_run_static": (c_int, [P(PsoDesc), c_i64, P(PsoResult), c_vp]),
     "pso64_create": (c_int, [c_int, c_i64, c_i32, P(c_f), c_f, c_f, c_f, c_f, c_u64, P(c_vp)]),
     "pso64_set_shift": (c_int, [c_vp, P(c_f)]),
     "pso64_reset": (c_int, [c_vp]),

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpso.so")
-SOURCES = ["pso_kernels.hip", "pso_block.hip", "pso_capi.hip", "pso_server.hip", "pso_f64.hip"]
+SOURCES = ["pso_kernels.hip", "pso_block.hip", "pso_capi.hip", "pso_server.hip", "pso_f64.hip", "pso_static.hip"]
 
 # IEEE binary32 throughout: no contraction of a*b+c into fma (the fitness
 # functions use explicit fmaf), denormals kept, correctly rounded divide and
