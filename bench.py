@@ -168,10 +168,13 @@ def copy_ceiling(torch, stream, nbytes=1 << 30, reps=5):
 
 
 def async_leg(pso, torch, wl, spec, ws, stream, seeds=32):
-    """Asynchronous variant on the same swarm: updates/s over one solve; and
+    """Asynchronous variant on the same swarm: updates/s over one solve and
+    its tiles (how many used a gbest published during the same iteration);
     the final-fitness distribution over 32 seeds of the synchronous,
-    asynchronous and persistent variants (quantiles 0, 10, 50, 90, 100)."""
+    asynchronous and persistent variants (quantiles 0, 10, 50, 90, 100) and
+    two-sample KS statistics against the synchronous one."""
     import numpy as np
+    import scipy.stats
     sw = pso.Swarm(spec.fitness, spec.N, spec.D, spec.box, spec.w, spec.c1, spec.c2, spec.vmax, spec.seed,
                    variant=pso.PSO_ASYNC, workspace=ws, stream=stream)
 
@@ -182,8 +185,9 @@ def async_leg(pso, torch, wl, spec, ws, stream, seeds=32):
     solve()
     ms = timed_events(torch, stream, solve)
     best = sw.best()
+    tiles = sw.async_counters()
     sw.close()
-    dist = {}
+    finals, fresh = {}, []
     for name, var in (("sync", pso.PSO_SYNC), ("async", pso.PSO_ASYNC), ("persistent", pso.PSO_PERSISTENT)):
         fs = []
         for seed in range(seeds):
@@ -191,9 +195,21 @@ def async_leg(pso, torch, wl, spec, ws, stream, seeds=32):
             with pso.Swarm(sp.fitness, sp.N, sp.D, sp.box, sp.w, sp.c1, sp.c2, sp.vmax, sp.seed, variant=var,
                            workspace=ws, stream=stream) as g:
                 fs.append(float(g.run(sp.T)["gbest_fit"]))
-        dist[name] = [float(q) for q in np.percentile(fs, [0, 10, 50, 90, 100])]
+                if var == pso.PSO_ASYNC:
+                    fresh.append(g.async_counters()["fresh_tiles"])
+        finals[name] = np.array(fs)
+    dist = {k: [float(q) for q in np.percentile(v, [0, 10, 50, 90, 100])] for k, v in finals.items()}
+    ks = {}
+    for k in ("async", "persistent"):
+        r = scipy.stats.ks_2samp(finals["sync"], finals[k])
+        ks[k] = dict(statistic=float(r.statistic), pvalue=float(r.pvalue))
     return dict(value=spec.N * spec.D * spec.T / (ms / 1e3), unit="particle·dim updates/s", ms_per_solve=ms,
-                gbest=float(best["gbest_fit"]), final_fitness_quantiles_32_seeds=dist)
+                gbest=float(best["gbest_fit"]),
+                tiles_per_workgroup=os.environ.get("PSO_ASYNC_TILES", "library default"),
+                tiles=tiles["tiles"], fresh_tiles=tiles["fresh_tiles"],
+                seeds_differing_from_sync=int(np.sum(finals["sync"] != finals["async"])),
+                fresh_tiles_per_seed_min=int(min(fresh)),
+                final_fitness_quantiles_32_seeds=dist, ks_vs_sync=ks)
 
 
 def small_leg(pso, torch, wl, stream):

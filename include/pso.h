@@ -169,6 +169,15 @@ int pso_set_state(pso_swarm *s, const float *x_host, const float *v_host, const 
  * since the last Step 1 -- the measured improvement rate of the run. */
 int pso_get_counters(pso_swarm *s, uint64_t *pbest_improvements);
 
+/* PSO_ASYNC (the lock-protected gbest of Sec. 3.2, Alg. 3): synchronises and
+ * reads, since the last Step 1, the number of tiles of particles the
+ * asynchronous step ran (a workgroup runs its tiles one after another and
+ * reads the running gbest before each), and how many of them used a gbest
+ * published during the same iteration -- newer than the gbest at the end of
+ * the previous iteration, which the synchronous variant would use.  Both
+ * stay 0 under the other variants.  Either pointer may be NULL. */
+int pso_get_async_counters(pso_swarm *s, uint64_t *tiles, uint64_t *fresh_tiles);
+
 /* Blocks until the swarm's enqueued work is done; reports device errors. */
 int pso_sync(pso_swarm *s);
 
@@ -217,7 +226,6 @@ int pso64_run(pso_swarm64 *s, int64_t max_iter, double tol, double f_star, doubl
 int pso64_get_state(pso_swarm64 *s, double *x, double *v, double *p, double *pf, int64_t *gbest_index,
                     int64_t *t);
 
-/* Frees the swarm.  NULL -> EINVAL. */
 /* The swarm's fitness function, with its shift, in binary64 at M points
  * (host, row-major M x D doubles) -> values (host, M doubles): the same
  * operation sequence as the binary64 swarm evaluates (Eq. 3 and the test
@@ -226,6 +234,7 @@ int pso64_get_state(pso_swarm64 *s, double *x, double *v, double *p, double *pf,
  * M < 0 or NULL pointers (with M > 0) -> EINVAL. */
 int pso64_eval(pso_swarm64 *s, const double *points, int64_t M, double *values);
 
+/* Frees the swarm.  NULL -> EINVAL. */
 int pso64_destroy(pso_swarm64 *s);
 
 /* ------------------------------------------------------------------------ */

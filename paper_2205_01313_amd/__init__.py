@@ -139,6 +139,12 @@ def pso_get_counters(h):
     return dict(pbest_improvements=n.value)
 
 
+def pso_get_async_counters(h):
+    n, f = ctypes.c_uint64(), ctypes.c_uint64()
+    _check(lib().pso_get_async_counters(h, ctypes.byref(n), ctypes.byref(f)), "pso_get_async_counters")
+    return dict(tiles=n.value, fresh_tiles=f.value)
+
+
 def pso_sync(h):
     return _check(lib().pso_sync(h), "pso_sync")
 
@@ -443,6 +449,9 @@ class Swarm:
 
     def counters(self):
         return pso_get_counters(self.h)
+
+    def async_counters(self):
+        return pso_get_async_counters(self.h)
 
     def close(self):
         if getattr(self, "h", None):

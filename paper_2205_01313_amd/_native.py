@@ -64,6 +64,7 @@ SIGNATURES = {
     "pso_get_state": (c_int, [c_vp, P(c_f), P(c_f), P(c_f), P(c_f), P(c_u64), P(c_f), P(c_i64), P(c_i64)]),
     "pso_set_state": (c_int, [c_vp, P(c_f), P(c_f), P(c_f), P(c_f), c_u64, P(c_f), c_i64, c_i64]),
     "pso_get_counters": (c_int, [c_vp, P(c_u64)]),
+    "pso_get_async_counters": (c_int, [c_vp, P(c_u64), P(c_u64)]),
     "pso_sync": (c_int, [c_vp]),
     "pso_destroy": (c_int, [c_vp]),
     "pso_batch_create": (c_int, [P(PsoDesc), c_i64, c_vp, P(c_vp)]),

@@ -308,15 +308,17 @@ void drop_steps_graph(pso_swarm *s)
     s->steps_key = -1;
 }
 
-// What a captured step launch depends on besides the swarm: its variant and
-// the step path chosen from the environment (PSO_STEP_SPLIT, PSO_STEP_ONE).
+// What a captured step launch depends on besides the swarm: its variant, the
+// step path chosen from the environment (PSO_STEP_SPLIT, PSO_STEP_ONE) and
+// the asynchronous step's tiles per workgroup.
 int steps_key_of(const pso_swarm *s)
 {
     auto mode = [](const char *name) {
         const char *e = getenv(name);
         return e ? (atoi(e) == 0 ? 1 : 2) : 0;
     };
-    return s->variant * 9 + mode("PSO_STEP_SPLIT") * 3 + mode("PSO_STEP_ONE");
+    return ((s->variant * 3 + mode("PSO_STEP_SPLIT")) * 3 + mode("PSO_STEP_ONE")) * 65 +
+           (int)pso::async_tiles_per_workgroup();
 }
 
 // Enqueues n step launches: replays of the captured graph of RUN_GRAPH_STEPS
@@ -548,6 +550,18 @@ int pso_get_counters(pso_swarm *s, uint64_t *pbest_improvements)
         int rc = fetch_ctrl(s, false);
         if (rc) return rc;
         if (pbest_improvements) *pbest_improvements = s->host_ctrl->improved;
+        return PSO_OK;
+    });
+}
+
+int pso_get_async_counters(pso_swarm *s, uint64_t *tiles, uint64_t *fresh_tiles)
+{
+    return pso::guarded([&]() -> int {
+        if (!s) return fail(PSO_EINVAL, "swarm is NULL");
+        int rc = fetch_ctrl(s, false);
+        if (rc) return rc;
+        if (tiles) *tiles = s->host_ctrl->tiles;
+        if (fresh_tiles) *fresh_tiles = s->host_ctrl->fresh;
         return PSO_OK;
     });
 }

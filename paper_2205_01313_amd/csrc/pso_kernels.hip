@@ -45,6 +45,9 @@
 #ifndef PSO_BLOCK
 #define PSO_BLOCK 256
 #endif
+#ifndef PSO_ASYNC_PF
+#define PSO_ASYNC_PF 0 // software prefetch of the next dimension pair in the asynchronous step
+#endif
 #ifndef PSO_STEP_ONE_K
 #define PSO_STEP_ONE_K 8 // dimension pairs loaded ahead by the one-particle-per-lane step
 #endif
@@ -134,17 +137,16 @@ SwarmArgs bind(void *base, const Layout &L, uint64_t N, int D)
 }
 
 
-// Iteration epilogue, run by the last workgroup: history, counters and the
-// stop rule for iteration t; in the synchronous variant also the gbest
-// position.  A changed gbest belongs to a particle whose pbest improved in
-// this iteration, so its pbest position is its current position x.
-template <int VAR>
+// Iteration epilogue, run by the last workgroup: history, counters, the stop
+// rule and the gbest position for iteration t.  A changed gbest belongs to a
+// particle whose pbest improved in this iteration, so its pbest position is
+// its current position x.
 __device__ void epilogue(const SwarmArgs &a, uint32_t t, bool first)
 {
     Ctrl *c = a.ctrl;
     const unsigned long long k = __hip_atomic_load(&c->gkey, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const bool changed = first || k != c->gkey_prev;
-    if (VAR == VAR_SYNC && changed) {
+    if (changed) {
         const size_t gi = (uint32_t)k;
         for (int d = threadIdx.x; d < a.D; d += BLOCK) a.gpos[d] = a.x[(size_t)d * a.Np + gi];
     }
@@ -153,7 +155,7 @@ __device__ void epilogue(const SwarmArgs &a, uint32_t t, bool first)
         if (changed) {
             c->giter = t;
             c->gkey_prev = k;
-            if (VAR == VAR_SYNC) c->pubkey = k;
+            c->pubkey = k;
         }
         c->t = t;
         c->arrive = 0;
@@ -170,6 +172,8 @@ __global__ void k_reset(SwarmArgs a)
     Ctrl *c = a.ctrl;
     c->gkey = NO_KEY;
     c->improved = 0;
+    c->tiles = 0;
+    c->fresh = 0;
     c->arrive = 0;
     c->gkey_prev = NO_KEY;
     c->giter = 0;
@@ -214,19 +218,18 @@ __global__ void __launch_bounds__(BLOCK) k_init(SwarmArgs a)
     const unsigned long long key = (4 * q < a.Np) ? init_quad<FIT, POL>(a, D, q, s_shift) : NO_KEY;
     const unsigned long long m = workgroup_min(key, NO_KEY, &wg_min);
     publish_sync(a.ctrl, m, NO_KEY);
-    if (arrive_last(a.ctrl, &last)) epilogue<VAR_SYNC>(a, 0u, true);
+    if (arrive_last(a.ctrl, &last)) epilogue(a, 0u, true);
 }
 
 // ---------------------------------------------------------------------------
-// One iteration t = (iterations completed) + 1 over the whole grid.  The
-// gbest position and the shift vector are staged in LDS (each dimension's
-// value is one broadcast read).  DC > 0 fixes D at compile time.
+// One synchronous iteration t = (iterations completed) + 1 over the whole
+// grid.  The gbest position and the shift vector are staged in LDS (each
+// dimension's value is one broadcast read).  DC > 0 fixes D at compile time.
 // ---------------------------------------------------------------------------
-template <int FIT, int DC, int VAR, int POL>
+template <int FIT, int DC, int POL>
 __global__ void PSO_STEP_ATTR k_step(SwarmArgs a)
 {
     __shared__ unsigned long long wg_min;
-    __shared__ unsigned long long snap_key;
     __shared__ unsigned int wg_count;
     __shared__ int flag;
     extern __shared__ float s_dyn[]; // gbest position (D floats), then shift (D floats)
@@ -236,20 +239,15 @@ __global__ void PSO_STEP_ATTR k_step(SwarmArgs a)
     float *s_g = s_dyn, *s_shift = s_dyn + D;
     const uint32_t t = (uint32_t)(c->t + 1);
     for (int d = threadIdx.x; d < D; d += BLOCK) {
-        if (VAR == VAR_SYNC) s_g[d] = a.gpos[d];
+        s_g[d] = a.gpos[d];
         s_shift[d] = a.shift[d];
     }
     if (threadIdx.x == 0) {
         wg_min = NO_KEY;
         wg_count = 0;
     }
-    unsigned long long thr;
-    if (VAR == VAR_SYNC) {
-        thr = c->gkey_prev;
-        __syncthreads();
-    } else {
-        thr = snapshot_async(a, s_g, &snap_key); // ends with a barrier
-    }
+    const unsigned long long thr = c->gkey_prev;
+    __syncthreads();
     const uint32_t q = blockIdx.x * BLOCK + threadIdx.x;
     uint32_t n_imp = 0;
     const unsigned long long key =
@@ -257,13 +255,99 @@ __global__ void PSO_STEP_ATTR k_step(SwarmArgs a)
     count_improvements(c, n_imp, &wg_count);
     const unsigned long long m = workgroup_min(key, thr, &wg_min);
     flush_count(c, &wg_count);
-    if (VAR == VAR_SYNC) {
-        publish_sync(c, m, thr);
-    } else {
-        publish_async(a, m, thr, &flag);
-        __syncthreads();
+    publish_sync(c, m, thr);
+    if (arrive_last(c, &flag)) epilogue(a, t, false);
+}
+
+// ---------------------------------------------------------------------------
+// One asynchronous iteration (the lock-protected gbest of Sec. 3.2, Alg. 3):
+// a workgroup whose particles beat the gbest publishes the better gbest at
+// once, and work that starts later in the same iteration uses it.
+//
+// The swarm is cut into tiles of BLOCK particle quads and each workgroup runs
+// the tiles blockIdx.x, blockIdx.x + gridDim.x, ... one after another (with
+// as many workgroups as tiles, all co-resident, every tile would start before
+// any publish and the trajectory would be the synchronous one).  Every tile
+// after a workgroup's first starts by reading the running gbest key.  If it
+// is the key of the previous iteration's gbest, its position is gpos, as in
+// the synchronous step.  If it is lower, a tile of this iteration published
+// it, and the position is that particle's x: its pbest position, written
+// once in this iteration before the key was published (release fence, then
+// atomicMin) and not rewritten before the iteration ends.  So the packed
+// (fitness, index) key is the whole publication -- the index locates the
+// position, as in Sec. 4.3 -- and no lock is needed to keep key and position
+// consistent.  The last workgroup copies the final gbest position to gpos,
+// as the synchronous epilogue does.  Each tile is counted, and so is every
+// tile that used a gbest published during the same iteration.
+// ---------------------------------------------------------------------------
+template <int FIT, int DC, int POL>
+__global__ void PSO_STEP_ATTR k_step_async(SwarmArgs a, uint32_t tiles)
+{
+    __shared__ unsigned long long wg_min[2];
+    __shared__ unsigned long long s_key;
+    __shared__ unsigned int wg_count;
+    __shared__ int flag;
+    extern __shared__ float s_dyn[]; // gbest position (D floats), then shift (D floats)
+    Ctrl *c = a.ctrl;
+    if (c->stop) return;
+    const int D = DC > 0 ? DC : a.D;
+    float *s_g = s_dyn, *s_shift = s_dyn + D;
+    const uint32_t t = (uint32_t)(c->t + 1);
+    const unsigned long long start_key = c->gkey_prev; // the gbest after iteration t - 1; its position is gpos
+    for (int d = threadIdx.x; d < D; d += BLOCK) {
+        s_g[d] = a.gpos[d];
+        s_shift[d] = a.shift[d];
     }
-    if (arrive_last(c, &flag)) epilogue<VAR>(a, t, false);
+    if (threadIdx.x == 0) {
+        wg_min[0] = NO_KEY;
+        wg_min[1] = NO_KEY;
+        wg_count = 0;
+    }
+    __syncthreads();
+    unsigned long long thr = start_key; // the gbest whose position s_g holds
+    uint32_t n_imp = 0, n_tiles = 0, n_fresh = 0;
+    int slot = 0;
+    for (uint32_t tile = blockIdx.x; tile < tiles; tile += gridDim.x, slot ^= 1) {
+        // a workgroup's first tile uses the previous iteration's gbest, as
+        // the synchronous step does; each later one reads the running key
+        if (n_tiles > 0) {
+            if (threadIdx.x == 0) s_key = __hip_atomic_load(&c->gkey, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __syncthreads();
+            const unsigned long long k = s_key;
+            if (k < thr) {
+                // published during this iteration: the position is x of
+                // particle k & 0xffffffff (coherent loads; their address
+                // depends on the key)
+                const size_t gi = (uint32_t)k;
+                for (int d = threadIdx.x; d < D; d += BLOCK)
+                    s_g[d] =
+                        __hip_atomic_load(&a.x[(size_t)d * a.Np + gi], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                thr = k;
+                __syncthreads();
+            }
+        }
+        ++n_tiles;
+        n_fresh += thr < start_key;
+        const uint32_t q = tile * BLOCK + threadIdx.x;
+        uint32_t n = 0;
+        const unsigned long long key =
+            (4 * q < a.N)
+                ? iterate_quad<FIT, DC, PSO_STEP_UNROLL, POL, (PSO_ASYNC_PF != 0 || FIT == F_ACKLEY)>(a, D, q, t, s_g,
+                                                                                                     s_shift, &n)
+                : NO_KEY;
+        n_imp += n;
+        const unsigned long long m = workgroup_min(key, thr, &wg_min[slot]);
+        if (threadIdx.x == 0) wg_min[slot ^ 1] = NO_KEY;
+        publish_sync(c, m, thr);
+    }
+    count_improvements(c, n_imp, &wg_count);
+    __syncthreads();
+    flush_count(c, &wg_count);
+    if (threadIdx.x == 0 && n_tiles) {
+        atomicAdd(&c->tiles, (unsigned long long)n_tiles);
+        if (n_fresh) atomicAdd(&c->fresh, (unsigned long long)n_fresh);
+    }
+    if (arrive_last(c, &flag)) epilogue(a, t, false);
 }
 
 // ---------------------------------------------------------------------------
@@ -300,7 +384,7 @@ __global__ void PSO_STEP_ATTR k_step_one(SwarmArgs a)
     const unsigned long long m = workgroup_min(key, thr, &wg_min);
     flush_count(c, &wg_count);
     publish_sync(c, m, thr);
-    if (arrive_last(c, &flag)) epilogue<VAR_SYNC>(a, t, false);
+    if (arrive_last(c, &flag)) epilogue(a, t, false);
 }
 
 // ---------------------------------------------------------------------------
@@ -423,7 +507,7 @@ __global__ void PSO_STEP_ATTR k_step_split(SwarmArgs a, uint32_t L, uint32_t C)
     const unsigned long long m = workgroup_min(key, thr, &wg_min);
     flush_count(c, &wg_count);
     publish_sync(c, m, thr);
-    if (arrive_last(c, &flag)) epilogue<VAR_SYNC>(a, t, false);
+    if (arrive_last(c, &flag)) epilogue(a, t, false);
 }
 
 // ---------------------------------------------------------------------------
@@ -635,7 +719,7 @@ __global__ void __launch_bounds__(BLOCK) k_reduce_final(SwarmArgs a, uint32_t nb
     const unsigned long long m = tree_min<UNROLLED>(key, sh);
     if (threadIdx.x == 0) c->gkey = m;
     __syncthreads();
-    epilogue<VAR_SYNC>(a, t, false);
+    epilogue(a, t, false);
 }
 
 // ---------------------------------------------------------------------------
@@ -769,23 +853,52 @@ static void launch_one(const SwarmArgs &a, hipStream_t stream)
     }
 }
 
+// Tiles per workgroup of the asynchronous step: PSO_ASYNC_TILES in the
+// environment (1..64), else PSO_ASYNC_TILES_DEFAULT.
+#ifndef PSO_ASYNC_TILES_DEFAULT
+#define PSO_ASYNC_TILES_DEFAULT 2
+#endif
+uint32_t async_tiles_per_workgroup()
+{
+    const char *env = getenv("PSO_ASYNC_TILES");
+    const int v = env ? atoi(env) : 0;
+    return (v >= 1 && v <= 64) ? (uint32_t)v : (uint32_t)PSO_ASYNC_TILES_DEFAULT;
+}
+
+template <int FIT, int POL>
+static void launch_async(const SwarmArgs &a, hipStream_t stream)
+{
+    const size_t lds = 2 * sizeof(float) * a.D;
+    const uint32_t tiles = grid_of(a).x, per = async_tiles_per_workgroup();
+    const dim3 grid((tiles + per - 1) / per);
+    switch (PSO_STEP_EXACT_D ? a.D : 0) {
+    case 32: hipLaunchKernelGGL((k_step_async<FIT, 32, POL>), grid, dim3(BLOCK), lds, stream, a, tiles); break;
+    case 128: hipLaunchKernelGGL((k_step_async<FIT, 128, POL>), grid, dim3(BLOCK), lds, stream, a, tiles); break;
+    default: hipLaunchKernelGGL((k_step_async<FIT, 0, POL>), grid, dim3(BLOCK), lds, stream, a, tiles); break;
+    }
+}
+
 template <int FIT, int VAR, int POL>
 static void launch_step_fvp(const SwarmArgs &a, hipStream_t stream)
 {
     uint32_t L = 0, C = 0;
-    if (VAR == VAR_SYNC && one_shape(a)) {
+    if (VAR == VAR_ASYNC) {
+        launch_async<FIT, POL>(a, stream);
+        return;
+    }
+    if (one_shape(a)) {
         launch_one<FIT, POL>(a, stream);
         return;
     }
-    if (VAR == VAR_SYNC && split_shape(a, Fitness<FIT>::STAGE_WORDS, &L, &C)) {
+    if (split_shape(a, Fitness<FIT>::STAGE_WORDS, &L, &C)) {
         launch_split<FIT, POL>(a, L, C, stream);
         return;
     }
     const size_t lds = 2 * sizeof(float) * a.D;
     switch (PSO_STEP_EXACT_D ? a.D : 0) {
-    case 32: hipLaunchKernelGGL((k_step<FIT, 32, VAR, POL>), grid_of(a), dim3(BLOCK), lds, stream, a); break;
-    case 128: hipLaunchKernelGGL((k_step<FIT, 128, VAR, POL>), grid_of(a), dim3(BLOCK), lds, stream, a); break;
-    default: hipLaunchKernelGGL((k_step<FIT, 0, VAR, POL>), grid_of(a), dim3(BLOCK), lds, stream, a); break;
+    case 32: hipLaunchKernelGGL((k_step<FIT, 32, POL>), grid_of(a), dim3(BLOCK), lds, stream, a); break;
+    case 128: hipLaunchKernelGGL((k_step<FIT, 128, POL>), grid_of(a), dim3(BLOCK), lds, stream, a); break;
+    default: hipLaunchKernelGGL((k_step<FIT, 0, POL>), grid_of(a), dim3(BLOCK), lds, stream, a); break;
     }
 }
 

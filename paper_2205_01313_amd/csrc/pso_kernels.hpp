@@ -16,7 +16,10 @@ struct alignas(256) Ctrl {
     // line 0: running minimum key of the current iteration (atomicMin target)
     unsigned long long gkey;
     unsigned long long improved; // pbest improvements since Step 1 (one add per workgroup)
-    unsigned char pad0[240];
+    // asynchronous step: tiles run since Step 1, and those that used a gbest
+    // published during the same iteration
+    unsigned long long tiles, fresh;
+    unsigned char pad0[224];
     // line 1: workgroups that finished the current launch
     unsigned int arrive;
     unsigned char pad1[252];
@@ -99,6 +102,9 @@ SwarmArgs bind(void *base, const Layout &L, uint64_t N, int D);
 hipError_t launch_reset(const SwarmArgs &a, hipStream_t stream);
 hipError_t launch_init(int fitness, const SwarmArgs &a, hipStream_t stream);
 hipError_t launch_step(int fitness, int variant, const SwarmArgs &a, hipStream_t stream);
+// Tiles each workgroup of the asynchronous step runs one after another
+// (PSO_ASYNC_TILES in the environment, 1..64; default 2).
+uint32_t async_tiles_per_workgroup();
 hipError_t launch_arm(const SwarmArgs &a, float tol, float fstar, hipStream_t stream);
 // Copies every pending pbest position from x to p (before the state is read).
 hipError_t launch_flush(const SwarmArgs &a, hipStream_t stream);

@@ -67,22 +67,51 @@ def test_async_stop_rule():
     assert r["gbest_fit"] < 1e-3 and r["iters"] < 400
 
 
+def test_full_size_uses_gbests_of_the_same_iteration():
+    """Rastrigin D=32, N=2^20 (the large workload), 20 iterations: tiles of
+    the asynchronous step use gbests that other tiles published during the
+    same iteration (counted on the device), every invariant holds, and the
+    trajectory leaves the synchronous one."""
+    spec = wl.large_rastrigin(seed=3)
+    announce("async full size: N=2^20, D=32, 20 iterations")
+    with gpu_swarm(spec, variant=pso.PSO_ASYNC) as g:
+        g.run(20)
+        cnt = g.async_counters()
+        st = g.state()
+        ha = g.history(0, 21)
+    print(f"\ntiles {cnt['tiles']}, of them on a gbest of the same iteration {cnt['fresh_tiles']}")
+    assert cnt["fresh_tiles"] > 0 and cnt["tiles"] >= cnt["fresh_tiles"]
+    check_invariants(spec, st, None, None)
+    with gpu_swarm(spec, variant=pso.PSO_SYNC) as g:
+        g.run(20)
+        assert g.async_counters() == dict(tiles=0, fresh_tiles=0)
+        hs = g.history(0, 21)
+    assert hs[0] == ha[0]  # same Step 1
+    assert not np.array_equal(hs, ha)
+
+
 def test_final_fitness_distribution_32_seeds():
-    """Rastrigin D=32, N=2^20, 200 iterations, seeds 0..31: the asynchronous
-    variant reaches the same quality as the synchronous one (medians within a
-    factor of 1.5 either way); the quantiles and a two-sample KS statistic are
-    printed for the record."""
+    """Rastrigin D=32, N=2^20, 200 iterations, seeds 0..31: every asynchronous
+    run uses gbests published during the same iteration and at least one
+    ends elsewhere than its synchronous twin, and the asynchronous variant
+    reaches the same quality (medians within a factor of 1.5 either way); the
+    quantiles and a two-sample KS statistic are printed for the record."""
     import scipy.stats
     fs = {pso.PSO_SYNC: [], pso.PSO_ASYNC: []}
+    fresh = []
     for variant in fs:
         for seed in range(32):
             spec = wl.large_rastrigin(seed=seed)
             with gpu_swarm(spec, variant=variant) as g:
                 fs[variant].append(float(g.run(spec.T)["gbest_fit"]))
+                if variant == pso.PSO_ASYNC:
+                    fresh.append(g.async_counters()["fresh_tiles"])
     s, a = np.array(fs[pso.PSO_SYNC]), np.array(fs[pso.PSO_ASYNC])
     ks = scipy.stats.ks_2samp(s, a)
     print(f"\nsync  quantiles (0,25,50,75,100): {np.percentile(s, [0, 25, 50, 75, 100])}")
     print(f"async quantiles (0,25,50,75,100): {np.percentile(a, [0, 25, 50, 75, 100])}")
-    print(f"KS statistic {ks.statistic:.3f}, p = {ks.pvalue:.3g}")
+    print(f"KS statistic {ks.statistic:.3f}, p = {ks.pvalue:.3g}; fresh tiles per run {min(fresh)}..{max(fresh)}")
     assert np.all(np.isfinite(s)) and np.all(np.isfinite(a))
+    assert min(fresh) > 0
+    assert np.any(s != a)
     assert np.median(a) <= 1.5 * np.median(s) and np.median(s) <= 1.5 * np.median(a)
