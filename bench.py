@@ -333,14 +333,14 @@ def paper_leg(pso):
     return dict(precision="f64", fitness="cubic", rows=rows)
 
 
-def batched_leg(pso, torch, wl, stream, subset=96):
+def batched_leg(pso, torch, wl, stream):
     """4096 swarms (N log-uniform in [32, 8192], D in {2..64}, four fitness
     functions with shifts, 500 iterations) in one persistent launch, its
     shape (lanes, workgroups, part size, LDS staging) picked by the
-    autotuner, and the streamed kernel's time on the same batch; and a
-    spread subset run as a batch, as the plain loop (one swarm after
-    another, one launch per iteration) and as a loop of pso_run calls
-    (allocation outside the timed loops; all three give the same results)."""
+    autotuner, and the streamed kernel's time on the same batch; then every
+    swarm of the batch run alone, as the plain loop (one swarm after another,
+    one launch per iteration) and as a loop of pso_run calls (each swarm's
+    creation outside the timed regions; all three give the same results)."""
     specs = wl.batch_specs()
     with pso.Batch(specs, stream=stream) as b:
         default_shape = b.shape
@@ -350,7 +350,7 @@ def batched_leg(pso, torch, wl, stream, subset=96):
         b.launch()
         torch.cuda.synchronize()
         ms = timed_events(torch, stream, b.launch)
-        res = b.results(positions=False)
+        res = b.results()
         # the streamed kernel on the same batch, for comparison
         b.set_shape(128, 0, 1 << 17)
         b.launch()
@@ -360,42 +360,58 @@ def batched_leg(pso, torch, wl, stream, subset=96):
     same_streamed = all(a["gbest_fit"] == c["gbest_fit"] and a["iters"] == c["iters"]
                         for a, c in zip(res, res_streamed))
     updates = sum(sp.N * sp.D * r["iters"] for sp, r in zip(specs, res))
-    sub = specs[:: len(specs) // subset][:subset]
-    with pso.Batch(sub, stream=stream) as b:
-        b.launch()
-        torch.cuda.synchronize()
-        ms_sub = timed_events(torch, stream, b.launch)
-        rb = b.results()
-    swarms = [pso.Swarm(sp.fitness, sp.N, sp.D, sp.box, sp.w, sp.c1, sp.c2, sp.vmax, sp.seed, shift=sp.shift)
-              for sp in sub]
-    # the plain loop: one swarm after another, one launch per iteration
-    for sw in swarms:
-        sw.reset()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for sw, sp in zip(swarms, sub):
-        sw.step(sp.T)
-        sw.sync()
-    ms_plain = (time.perf_counter() - t0) * 1e3
-    rs = [sw.best() for sw in swarms]
-    # and one pso_run per swarm (one staged workgroup for the small swarms)
-    for sw in swarms:
-        sw.reset()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    rp = [sw.run(sp.T) for sw, sp in zip(swarms, sub)]
-    ms_run = (time.perf_counter() - t0) * 1e3
-    for sw in swarms:
-        sw.close()
-    same = all(a["gbest_fit"] == c["gbest_fit"] == d["gbest_fit"] and (a["gbest_pos"] == c["gbest_pos"]).all()
-               and (a["gbest_pos"] == d["gbest_pos"]).all() for a, c, d in zip(rb, rp, rs))
+    # every swarm alone, in one reused workspace on the same stream
+    ws = torch.empty(max(pso.pso_workspace_bytes(sp.N, sp.D) for sp in specs), dtype=torch.uint8, device="cuda")
+    s_plain = s_run = 0.0
+    same = True
+    for sp, r in zip(specs, res):
+        with pso.Swarm(sp.fitness, sp.N, sp.D, sp.box, sp.w, sp.c1, sp.c2, sp.vmax, sp.seed, shift=sp.shift,
+                       workspace=ws, stream=stream) as sw:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sw.step(sp.T)
+            sw.sync()
+            s_plain += time.perf_counter() - t0
+            a = sw.best()
+            sw.reset()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            c = sw.run(sp.T)
+            s_run += time.perf_counter() - t0
+        same = same and a["gbest_fit"] == c["gbest_fit"] == r["gbest_fit"] and \
+            (a["gbest_pos"] == r["gbest_pos"]).all() and (c["gbest_pos"] == r["gbest_pos"]).all()
     return dict(swarms=len(specs), iterations=500, ms=ms, value=updates / (ms / 1e3), unit="particle·dim updates/s",
                 autotuned_shape=shape, autotune_s=tune_s, default_shape=default_shape,
                 streamed_ms=ms_streamed, streamed_shape=dict(lanes=128, grid=0, part_work=1 << 17, stage_kib=0),
                 streamed_equal_results=bool(same_streamed),
-                subset=len(sub), subset_batched_ms=ms_sub, subset_plain_loop_ms=ms_plain,
-                batched_vs_plain_speedup=ms_plain / ms_sub, subset_pso_run_loop_ms=ms_run,
-                batched_vs_pso_run_loop_speedup=ms_run / ms_sub, equal_results=bool(same))
+                plain_loop_ms=s_plain * 1e3, batched_vs_plain_speedup=s_plain * 1e3 / ms,
+                pso_run_loop_ms=s_run * 1e3, batched_vs_pso_run_loop_speedup=s_run * 1e3 / ms,
+                equal_results=bool(same))
+
+
+def f64_leg(pso, wl, reps=3):
+    """The large Rastrigin workload (D=32, N=2^20, 200 iterations) through the
+    binary64 path, the paper's precision: updates/s and the share of the HBM
+    roofline on its algorithmic bytes, at least 40 per update (read x, v, p;
+    write x, v, 8 bytes each) plus the pbest fitness read once per particle
+    -- a lower bound, since the pbest writes (8 bytes per improved
+    element) are not counted."""
+    spec = wl.large_rastrigin(seed=0)
+    with pso.Swarm64(spec.fitness, spec.N, spec.D, spec.box, spec.w, spec.c1, spec.c2, spec.vmax, spec.seed) as g:
+        g.run(spec.T)
+        secs = []
+        for _ in range(reps):
+            g.reset()
+            t0 = time.perf_counter()
+            r = g.run(spec.T)
+            secs.append(time.perf_counter() - t0)
+    s = sorted(secs)[reps // 2]
+    us = s * 1e6 / spec.T
+    alg = spec.N * spec.D * 40.0 + spec.N * 8.0
+    return dict(workload="Rastrigin D=32, N=2^20, 200 iterations, binary64", s_per_solve=s,
+                us_per_iteration=us, value=spec.N * spec.D * spec.T / s, unit="particle·dim updates/s",
+                alg_bytes_per_iteration_lower_bound=alg, hbm_frac_lower_bound=alg / (us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+                gbest=float(r["gbest_fit"]))
 
 
 def serving_leg(pso, wl, rates=(2000, 10000, 50000), count=20000, budget=32 << 30, chunk=0):
@@ -460,9 +476,9 @@ def main():
     ap.add_argument("--variant", choices=["sync", "async"], default="sync")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=200)
-    ap.add_argument("--legs", default="main,async,small,deep,latency,paper,batched,serving",
-                    help="comma list of legs beyond the main line: async, small, deep, latency, paper, batched, "
-                         "serving")
+    ap.add_argument("--legs", default="main,async,small,deep,f64,latency,paper,batched,serving",
+                    help="comma list of legs beyond the main line: async, small, deep, f64, latency, paper, "
+                         "batched, serving")
     ap.add_argument("--pmc-probe", nargs="?", const="step",
                     choices=["step", "batch", "deep_rosenbrock", "deep_ackley"],
                     help="for rocprofv3 counter runs: 'step' (default) = init + 20 step launches, then a 256 MiB "
@@ -634,6 +650,8 @@ def main():
         out["small"] = small_leg(pso, torch, wl, stream)
     if "deep" in legs:
         out["deep"] = deep_leg(pso, torch, wl, stream)
+    if "f64" in legs:
+        out["f64"] = f64_leg(pso, wl)
     if "latency" in legs:
         out["latency"] = latency_leg(pso)
     if "paper" in legs:
