@@ -309,15 +309,17 @@ void drop_steps_graph(pso_swarm *s)
 }
 
 // What a captured step launch depends on besides the swarm: its variant, the
-// step path chosen from the environment (PSO_STEP_SPLIT, PSO_STEP_ONE) and
-// the asynchronous step's tiles per workgroup.
+// step path chosen from the environment (PSO_STEP_SPLIT, PSO_STEP_ONE,
+// PSO_SPLIT_PHASES) and the asynchronous step's tiles per workgroup.
 int steps_key_of(const pso_swarm *s)
 {
     auto mode = [](const char *name) {
         const char *e = getenv(name);
         return e ? (atoi(e) == 0 ? 1 : 2) : 0;
     };
-    return ((s->variant * 3 + mode("PSO_STEP_SPLIT")) * 3 + mode("PSO_STEP_ONE")) * 65 +
+    const char *ph = getenv("PSO_SPLIT_PHASES");
+    const int phases = ph ? std::min(std::max(atoi(ph), 0), 2) : 0;
+    return (((s->variant * 3 + mode("PSO_STEP_SPLIT")) * 3 + mode("PSO_STEP_ONE")) * 3 + phases) * 65 +
            (int)pso::async_tiles_per_workgroup();
 }
 

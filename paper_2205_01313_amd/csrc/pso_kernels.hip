@@ -388,6 +388,48 @@ __global__ void PSO_STEP_ATTR k_step_one(SwarmArgs a)
 }
 
 // ---------------------------------------------------------------------------
+// Staged fitness terms of the split step.  The fitness is a sequential sum
+// over the dimensions (Fitness<FIT>::add), so it cannot be split across
+// lanes; what can be is the work of each term.  Every term that does not
+// depend on another dimension is computed by the lane that updates that
+// dimension, and the folding lane only adds: Sphere z^2, Rastrigin and
+// Cubic their term, Ackley z^2 and cos(2 pi z) (two independent sums).
+// Rosenbrock's term of dimension d > 0 needs z_{d-1} as well; z itself is
+// staged and the folding lane evaluates the terms (add()).  (Computing them
+// in the updating lanes, with each chunk's last z in a boundary row for the
+// next chunk's first term, was measured slower: 39.0 against 34.6 us per
+// iteration at N = 65 536, D = 128.)  Each term is the same expression add()
+// evaluates, so every sum is the same bits.
+// ---------------------------------------------------------------------------
+template <int FIT>
+__device__ __forceinline__ float split_term(float z)
+{
+    if constexpr (FIT == F_SPHERE) return z * z;
+    else if constexpr (FIT == F_RASTRIGIN) return z * z - 10.0f * cospi_f32(2.0f * z);
+    else if constexpr (FIT == F_ACKLEY) return z * z;
+    else if constexpr (FIT == F_CUBIC) {
+        const float z2 = z * z;
+        return ((z2 * z - 0.8f * z2) - 1000.0f * z) + 8000.0f;
+    } else return z;
+}
+
+// acc + t[0] + t[pitch] + ... + t[(n - 1) * pitch], in that order, eight
+// loads in flight.
+__device__ __forceinline__ float fold_column(float acc, const float *t, uint32_t pitch, int n)
+{
+    int j = 0;
+    for (; j + 8 <= n; j += 8) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = t[(uint32_t)(j + u) * pitch];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc = acc + v[u];
+    }
+    for (; j < n; ++j) acc = acc + t[(uint32_t)j * pitch];
+    return acc;
+}
+
+// ---------------------------------------------------------------------------
 // Split step, for swarms too small to fill the GPU at four particles per
 // lane (at N = 65 536 the plain step has a quarter of a wavefront per SIMD).
 // L lanes share a particle quad and each walks C consecutive dimensions of
@@ -396,25 +438,77 @@ __global__ void PSO_STEP_ATTR k_step_one(SwarmArgs a)
 // workgroup): the lanes of one chunk are consecutive, so a wavefront moves
 // 256-byte row segments, and a 64-byte pbest group is four lanes of one
 // chunk, as in the plain step.  Each lane stages its dimensions' fitness
-// terms in LDS ([word][d][particle], one 16-byte store per quad); after a
-// barrier one lane per particle folds them in dimension order, so the
-// fitness is the same sequential sum as in the plain step, bit for bit.
+// terms in LDS ([word][d][particle], one 16-byte store per quad, split_term
+// above); after a barrier the folding lanes add them in dimension order, so
+// the fitness is the same sequential sum as in the plain step, bit for bit.
+// With H = 2 phases the dimensions are covered in two halves of L * C: each
+// lane walks one chunk of each half, the terms of one half are staged at a
+// time, and the folding lane carries its particle's running sum from the
+// first half to the second -- the same additions in the same order, in half
+// the LDS per particle.
+//
+// Every workgroup of the launch is resident at once, so the iteration ends
+// when the workgroup whose loads were served last has folded, tested and
+// published its particles: the work after the loads is on the critical path.
+// So the folds are additions only (above), Ackley's two sums are folded by
+// two lanes at once, the folding lanes are spread over the wavefronts, each
+// folding lane reads its particle's pbest fitness before the update, and the
+// first dimension pair's loads are issued before the barrier that publishes
+// the gbest position and shift in LDS.
 // ---------------------------------------------------------------------------
-template <int FIT, int POL>
-__global__ void PSO_STEP_ATTR k_step_split(SwarmArgs a, uint32_t L, uint32_t C)
+// At most 128 VGPRs (four wavefronts per SIMD): 1024 workgroups of 256 lanes,
+// N = 65 536 at D = 128, are then resident at once.
+template <int FIT, int POL, uint32_t H>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
+k_step_split(SwarmArgs a, uint32_t L, uint32_t C)
 {
     __shared__ unsigned long long wg_min;
     __shared__ unsigned int wg_count;
     __shared__ int flag;
-    extern __shared__ float s_dyn[]; // gbest position (D), shift (D), staged terms
+    extern __shared__ float s_dyn[]; // gbest position (D), shift (D), staged terms of one phase
     Ctrl *c = a.ctrl;
     if (c->stop) return;
     constexpr int W = Fitness<FIT>::STAGE_WORDS;
     constexpr bool KX = (POL & KEEP_X) != 0, KV = (POL & KEEP_V) != 0, KP = (POL & KEEP_P) != 0;
+    constexpr uint32_t WAVES = BLOCK / 64;
     const int D = a.D;
+    const size_t Np = a.Np;
     const uint32_t Q = BLOCK / L, P = 4 * Q;
-    float *s_g = s_dyn, *s_shift = s_dyn + D, *s_t0 = s_dyn + 2 * D, *s_t1 = s_t0 + (size_t)D * P;
+    const int DP = H > 1 ? (int)(L * C) : D; // dimensions per phase
+    float *s_g = s_dyn, *s_shift = s_dyn + D, *s_t0 = s_dyn + 2 * D, *s_t1 = s_t0 + (size_t)DP * P;
     const uint32_t t = (uint32_t)(c->t + 1);
+    const uint32_t k = threadIdx.x / Q, qq = threadIdx.x % Q;
+    const uint32_t q = blockIdx.x * Q + qq, i0 = 4 * q;
+    const bool active = i0 < a.N;
+    // Folding lanes.  With P <= BLOCK, particle slot j < P / WAVES of
+    // wavefront w is particle w * P / WAVES + j; Ackley's second sum is
+    // folded by lane j + 32 of the same wavefront where the slots fit in 32
+    // lanes.  With P > BLOCK (one phase only) lane t folds particles t,
+    // t + BLOCK, ... after the update.
+    const bool spread = P <= BLOCK;
+    const uint32_t per_wave = P / WAVES, lane = threadIdx.x & 63;
+    const bool two = W == 2 && per_wave <= 32;
+    const uint32_t slot = two ? (lane & 31u) : lane, word = two ? (lane >> 5) : 0u;
+    const uint32_t fs = (threadIdx.x / 64) * per_wave + slot;
+    const bool folder = spread && slot < per_wave && blockIdx.x * P + fs < a.N;
+    const bool owner = folder && word == 0; // tests and writes the particle
+    const float pf_old = owner ? a.pf[blockIdx.x * P + fs] : 0.0f;
+    const uint32_t pend = active ? *reinterpret_cast<const uint32_t *>(a.pend + i0) : 0u;
+    // the first dimension pair of the lane's first chunk, loaded before the
+    // barrier below
+    f4 ax[2], av[2], ap[2];
+    {
+        const int d_begin = (int)(k * C), d_end = min(D, (int)((k + 1) * C));
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (active && d_begin + h < d_end) {
+                const size_t row = (size_t)(d_begin + h) * Np;
+                ax[h] = ld_state<KX>(a.x + row, q);
+                av[h] = ld_state<KV>(a.v + row, q);
+                ap[h] = ld_state<KP>(a.p + row, q);
+            }
+        }
+    }
     for (int d = threadIdx.x; d < D; d += BLOCK) {
         s_g[d] = a.gpos[d];
         s_shift[d] = a.shift[d];
@@ -425,83 +519,122 @@ __global__ void PSO_STEP_ATTR k_step_split(SwarmArgs a, uint32_t L, uint32_t C)
     }
     const unsigned long long thr = c->gkey_prev;
     __syncthreads();
-    const uint32_t k = threadIdx.x / Q, qq = threadIdx.x % Q;
-    const uint32_t q = blockIdx.x * Q + qq, i0 = 4 * q;
-    const bool active = i0 < a.N;
-    const uint32_t pend = active ? *reinterpret_cast<const uint32_t *>(a.pend + i0) : 0u;
     const bool line_dirty = group_dirty(pend);
-    if (active) {
-        const size_t Np = a.Np;
-        const int d_begin = (int)(k * C), d_end = min(D, (int)((k + 1) * C));
-        // software pipeline over the chunk's dimension pairs, as in the
-        // plain step: the next pair's rows are loaded before this pair's
-        // stores (D = 128, N = 65 536, us per iteration: Ackley 46.9 -> 45.9,
-        // Rosenbrock 36.9 -> 36.8)
-        f4 ax[2], av[2], ap[2];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            if (d_begin + h < d_end) {
-                const size_t row = (size_t)(d_begin + h) * Np;
-                ax[h] = ld_state<KX>(a.x + row, q);
-                av[h] = ld_state<KV>(a.v + row, q);
-                ap[h] = ld_state<KP>(a.p + row, q);
-            }
-        }
-        for (int d = d_begin; d < d_end; d += 2) {
-            f4 cx[2], cv[2], cp[2];
+    float acc = 0.0f, acc1 = 0.0f; // running sums of the folded particle (acc1: both words in one lane)
+    Fitness<FIT> rfit;             // Rosenbrock: the folded particle's running fitness
+#pragma unroll 1
+    for (uint32_t ph = 0; ph < H; ++ph) {
+        const int d_lo = (int)ph * DP; // first dimension of the phase
+        const int d_begin = d_lo + (int)(k * C), d_end = min(D, d_lo + (int)((k + 1) * C));
+        if (ph > 0) {
+            __syncthreads(); // the previous phase's terms are folded
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                cx[h] = ax[h];
-                cv[h] = av[h];
-                cp[h] = ap[h];
-            }
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                if (d + 2 + h < d_end) {
-                    const size_t row = (size_t)(d + 2 + h) * Np;
+                if (active && d_begin + h < d_end) {
+                    const size_t row = (size_t)(d_begin + h) * Np;
                     ax[h] = ld_state<KX>(a.x + row, q);
                     av[h] = ld_state<KV>(a.v + row, q);
                     ap[h] = ld_state<KP>(a.p + row, q);
                 }
             }
-            U4 u[4];
+        }
+        if (active) {
+            // software pipeline over the chunk's dimension pairs, as in the
+            // plain step: the next pair's rows are loaded before this pair's
+            // stores
+            for (int d = d_begin; d < d_end; d += 2) {
+                f4 cx[2], cv[2], cp[2];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) u[j] = philox4x32_10(a.k0, a.k1, (uint32_t)d >> 1, i0 + j, t, TAG_VEL);
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                if (h == 1 && d + 1 >= d_end) break;
-                const size_t row = (size_t)(d + h) * Np;
-                const f4 xn = update_row<POL>(a, row, q, cx[h], cv[h], cp[h], pend, line_dirty, u, h, s_g[d + h]);
-                const float sh = s_shift[d + h];
-                f4 w0, w1;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    float t0 = 0.0f, t1 = 0.0f;
-                    Fitness<FIT>::stage(xn[j] - sh, &t0, &t1);
-                    w0[j] = t0;
-                    w1[j] = t1;
+                for (int h = 0; h < 2; ++h) {
+                    cx[h] = ax[h];
+                    cv[h] = av[h];
+                    cp[h] = ap[h];
                 }
-                *reinterpret_cast<f4 *>(s_t0 + (size_t)(d + h) * P + 4 * qq) = w0;
-                if constexpr (W == 2) *reinterpret_cast<f4 *>(s_t1 + (size_t)(d + h) * P + 4 * qq) = w1;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    if (d + 2 + h < d_end) {
+                        const size_t row = (size_t)(d + 2 + h) * Np;
+                        ax[h] = ld_state<KX>(a.x + row, q);
+                        av[h] = ld_state<KV>(a.v + row, q);
+                        ap[h] = ld_state<KP>(a.p + row, q);
+                    }
+                }
+                U4 u[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) u[j] = philox4x32_10(a.k0, a.k1, (uint32_t)d >> 1, i0 + j, t, TAG_VEL);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    if (h == 1 && d + 1 >= d_end) break;
+                    const size_t row = (size_t)(d + h) * Np;
+                    const f4 xn =
+                        update_row<POL>(a, row, q, cx[h], cv[h], cp[h], pend, line_dirty, u, h, s_g[d + h]);
+                    const float sh = s_shift[d + h];
+                    f4 w0, w1;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const float z = xn[j] - sh;
+                        w0[j] = split_term<FIT>(z);
+                        if constexpr (W == 2) w1[j] = cospi_f32(2.0f * z);
+                    }
+                    const size_t at = (size_t)(d + h - d_lo) * P + 4 * qq;
+                    *reinterpret_cast<f4 *>(s_t0 + at) = w0;
+                    if constexpr (W == 2) *reinterpret_cast<f4 *>(s_t1 + at) = w1;
+                }
+            }
+        }
+        __syncthreads();
+        if (folder) {
+            const int n = min(DP, D - d_lo);
+            if constexpr (FIT == F_ROSENBROCK) {
+                fold_range<FIT>(rfit, s_t0, s_t1, P, fs, d_lo, n);
+            } else {
+                acc = fold_column(acc, (word ? s_t1 : s_t0) + fs, P, n);
+                if (W == 2 && !two) acc1 = fold_column(acc1, s_t1 + fs, P, n);
             }
         }
     }
-    __syncthreads();
-    // Step 4 for particle s of the workgroup: fold, strict improvement
+    // Step 4: strict improvement of each folded particle
     unsigned long long key = NO_KEY;
     uint32_t n_imp = 0;
-    for (uint32_t sidx = threadIdx.x; sidx < P; sidx += BLOCK) {
-        const uint32_t i = blockIdx.x * P + sidx;
-        if (i >= a.N) break;
-        const float f = fold_terms<FIT>(s_t0, s_t1, P, sidx, D);
-        const bool imp = f < a.pf[i];
-        if (imp) {
-            a.pf[i] = f;
-            const unsigned long long kk = make_key(f, i);
-            key = kk < key ? kk : key;
-            ++n_imp;
+    if (spread) {
+        const float other = __shfl(acc, (int)((lane + 32) & 63), 64); // Ackley's second sum, from lane + 32
+        if (owner) {
+            const uint32_t i = blockIdx.x * P + fs;
+            Fitness<FIT> fit = rfit;
+            if constexpr (FIT != F_ROSENBROCK) {
+                fit.acc = acc;
+                fit.aux = two ? other : acc1;
+            }
+            const float f = fit.value(D);
+            const bool imp = f < pf_old;
+            if (imp) {
+                a.pf[i] = f;
+                key = make_key(f, i);
+                n_imp = 1;
+            }
+            a.pend[i] = imp ? 1 : 0;
         }
-        a.pend[i] = imp ? 1 : 0;
+    } else {
+        for (uint32_t sidx = threadIdx.x; sidx < P; sidx += BLOCK) {
+            const uint32_t i = blockIdx.x * P + sidx;
+            if (i >= a.N) break;
+            Fitness<FIT> fit;
+            if constexpr (FIT == F_ROSENBROCK) {
+                fold_range<FIT>(fit, s_t0, s_t1, P, sidx, 0, D);
+            } else {
+                fit.acc = fold_column(0.0f, s_t0 + sidx, P, D);
+                if constexpr (W == 2) fit.aux = fold_column(0.0f, s_t1 + sidx, P, D);
+            }
+            const float f = fit.value(D);
+            const bool imp = f < a.pf[i];
+            if (imp) {
+                a.pf[i] = f;
+                const unsigned long long kk = make_key(f, i);
+                key = kk < key ? kk : key;
+                ++n_imp;
+            }
+            a.pend[i] = imp ? 1 : 0;
+        }
     }
     count_improvements(c, n_imp, &wg_count);
     const unsigned long long m = workgroup_min(key, thr, &wg_min);
@@ -793,16 +926,21 @@ hipError_t launch_init(int fitness, const SwarmArgs &a, hipStream_t stream)
     return hipGetLastError();
 }
 
-// Split shape (lanes per quad L, dimensions per lane C) for the step of a
-// swarm, or false for the plain step.  The split step runs with C <= 8 (4
-// for Ackley's two staged words, keeping its LDS at 32 KiB) and L a power of
-// two <= 64, for D >= 16.  It is chosen for N <= 2^17 (at most 512 plain
-// wavefronts, half a wavefront per SIMD) and, with two staged words, N*D <=
-// 2^24: measured on gfx950 over N = 2^14..2^19, D = 16..256 for Rastrigin,
-// Rosenbrock and Ackley, it is 1.1-8.9x faster there and slower beyond.
-// PSO_STEP_SPLIT=0 in the environment disables it, =1 uses it whenever the
-// shape allows (tests of both paths).
-static bool split_shape(const SwarmArgs &a, int words, uint32_t *L, uint32_t *C)
+// Split shape (lanes per quad L, dimensions per lane C, phases H) for the
+// step of a swarm, or false for the plain step.  The split step runs with C
+// <= 8 (4 for Ackley's two staged words, keeping its LDS at 32 KiB) and L a
+// power of two <= 64, for D >= 16.  It is chosen for N <= 2^17 (at most 512
+// plain wavefronts, half a wavefront per SIMD) and, with two staged words,
+// N*D <= 2^24: measured on gfx950 over N = 2^14..2^19, D = 16..256 for
+// Rastrigin, Rosenbrock and Ackley, it is 1.1-8.9x faster there and slower
+// beyond.  It runs in one phase: two phases of L / 2 lanes per quad (half
+// the LDS per particle, twice the particles per workgroup, so Ackley's 2048
+// workgroups at N = 65 536, D = 128 become 1024, all resident) need more
+// than 128 VGPRs and spill (us per iteration, one / two phases: Rosenbrock
+// 34.6 / 37.2, Ackley 44.0 / 48.2).  PSO_STEP_SPLIT=0 in the environment
+// disables the split step, =1 uses it whenever the shape allows;
+// PSO_SPLIT_PHASES=2 takes two phases where L >= 8 (tests of every path).
+static bool split_shape(const SwarmArgs &a, int words, uint32_t *L, uint32_t *C, uint32_t *H)
 {
     const char *env = getenv("PSO_STEP_SPLIT");
     const int mode = env ? atoi(env) : -1;
@@ -814,20 +952,28 @@ static bool split_shape(const SwarmArgs &a, int words, uint32_t *L, uint32_t *C)
     if (l > 64) return false;
     uint32_t c = ((uint32_t)a.D + l - 1) / l;
     c += c & 1u;
-    *L = l;
+    const char *penv = getenv("PSO_SPLIT_PHASES");
+    const int pmode = penv ? atoi(penv) : 0;
+    const uint32_t h = (pmode == 2 && l >= 8) ? 2u : 1u;
+    *L = l / h;
     *C = c;
+    *H = h;
     return true;
 }
 
 template <int FIT, int POL>
-static void launch_split(const SwarmArgs &a, uint32_t L, uint32_t C, hipStream_t stream)
+static void launch_split(const SwarmArgs &a, uint32_t L, uint32_t C, uint32_t H, hipStream_t stream)
 {
     constexpr int W = Fitness<FIT>::STAGE_WORDS;
     const uint32_t Q = BLOCK / L, P = 4 * Q;
+    const size_t DP = H > 1 ? (size_t)L * C : (size_t)a.D;
     const uint64_t quads = ((uint64_t)a.N + 3) / 4;
     const dim3 grid((unsigned)((quads + Q - 1) / Q));
-    const size_t lds = sizeof(float) * (2 * (size_t)a.D + (size_t)W * a.D * P);
-    hipLaunchKernelGGL((k_step_split<FIT, POL>), grid, dim3(BLOCK), lds, stream, a, L, C);
+    const size_t lds = sizeof(float) * (2 * (size_t)a.D + (size_t)W * DP * P);
+    if (H > 1)
+        hipLaunchKernelGGL((k_step_split<FIT, POL, 2>), grid, dim3(BLOCK), lds, stream, a, L, C);
+    else
+        hipLaunchKernelGGL((k_step_split<FIT, POL, 1>), grid, dim3(BLOCK), lds, stream, a, L, C);
 }
 
 // One particle per lane (k_step_one) for the shapes where it is the faster
@@ -881,7 +1027,7 @@ static void launch_async(const SwarmArgs &a, hipStream_t stream)
 template <int FIT, int VAR, int POL>
 static void launch_step_fvp(const SwarmArgs &a, hipStream_t stream)
 {
-    uint32_t L = 0, C = 0;
+    uint32_t L = 0, C = 0, H = 1;
     if (VAR == VAR_ASYNC) {
         launch_async<FIT, POL>(a, stream);
         return;
@@ -890,8 +1036,8 @@ static void launch_step_fvp(const SwarmArgs &a, hipStream_t stream)
         launch_one<FIT, POL>(a, stream);
         return;
     }
-    if (split_shape(a, Fitness<FIT>::STAGE_WORDS, &L, &C)) {
-        launch_split<FIT, POL>(a, L, C, stream);
+    if (split_shape(a, Fitness<FIT>::STAGE_WORDS, &L, &C, &H)) {
+        launch_split<FIT, POL>(a, L, C, H, stream);
         return;
     }
     const size_t lds = 2 * sizeof(float) * a.D;

@@ -389,6 +389,29 @@ __device__ __forceinline__ float fold_terms(const float *t0, const float *t1, si
     return fit.value(D);
 }
 
+// Folds the staged terms of dimensions d0 .. d0+n-1 (rows 0 .. n-1 of the
+// term arrays, column idx, row pitch `pitch`) into fit, in dimension order:
+// folding a particle's dimensions in consecutive ranges gives exactly
+// fold_terms over all of them.
+template <int FIT>
+__device__ __forceinline__ void fold_range(Fitness<FIT> &fit, const float *t0, const float *t1, size_t pitch,
+                                           uint32_t idx, int d0, int n)
+{
+    constexpr int W = Fitness<FIT>::STAGE_WORDS;
+    int j = 0;
+    for (; j + 8 <= n; j += 8) {
+        float a0[8], a1[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            a0[u] = t0[(size_t)(j + u) * pitch + idx];
+            a1[u] = W == 2 ? t1[(size_t)(j + u) * pitch + idx] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) fit.fold(a0[u], a1[u], d0 + j + u);
+    }
+    for (; j < n; ++j) fit.fold(t0[(size_t)j * pitch + idx], W == 2 ? t1[(size_t)j * pitch + idx] : 0.0f, d0 + j);
+}
+
 // p <- x for the marked particles of quad q; clears the marks.
 __device__ __forceinline__ void flush_quad(const SwarmArgs &a, uint32_t q)
 {

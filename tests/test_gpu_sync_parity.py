@@ -79,18 +79,22 @@ def test_deep_d128_full_run(mk):
     run_both(spec, spec.T, nthreads=16)
 
 
-@pytest.mark.parametrize("split", ["0", "1"])
+@pytest.mark.parametrize("split,phases", [("0", None), ("1", None), ("1", "1"), ("1", "2")])
 @pytest.mark.parametrize("fit", wl.FITNESS_NAMES)
 @pytest.mark.parametrize("N,D", [(4099, 16), (2050, 17), (3001, 33), (1025, 130), (701, 200), (129, 512)])
-def test_split_and_plain_steps_equal_oracle(monkeypatch, split, fit, N, D):
+def test_split_and_plain_steps_equal_oracle(monkeypatch, split, phases, fit, N, D):
     """The step launched per iteration, forced onto the plain kernel (four
     particles per lane) or the split kernel (lanes share a particle's
-    dimensions, terms folded in order from LDS): both bit-exact against the
-    oracle, over ragged particle counts, odd D, one to 64 chunks per quad."""
+    dimensions, terms folded in order from LDS), the latter in one phase or
+    in two (each half of the dimensions staged and folded in turn, the
+    running sum carried over): all bit-exact against the oracle, over ragged
+    particle counts, odd D, one to 64 chunks per quad."""
     monkeypatch.setenv("PSO_STEP_SPLIT", split)
+    if phases is not None:
+        monkeypatch.setenv("PSO_SPLIT_PHASES", phases)
     T = 30
     spec = wl.SwarmSpec(fit, N, D, T, seed=N + 7 * D, shift_amplitude=2.0)
-    announce(f"split={split} {fit} N={N} D={D} T={T}")
+    announce(f"split={split} phases={phases} {fit} N={N} D={D} T={T}")
     o = oracle_swarm(spec, 8).run_f32(T)
     with gpu_swarm(spec) as g:
         g.step(T)
