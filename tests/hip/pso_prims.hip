@@ -145,6 +145,26 @@ __global__ void k_seqlock_stress(SwarmArgs a, uint32_t writers, uint32_t rounds,
     }
 }
 
+// VALU throughput of the random-number generator: each lane draws `calls`
+// Philox4x32-10 blocks, four independent ones at a time (as a step kernel
+// draws one per particle of its quad), with the counters the step kernels
+// use -- (pair j, particle `lane`, iteration 0, velocity tag) under key
+// (k0, k1) -- and folds every output word into a running XOR, so no draw is
+// dead code; out[lane] receives the XOR.
+__global__ void __launch_bounds__(256) k_philox_rate(uint32_t k0, uint32_t k1, uint32_t calls, uint32_t *out)
+{
+    const uint32_t lane = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t acc = 0;
+    for (uint32_t j = 0; j < calls; j += 4) {
+        U4 u[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) u[k] = philox4x32_10(k0, k1, j + (uint32_t)k, lane, 0u, TAG_VEL);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc ^= u[k].a ^ u[k].b ^ u[k].c ^ u[k].d;
+    }
+    out[lane] = acc;
+}
+
 template <class T>
 hipError_t upload(T **d, const T *h, size_t n)
 {
@@ -220,6 +240,34 @@ int prim_group_min(const uint64_t *keys, const uint64_t *thr, int64_t groups, in
 out:
     (void)hipFree(dk);
     (void)hipFree(dt);
+    (void)hipFree(dout);
+    return rc;
+}
+
+// k_philox_rate over `lanes` lanes (a multiple of 256) and `calls` draws per
+// lane (a multiple of 4): out (lanes words) receives each lane's XOR and
+// *ms the kernel's time from HIP events (after one untimed launch).
+int prim_philox_rate(uint32_t k0, uint32_t k1, uint32_t calls, int64_t lanes, uint32_t *out, float *ms)
+{
+    if (lanes < 256 || lanes % 256 != 0 || lanes > (1ll << 24) || calls < 4 || calls % 4 != 0) return -1;
+    int rc = 0;
+    uint32_t *dout = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    TRY(hipMalloc(&dout, sizeof(uint32_t) * (size_t)lanes));
+    TRY(hipEventCreate(&e0));
+    TRY(hipEventCreate(&e1));
+    hipLaunchKernelGGL(k_philox_rate, dim3((uint32_t)(lanes / 256)), dim3(256), 0, 0, k0, k1, calls, dout);
+    TRY(hipGetLastError());
+    TRY(hipEventRecord(e0, 0));
+    hipLaunchKernelGGL(k_philox_rate, dim3((uint32_t)(lanes / 256)), dim3(256), 0, 0, k0, k1, calls, dout);
+    TRY(hipGetLastError());
+    TRY(hipEventRecord(e1, 0));
+    TRY(hipEventSynchronize(e1));
+    TRY(hipEventElapsedTime(ms, e0, e1));
+    TRY(hipMemcpy(out, dout, sizeof(uint32_t) * (size_t)lanes, hipMemcpyDeviceToHost));
+out:
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
     (void)hipFree(dout);
     return rc;
 }
