@@ -360,14 +360,17 @@ int pso_batch_get_shape(pso_batch *b, pso_batch_shape *shape);
 int pso_batch_set_shape(pso_batch *b, const pso_batch_shape *shape);
 
 /* Autotuner (the batching row of the workload set: tiles and schedules
- * picked by measurement on the device).  Times probe_iters iterations of the
- * whole batch under each candidate shape -- streamed: 64/128/256 lanes x
- * 2^15/2^17 updates per part x all or half of the co-resident workgroups;
- * LDS-staged: 512/1024 lanes x 78/158 KiB per workgroup (less for D above
- * 64), where the swarms fit -- each after an untimed Step 1, keeps the fastest, records it for
- * later batches of the same signature, and writes it to *chosen (may be
- * NULL).  Leaves the batch ready for pso_batch_launch (which restarts it).
- * Synchronous; costs about 16 x (probe_iters + 1) iterations of the batch.
+ * picked by measurement on the device).  Under each candidate shape --
+ * streamed: 64/128/256 lanes x 2^15/2^17 updates per part x all or half of
+ * the co-resident workgroups; LDS-staged: 512/1024 lanes x 78/158 KiB per
+ * workgroup (less for D above 64), where the swarms fit -- it runs Step 1
+ * untimed, then times launches of probe_iters and 3 x probe_iters
+ * iterations of the whole batch, splits a launch's time into a fixed part
+ * and a part per iteration, and prices the shape at the batch's mean
+ * iteration limit (max_iter); it keeps the cheapest, records it for later
+ * batches of the same signature, and writes it to *chosen (may be NULL).
+ * Leaves the batch ready for pso_batch_launch (which restarts it).
+ * Synchronous; costs about 16 x (4 probe_iters + 1) iterations of the batch.
  * probe_iters < 1 -> EINVAL. */
 int pso_batch_autotune(pso_batch *b, int64_t probe_iters, pso_batch_shape *chosen);
 

@@ -968,6 +968,28 @@ hipError_t launch_block_run(int fitness, const SwarmArgs &a, long long T, hipStr
 }
 
 
+__global__ void __launch_bounds__(64) k_upload(const UploadRec *recs, uint32_t n, const float *pool, BatchItem *items,
+                                                BatchResult *state)
+{
+    if (blockIdx.x >= n) return;
+    const UploadRec &u = recs[blockIdx.x];
+    if (threadIdx.x == 0) {
+        items[u.slot] = u.item;
+        state[u.slot] = u.state;
+        if (u.reset_gang && u.item.gang) *u.item.gang = GangSync{};
+    }
+    float *shift = const_cast<float *>(u.item.a.shift);
+    for (int d = threadIdx.x; d < u.item.a.D; d += 64) shift[d] = pool[u.shift_at + d];
+}
+
+hipError_t launch_upload(const UploadRec *recs, uint32_t n, const float *pool, BatchItem *items, BatchResult *state,
+                         hipStream_t stream)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_upload, dim3(n), dim3(64), 0, stream, recs, n, pool, items, state);
+    return hipGetLastError();
+}
+
 hipError_t launch_batch_reset(const BatchItem *items, BatchResult *results, uint32_t count, unsigned int *next,
                               hipStream_t stream)
 {

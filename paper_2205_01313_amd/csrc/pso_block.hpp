@@ -143,4 +143,21 @@ hipError_t shape_grid(int maxD, const BatchShape &sh, int *grid);
 // Sets one device word to zero with a kernel (stream-ordered; no memset).
 hipError_t launch_clear_u32(unsigned int *p, hipStream_t stream);
 
+// The first upload of a newly admitted request to the request server's
+// device tables: its item and loop state go to slot `slot`, its D shift
+// floats (from a launch's float pool, at shift_at) to item.a.shift, and a
+// swarm of several parts gets its gang counters cleared.  One record per
+// request; launch_upload applies a launch's records in one kernel, so the
+// uploads of a launch are two copies and one launch whatever their number.
+struct UploadRec {
+    BatchItem item;
+    BatchResult state;
+    uint32_t slot;
+    uint32_t shift_at;
+    uint32_t reset_gang;
+    uint32_t pad;
+};
+hipError_t launch_upload(const UploadRec *recs, uint32_t n, const float *pool, BatchItem *items, BatchResult *state,
+                         hipStream_t stream);
+
 } // namespace pso

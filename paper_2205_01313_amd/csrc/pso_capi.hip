@@ -961,12 +961,28 @@ int pso_batch_autotune(pso_batch *b, int64_t probe_iters, pso_batch_shape *chose
             (void)hipEventDestroy(e0);
             return fail(PSO_EDEVICE, "hipEventCreate failed");
         }
-        float best_ms = -1.0f;
+        // A launch costs a fixed part (Step 1 aside: a staged shape loads and
+        // stores every part's state once) plus a part per iteration.  Two
+        // probe lengths, p and 3p iterations, give both; a shape is priced
+        // at the batch's mean iteration limit, so the fixed cost of staging
+        // is not weighed as if a launch ran p iterations only.
+        double iters_run = 0.0;
+        for (int64_t i = 0; i < b->count; ++i) iters_run += double(b->items[i].max_iter);
+        iters_run = std::max(1.0, iters_run / double(b->count));
+        double best_ms = -1.0;
         pso::BatchShape best = b->shape;
         int rc = PSO_OK;
+        auto timed = [&](long long iters, float *ms) -> int {
+            if (hipEventRecord(e0, b->stream) != hipSuccess) return fail(PSO_EDEVICE, "hipEventRecord failed");
+            if (int r = batch_launch_iters(b, iters, false)) return r;
+            if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(ms, e0, e1) != hipSuccess)
+                return fail(PSO_EDEVICE, "timing a probe launch failed");
+            return PSO_OK;
+        };
         for (const pso::BatchShape &sh : tuner_candidates(b->maxD)) {
-            // Step 1 and one iteration untimed, then probe_iters timed iterations;
-            // a staged shape that this batch's swarms do not fit is skipped
+            // Step 1 and one iteration untimed, then the two timed probes; a
+            // staged shape that this batch's swarms do not fit is skipped
             if ((rc = batch_configure(b, sh))) {
                 if (sh.stage_kib > 0 && rc == PSO_EINVAL) {
                     rc = PSO_OK;
@@ -975,23 +991,17 @@ int pso_batch_autotune(pso_batch *b, int64_t probe_iters, pso_batch_shape *chose
                 break;
             }
             if ((rc = batch_launch_iters(b, 1, true))) break;
-            if (hipEventRecord(e0, b->stream) != hipSuccess) {
-                rc = fail(PSO_EDEVICE, "hipEventRecord failed");
-                break;
-            }
-            if ((rc = batch_launch_iters(b, probe_iters, false))) break;
-            float ms = 0.0f;
-            if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-                rc = fail(PSO_EDEVICE, "timing a probe launch failed");
-                break;
-            }
+            float t1 = 0.0f, t3 = 0.0f;
+            if ((rc = timed(probe_iters, &t1)) || (rc = timed(3 * probe_iters, &t3))) break;
             unsigned int err = 0;
             if (hipMemcpy(&err, b->d_err, sizeof err, hipMemcpyDeviceToHost) != hipSuccess || err) {
                 rc = fail(PSO_EDEVICE, "a probe launch reported a device error");
                 break;
             }
-            if (best_ms < 0.0f || ms < best_ms) {
+            const double per_iter = std::max(0.0, double(t3 - t1) / double(2 * probe_iters));
+            const double fixed = std::max(0.0, double(t1) - per_iter * double(probe_iters));
+            const double ms = fixed + per_iter * iters_run;
+            if (best_ms < 0.0 || ms < best_ms) {
                 best_ms = ms;
                 best = sh;
             }

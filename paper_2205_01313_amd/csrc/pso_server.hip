@@ -119,6 +119,9 @@ struct pso_server {
     pso::BatchResult *d_out[STREAMS] = {}; // compact state of a launch's items
     float *d_opos[STREAMS] = {};           // compact gbest positions (cap_pos floats)
     size_t cap_pos[STREAMS] = {};
+    pso::UploadRec *d_up[STREAMS] = {};    // a launch's first uploads (max_slots records)
+    float *d_pool[STREAMS] = {};           // their shift vectors (cap_pool floats)
+    size_t cap_pool[STREAMS] = {};
     int launch_maxD[STREAMS] = {};
     // pinned staging
     pso::BatchItem *h_items = nullptr;   // max_slots
@@ -127,7 +130,9 @@ struct pso_server {
     size_t cap_entries[STREAMS] = {};
     unsigned int *h_err[STREAMS] = {};
     pso::BatchResult *h_out[STREAMS] = {};
-    std::vector<float> h_opos[STREAMS];
+    float *h_opos[STREAMS] = {};        // cap_pos floats
+    pso::UploadRec *h_up[STREAMS] = {}; // max_slots records
+    float *h_pool[STREAMS] = {};        // cap_pool floats
     hipStream_t st[STREAMS] = {};
     hipEvent_t ev[STREAMS] = {};
     // bookkeeping (guarded by mu)
@@ -144,7 +149,6 @@ struct pso_server {
     std::vector<int> fresh;              // slots whose item/state must be uploaded
     std::vector<int> fresh_gang;         // of those, slots whose gang counter must be cleared
     std::vector<char> pending_upload;    // per slot: admitted, its upload not yet enqueued
-    pso::GangSync *h_gang0 = nullptr;    // pinned zeroed GangSync
     std::vector<int> inflight[STREAMS];  // slots of each in-flight launch
     bool busy[STREAMS] = {};
     std::thread th;
@@ -182,6 +186,11 @@ void server_free(pso_server *s)
         (void)hipFree(s->d_next[k]);
         (void)hipFree(s->d_out[k]);
         (void)hipFree(s->d_opos[k]);
+        (void)hipFree(s->d_up[k]);
+        (void)hipFree(s->d_pool[k]);
+        (void)hipHostFree(s->h_opos[k]);
+        (void)hipHostFree(s->h_up[k]);
+        (void)hipHostFree(s->h_pool[k]);
         (void)hipHostFree(s->h_entries[k]);
         (void)hipHostFree(s->h_err[k]);
         (void)hipHostFree(s->h_out[k]);
@@ -190,7 +199,6 @@ void server_free(pso_server *s)
     }
     (void)hipHostFree(s->h_items);
     (void)hipHostFree(s->h_state);
-    (void)hipHostFree(s->h_gang0);
     delete s;
 }
 
@@ -295,32 +303,55 @@ bool launch_ready(pso_server *s, int k)
     // this launch runs -- the slots in `sel`, nothing else.  An upload is
     // ordered before the launch on its own stream only, so a fresh slot left
     // for a later launch keeps its upload pending until that launch (on
-    // either stream) takes it.
+    // either stream) takes it.  The uploads of a launch are packed into one
+    // record array and one float pool: two copies and one scatter kernel
+    // (one copy per table entry cost a dispatch each -- about 200 per launch
+    // and 3 ms of stream time between launches at 10 000 requests/s).
     std::vector<char> in_sel(s->max_slots, 0);
     for (int slot : sel) in_sel[slot] = 1;
+    std::vector<char> gang_due(s->max_slots, 0);
+    for (int slot : s->fresh_gang) gang_due[slot] = 1;
     std::vector<int> fresh_rest, gang_rest;
+    size_t pool_need = 0;
+    for (int slot : s->fresh)
+        if (in_sel[slot]) pool_need += (size_t)s->slot_req[slot]->d.D;
+    if (pool_need > s->cap_pool[k]) { // grow this stream's float pool (the stream is idle)
+        if (hipStreamSynchronize(st) != hipSuccess) return false;
+        (void)hipFree(s->d_pool[k]);
+        (void)hipHostFree(s->h_pool[k]);
+        s->d_pool[k] = nullptr;
+        s->h_pool[k] = nullptr;
+        s->cap_pool[k] = std::max(pool_need, 2 * s->cap_pool[k]);
+        if (hipMalloc(&s->d_pool[k], sizeof(float) * s->cap_pool[k]) != hipSuccess ||
+            hipHostMalloc(reinterpret_cast<void **>(&s->h_pool[k]), sizeof(float) * s->cap_pool[k],
+                          hipHostMallocDefault) != hipSuccess)
+            return false;
+    }
+    uint32_t nup = 0, at = 0;
     for (int slot : s->fresh) {
         if (!in_sel[slot]) {
             fresh_rest.push_back(slot);
             continue;
         }
-        Req *r = s->slot_req[slot];
-        if (hipMemcpyAsync(&s->d_items[slot], &s->h_items[slot], sizeof(pso::BatchItem), hipMemcpyHostToDevice, st) !=
-                hipSuccess ||
-            hipMemcpyAsync(&s->d_state[slot], &s->h_state[slot], sizeof(pso::BatchResult), hipMemcpyHostToDevice, st) !=
-                hipSuccess ||
-            hipMemcpyAsync(const_cast<float *>(s->h_items[slot].a.shift), r->shift.data(), sizeof(float) * r->d.D,
-                           hipMemcpyHostToDevice, st) != hipSuccess)
-            return false;
+        const Req *r = s->slot_req[slot];
+        pso::UploadRec &u = s->h_up[k][nup++];
+        u.item = s->h_items[slot];
+        u.state = s->h_state[slot];
+        u.slot = (uint32_t)slot;
+        u.shift_at = at;
+        u.reset_gang = gang_due[slot] ? 1u : 0u;
+        u.pad = 0;
+        std::memcpy(s->h_pool[k] + at, r->shift.data(), sizeof(float) * r->d.D);
+        at += (uint32_t)r->d.D;
         s->pending_upload[slot] = 0;
     }
-    for (int slot : s->fresh_gang) {
-        if (!in_sel[slot]) {
-            gang_rest.push_back(slot);
-            continue;
-        }
-        if (hipMemcpyAsync(s->h_items[slot].gang, s->h_gang0, sizeof(pso::GangSync), hipMemcpyHostToDevice, st) !=
-            hipSuccess)
+    for (int slot : s->fresh_gang)
+        if (!in_sel[slot]) gang_rest.push_back(slot);
+    if (nup > 0) {
+        if (hipMemcpyAsync(s->d_up[k], s->h_up[k], sizeof(pso::UploadRec) * nup, hipMemcpyHostToDevice, st) !=
+                hipSuccess ||
+            hipMemcpyAsync(s->d_pool[k], s->h_pool[k], sizeof(float) * at, hipMemcpyHostToDevice, st) != hipSuccess ||
+            pso::launch_upload(s->d_up[k], nup, s->d_pool[k], s->d_items, s->d_state, st) != hipSuccess)
             return false;
     }
     s->fresh.swap(fresh_rest);
@@ -372,19 +403,26 @@ bool launch_ready(pso_server *s, int k)
         hipSuccess)
         return false;
     const size_t need = (size_t)n * maxD;
-    if (need > s->cap_pos[k]) { // grow the compact position buffer
+    if (need > s->cap_pos[k]) { // grow the compact position buffers
         if (hipStreamSynchronize(st) != hipSuccess) return false;
         (void)hipFree(s->d_opos[k]);
+        (void)hipHostFree(s->h_opos[k]);
         s->d_opos[k] = nullptr;
+        s->h_opos[k] = nullptr;
         s->cap_pos[k] = std::max(need, 2 * s->cap_pos[k]);
-        if (hipMalloc(&s->d_opos[k], sizeof(float) * s->cap_pos[k]) != hipSuccess) return false;
+        if (hipMalloc(&s->d_opos[k], sizeof(float) * s->cap_pos[k]) != hipSuccess ||
+            hipHostMalloc(reinterpret_cast<void **>(&s->h_opos[k]), sizeof(float) * s->cap_pos[k],
+                          hipHostMallocDefault) != hipSuccess)
+            return false;
     }
     const int grid = std::min<int>((int)ne, grid_cap);
     if (pso::launch_batch(s->d_items, s->d_entries[k], s->d_state, ne, s->d_next[k], maxD, grid,
                           staged ? SERVER_STAGE_LANES : pso::DEFAULT_BATCH_SHAPE.lanes, s->chunk, MAX_SLICE_ITERS, st,
                           s->d_out[k], s->d_opos[k], s->d_err, staged ? SERVER_STAGE_KIB : 0) != hipSuccess)
         return false;
+    // the launch's results, positions included, come back before its event
     if (hipMemcpyAsync(s->h_out[k], s->d_out[k], sizeof(pso::BatchResult) * n, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(s->h_opos[k], s->d_opos[k], sizeof(float) * need, hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipMemcpyAsync(s->h_err[k], s->d_err, sizeof(unsigned int), hipMemcpyDeviceToHost, st) != hipSuccess)
         return false;
     if (hipEventRecord(s->ev[k], st) != hipSuccess) return false;
@@ -399,11 +437,11 @@ bool launch_ready(pso_server *s, int k)
     return true;
 }
 
-// Collects a finished launch (its compact states are already on the host):
+// Collects a finished launch (its compact states and positions are already on
+// the host):
 // completed swarms return their result and memory; the others become ready.
 bool collect(pso_server *s, int k)
 {
-    hipStream_t st = s->st[k];
     if (*s->h_err[k]) return false; // parts of a swarm timed out waiting for each other
     const int n = (int)s->inflight[k].size();
     const int maxD = s->launch_maxD[k];
@@ -425,20 +463,13 @@ bool collect(pso_server *s, int k)
         else
             s->ready.push_back(slot);
     }
-    if (!done_j.empty()) {
-        s->h_opos[k].resize((size_t)n * maxD);
-        if (hipMemcpyAsync(s->h_opos[k].data(), s->d_opos[k], sizeof(float) * n * maxD, hipMemcpyDeviceToHost, st) !=
-                hipSuccess ||
-            hipStreamSynchronize(st) != hipSuccess)
-            return false;
-    }
     {
         std::lock_guard<std::mutex> g(s->mu);
         const auto now = s->now();
         for (int j : done_j) {
             const int slot = s->inflight[k][j];
             Req *r = s->slot_req[slot];
-            r->gpos.assign(s->h_opos[k].begin() + (size_t)j * maxD, s->h_opos[k].begin() + (size_t)j * maxD + r->d.D);
+            r->gpos.assign(s->h_opos[k] + (size_t)j * maxD, s->h_opos[k] + (size_t)j * maxD + r->d.D);
             r->t_done = now;
             r->status = PSO_OK;
             s->latencies.push_back(ms_since(r->t_submit, now));
@@ -600,8 +631,6 @@ int pso_server_create(size_t mem_budget, int64_t chunk_updates, pso_server **out
                   hipMalloc(&s->d_state, sizeof(pso::BatchResult) * s->max_slots) == hipSuccess &&
                   hipMalloc(&s->d_err, sizeof(unsigned int)) == hipSuccess &&
                   hipMemset(s->d_err, 0, sizeof(unsigned int)) == hipSuccess &&
-                  hipHostMalloc(reinterpret_cast<void **>(&s->h_gang0), sizeof(pso::GangSync), hipHostMallocDefault) ==
-                      hipSuccess &&
                   hipHostMalloc(reinterpret_cast<void **>(&s->h_items), sizeof(pso::BatchItem) * s->max_slots,
                                 hipHostMallocDefault) == hipSuccess &&
                   hipHostMalloc(reinterpret_cast<void **>(&s->h_state), sizeof(pso::BatchResult) * s->max_slots,
@@ -617,13 +646,15 @@ int pso_server_create(size_t mem_budget, int64_t chunk_updates, pso_server **out
                  hipHostMalloc(reinterpret_cast<void **>(&s->h_err[k]), sizeof(unsigned int), hipHostMallocDefault) ==
                      hipSuccess &&
                  hipStreamCreateWithFlags(&s->st[k], hipStreamNonBlocking) == hipSuccess &&
-                 hipEventCreateWithFlags(&s->ev[k], hipEventDisableTiming) == hipSuccess;
+                 hipEventCreateWithFlags(&s->ev[k], hipEventDisableTiming) == hipSuccess &&
+                 hipMalloc(&s->d_up[k], sizeof(pso::UploadRec) * s->max_slots) == hipSuccess &&
+                 hipHostMalloc(reinterpret_cast<void **>(&s->h_up[k]), sizeof(pso::UploadRec) * s->max_slots,
+                               hipHostMallocDefault) == hipSuccess;
         }
         if (!ok) {
             server_free(s);
             return pso_internal_fail(PSO_ENOMEM, "device or pinned allocation for the server failed");
         }
-        std::memset(s->h_gang0, 0, sizeof(pso::GangSync));
         for (int k = 0; k < STREAMS; ++k) s->cap_entries[k] = (size_t)s->max_slots;
         s->slot_req.assign(s->max_slots, nullptr);
         s->pending_upload.assign(s->max_slots, 0);

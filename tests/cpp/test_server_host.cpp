@@ -58,6 +58,12 @@ uint64_t mix(uint64_t x)
     return x ^ (x >> 33);
 }
 
+// the shift vector the load test gives the swarm with this seed; while
+// check_shift is set the model counts a violation for any other shift it
+// finds in a launched swarm's device state
+bool check_shift = false;
+float shift_of(uint64_t seed, int d) { return float(mix(seed * 7919u + (uint64_t)d) % 97) - 48.0f; }
+
 // pseudo-fitness of the swarm with this seed at iteration t (t = 0: Step 1)
 unsigned long long key_at(uint64_t seed, long long t, uint64_t N)
 {
@@ -108,6 +114,12 @@ void batch(const pso::BatchItem *items, const pso::BatchEntry *entries, pso::Bat
         }
         pso::BatchResult &r = results[e.item];
         const uint64_t seed = (uint64_t)it.a.k0 | ((uint64_t)it.a.k1 << 32);
+        if (check_shift)
+            for (int d = 0; d < it.a.D; ++d)
+                if (it.a.shift[d] != shift_of(seed, d)) {
+                    violations.fetch_add(1);
+                    break;
+                }
         auto met = [&] { return it.tol > 0.0f && std::fabs(pso::key_fitness(r.gkey) - it.fstar) < it.tol; };
         if (!r.started) {
             r = pso::BatchResult{key_at(seed, 0, it.a.N), 0, 0, 1u, 0u, 0u, 0u};
@@ -218,6 +230,23 @@ hipError_t launch_batch(const BatchItem *items, const BatchEntry *entries, Batch
     return hipSuccess;
 }
 
+hipError_t launch_upload(const UploadRec *recs, uint32_t n, const float *pool, BatchItem *items, BatchResult *state,
+                         hipStream_t stream)
+{
+    if (n == 0) return hipSuccess;
+    stub_enqueue(stream, [=] {
+        for (uint32_t r = 0; r < n; ++r) {
+            const UploadRec &u = recs[r];
+            items[u.slot] = u.item;
+            state[u.slot] = u.state;
+            if (u.reset_gang && u.item.gang) *u.item.gang = GangSync{};
+            float *shift = const_cast<float *>(u.item.a.shift);
+            for (int d = 0; d < u.item.a.D; ++d) shift[d] = pool[u.shift_at + d];
+        }
+    });
+    return hipSuccess;
+}
+
 } // namespace pso
 
 // ---------------------------------------------------------------------------
@@ -278,9 +307,14 @@ static void test_results_under_load()
     CHECK(pso_server_create(size_t(64) << 16, 0, &srv) == PSO_OK); // 64 slots
     const int n = 600;
     std::vector<pso_desc> descs(n);
+    std::vector<std::vector<float>> shifts(n);
     std::mt19937 rng(5);
-    for (int k = 0; k < n; ++k)
+    for (int k = 0; k < n; ++k) {
         descs[k] = desc_of(1000 + k, 16 + rng() % 3000, 1 + rng() % 40, 1 + rng() % 300, k % 5 == 0 ? 0.05f : 0.0f);
+        for (int d = 0; d < descs[k].D; ++d) shifts[k].push_back(model::shift_of(descs[k].seed, d));
+        descs[k].shift = shifts[k].data();
+    }
+    model::check_shift = true;
     std::vector<uint64_t> tickets(n);
     std::vector<std::vector<float>> pos(n);
     auto submitter = [&](int lo) {
@@ -309,6 +343,7 @@ static void test_results_under_load()
     CHECK(st.completed == (uint64_t)n && st.mem_used == 0 && st.launches > 20);
     CHECK(model::violations.load() == 0);
     CHECK(pso_server_destroy(srv) == PSO_OK);
+    model::check_shift = false;
     unsetenv("PSO_SERVER_LAUNCH_WAVES");
 }
 
