@@ -7,8 +7,11 @@
 // definition; Rastrigin and Ackley call the device's double cos and exp.
 //
 // Layout: x, v, p as double rows of Np particles (element (d, i) at
-// d*Np + i), one particle per lane (8-byte accesses, 512 bytes per
-// wavefront).  A new pbest position is written at once.  A 64-bit fitness
+// d*Np + i).  Small swarms take one particle per lane (8-byte accesses, 512
+// bytes per wavefront) and write a new pbest position at once; the grid step
+// of a large swarm takes two particles per lane with 16-byte accesses and
+// defers the pbest position into the next iteration's pass, as the binary32
+// step does (k_step64w).  A 64-bit fitness
 // and a particle index no longer fit one 64-bit word, so the gbest is not an
 // atomic minimum: every workgroup writes its (order bits, index) minimum of
 // the improved particles into its own slot, and the last workgroup to arrive
@@ -24,6 +27,7 @@
 #include "pso_device.hpp"
 #include "pso_f64.hpp"
 #include "pso_guard.hpp"
+#include "pso_kernels.hpp"
 
 int pso_internal_fail(int code, const char *fmt, ...);
 int pso_internal_check_desc(const pso_desc *d);
@@ -48,6 +52,7 @@ Layout64 layout64_of(uint64_t N, int D)
     L.slot_idx = o; o += al256(sizeof(uint32_t) * 2 * L.nblocks);
     L.cand_pos = o; o += al256(sizeof(double) * 2 * L.nblocks * (size_t)D);
     L.pf = o;       o += al256(sizeof(double) * L.Np);
+    L.pend = o;     o += al256(L.Np);
     L.x = o;        o += al256(sizeof(double) * L.Np * (size_t)D);
     L.v = o;        o += al256(sizeof(double) * L.Np * (size_t)D);
     L.p = o;        o += al256(sizeof(double) * L.Np * (size_t)D);
@@ -66,6 +71,7 @@ Swarm64Args bind64(void *base, const Layout64 &L, uint64_t N, int D)
     a.slot_idx = reinterpret_cast<uint32_t *>(b + L.slot_idx);
     a.cand_pos = reinterpret_cast<double *>(b + L.cand_pos);
     a.pf = reinterpret_cast<double *>(b + L.pf);
+    a.pend = reinterpret_cast<uint8_t *>(b + L.pend);
     a.x = reinterpret_cast<double *>(b + L.x);
     a.v = reinterpret_cast<double *>(b + L.v);
     a.p = reinterpret_cast<double *>(b + L.p);
@@ -301,6 +307,7 @@ __global__ void __launch_bounds__(BLOCK64) k_init64(Swarm64Args a)
     const uint32_t i = blockIdx.x * BLOCK64 + threadIdx.x;
     unsigned long long k = ~0ull;
     uint32_t ki = NO_IDX;
+    if (i < a.Np) a.pend[i] = 0;
     if (i < a.N) {
         const double f = init_particle64<FIT>(a, i, s_shift64);
         a.pf[i] = f;
@@ -342,6 +349,153 @@ __global__ void __launch_bounds__(BLOCK64) k_step64(Swarm64Args a)
     }
     wg_lexmin(k, ki, s_k, s_i);
     if (post_and_arrive64(a, k, ki, &last)) finish64(a, t, false, s_k, s_i);
+}
+
+// ---------------------------------------------------------------------------
+// Grid step of a large swarm: lane q owns particles 2q and 2q+1 and walks
+// their dimensions in order with 16-byte accesses of one dimension's row
+// (1 KiB per wavefront), the next dimension pair's rows loaded ahead.  A
+// particle whose pbest improves is marked in pend and its new pbest
+// position left in x; the next iteration reads x anyway, takes it as the
+// pbest position of marked particles and writes p for every lane of a
+// 64-byte group (4 lanes) holding a mark.  x may be kept in the
+// memory-side cache while v and p stream (cache_policy).  The arithmetic
+// of every element is iterate_particle64's, so the results are the same bits.
+// ---------------------------------------------------------------------------
+typedef double d2 __attribute__((ext_vector_type(2)));
+
+template <bool KEEP>
+__device__ __forceinline__ d2 ld64(const double *row, uint32_t q)
+{
+    if constexpr (KEEP)
+        return *(reinterpret_cast<const d2 *>(row) + q);
+    else
+        return __builtin_nontemporal_load(reinterpret_cast<const d2 *>(row) + q);
+}
+
+template <bool KEEP>
+__device__ __forceinline__ void st64(double *row, uint32_t q, d2 v)
+{
+    if constexpr (KEEP)
+        *(reinterpret_cast<d2 *>(row) + q) = v;
+    else
+        __builtin_nontemporal_store(v, reinterpret_cast<d2 *>(row) + q);
+}
+
+template <int FIT, int POL>
+__global__ void __launch_bounds__(BLOCK64) k_step64w(Swarm64Args a)
+{
+    __shared__ unsigned long long s_k[BLOCK64 / 64];
+    __shared__ uint32_t s_i[BLOCK64 / 64];
+    __shared__ int last;
+    extern __shared__ double s_dyn64[]; // gbest position (D), shift (D)
+    constexpr bool KX = (POL & KEEP_X) != 0, KV = (POL & KEEP_V) != 0, KP = (POL & KEEP_P) != 0;
+    Ctrl64 *c = a.ctrl;
+    if (c->stop) return;
+    const int D = a.D;
+    const size_t Np = a.Np;
+    double *s_g = s_dyn64, *s_shift = s_dyn64 + D;
+    for (int d = threadIdx.x; d < D; d += BLOCK64) {
+        s_g[d] = a.gpos[d];
+        s_shift[d] = a.shift[d];
+    }
+    const uint32_t t = (uint32_t)(c->t + 1);
+    const unsigned long long pk = c->gord;
+    const uint32_t pi = c->gidx;
+    const uint32_t q = blockIdx.x * BLOCK64 + threadIdx.x, i0 = 2 * q;
+    const bool active = i0 < a.N;
+    const uint32_t pend = active ? *reinterpret_cast<const uint16_t *>(a.pend + i0) : 0u;
+    const d2 pf_old = active ? *reinterpret_cast<const d2 *>(a.pf + i0) : d2{0.0, 0.0};
+    __syncthreads();
+    const unsigned long long dirty = __ballot(pend != 0u);
+    const bool line_dirty = ((dirty >> ((threadIdx.x & 63) & ~3u)) & 0xFull) != 0;
+    Fitness64<FIT> fit[2];
+    if (active) {
+        d2 ax[2], av[2], ap[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (h < D) {
+                ax[h] = ld64<KX>(a.x + (size_t)h * Np, q);
+                av[h] = ld64<KV>(a.v + (size_t)h * Np, q);
+                ap[h] = ld64<KP>(a.p + (size_t)h * Np, q);
+            }
+        }
+        for (int d = 0; d < D; d += 2) {
+            d2 cx[2], cv[2], cp[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                cx[h] = ax[h];
+                cv[h] = av[h];
+                cp[h] = ap[h];
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                if (d + 2 + h < D) {
+                    const size_t row = (size_t)(d + 2 + h) * Np;
+                    ax[h] = ld64<KX>(a.x + row, q);
+                    av[h] = ld64<KV>(a.v + row, q);
+                    ap[h] = ld64<KP>(a.p + row, q);
+                }
+            }
+            U4 u[2];
+#pragma unroll
+            for (int k = 0; k < 2; ++k) u[k] = philox4x32_10(a.k0, a.k1, (uint32_t)d >> 1, i0 + k, t, TAG_VEL);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                if (d + h >= D) break;
+                const size_t row = (size_t)(d + h) * Np;
+                d2 ps = cp[h], xn, vn;
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    if (pend & (0xFFu << (8 * k))) ps[k] = cx[h][k];
+                    const double x = cx[h][k], v = cv[h][k], p = ps[k];
+                    const double r1 = (double)unit_float(h ? u[k].c : u[k].a);
+                    const double r2 = (double)unit_float(h ? u[k].d : u[k].b);
+                    // Eq. 1 left to right, clamp to [-vmax, vmax]; Eq. 2, clamp to [lo, hi]
+                    double nv = a.w * v + a.c1 * r1 * (p - x) + a.c2 * r2 * (s_g[d + h] - x);
+                    nv = clampd(nv, -a.vmax, a.vmax);
+                    vn[k] = nv;
+                    xn[k] = clampd(x + nv, a.lo, a.hi);
+                    fit[k].add(xn[k] - s_shift[d + h], d + h);
+                }
+                st64<KX>(a.x + row, q, xn);
+                st64<KV>(a.v + row, q, vn);
+                if (line_dirty) st64<KP>(a.p + row, q, ps);
+            }
+        }
+    }
+    // Step 4: strict improvement (NaN never improves); candidates for the
+    // gbest as in k_step64
+    unsigned long long k = ~0ull;
+    uint32_t ki = NO_IDX;
+    if (active) {
+        uint32_t pend_new = 0;
+        d2 pf_new = pf_old;
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk) {
+            const uint32_t i = i0 + kk;
+            if (i >= a.N) continue;
+            const double f = fit[kk].value(D);
+            if (!(f < pf_old[kk])) continue;
+            pf_new[kk] = f;
+            pend_new |= 1u << (8 * kk);
+            const unsigned long long o = ord64(f);
+            if (o < pk || (o == pk && i < pi)) lexmin(k, ki, o, i);
+        }
+        if (pend_new) *reinterpret_cast<d2 *>(a.pf + i0) = pf_new;
+        if (pend_new != pend) *reinterpret_cast<uint16_t *>(a.pend + i0) = (uint16_t)pend_new;
+    }
+    wg_lexmin(k, ki, s_k, s_i);
+    if (post_and_arrive64(a, k, ki, &last)) finish64(a, t, false, s_k, s_i);
+}
+
+// p <- x for every pending particle; clears the marks.
+__global__ void __launch_bounds__(BLOCK64) k_flush64(Swarm64Args a)
+{
+    const uint32_t i = blockIdx.x * BLOCK64 + threadIdx.x;
+    if (i >= a.N || !a.pend[i]) return;
+    for (int d = 0; d < a.D; ++d) a.p[(size_t)d * a.Np + i] = a.x[(size_t)d * a.Np + i];
+    a.pend[i] = 0;
 }
 
 // Up to T iterations of a small swarm in one workgroup of LANES lanes
@@ -531,6 +685,18 @@ __global__ void k_arm64(Swarm64Args a, double tol, double fstar)
 
 static inline dim3 grid64(const Swarm64Args &a) { return dim3((a.N + BLOCK64 - 1) / BLOCK64); }
 
+// The grid step takes two particles per lane (k_step64w) from N = 2^14 on;
+// PSO64_WIDE=0 or 1 in the environment forces either form (tests of both).
+#ifndef PSO64_WIDE_MIN_N
+#define PSO64_WIDE_MIN_N 16384
+#endif
+static bool step64_wide(const Swarm64Args &a)
+{
+    const char *env = getenv("PSO64_WIDE");
+    if (env) return atoi(env) != 0;
+    return a.N >= PSO64_WIDE_MIN_N;
+}
+
 #define PSO64_DISPATCH(FN, ...)                                                                                    \
     switch (fitness) {                                                                                             \
     case F_SPHERE: FN<F_SPHERE>(__VA_ARGS__); break;                                                               \
@@ -574,7 +740,19 @@ static void init64_f(const Swarm64Args &a, hipStream_t s)
 template <int FIT>
 static void step64_f(const Swarm64Args &a, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_step64<FIT>, grid64(a), dim3(BLOCK64), 2 * sizeof(double) * a.D, s, a);
+    const size_t lds = 2 * sizeof(double) * a.D;
+    if (!step64_wide(a)) {
+        hipLaunchKernelGGL(k_step64<FIT>, grid64(a), dim3(BLOCK64), lds, s, a);
+        return;
+    }
+    const dim3 grid((a.Np / 2 + BLOCK64 - 1) / BLOCK64);
+    // rows of doubles: the binary32 policy at twice the row pitch in floats
+    switch (cache_policy(2 * (uint64_t)a.Np, a.D)) {
+    case POL_STREAM: hipLaunchKernelGGL((k_step64w<FIT, POL_STREAM>), grid, dim3(BLOCK64), lds, s, a); break;
+    case POL_X: hipLaunchKernelGGL((k_step64w<FIT, POL_X>), grid, dim3(BLOCK64), lds, s, a); break;
+    case POL_XV: hipLaunchKernelGGL((k_step64w<FIT, POL_XV>), grid, dim3(BLOCK64), lds, s, a); break;
+    default: hipLaunchKernelGGL((k_step64w<FIT, POL_ALL>), grid, dim3(BLOCK64), lds, s, a); break;
+    }
 }
 // One workgroup: 256 lanes for up to 512 particle-dimensions, else 1024.
 template <int FIT>
@@ -655,6 +833,12 @@ hipError_t launch64_block_run(int fitness, const Swarm64Args &a, long long T, hi
 hipError_t launch64_arm(const Swarm64Args &a, double tol, double fstar, hipStream_t stream)
 {
     hipLaunchKernelGGL(k_arm64, dim3(1), dim3(64), 0, stream, a, tol, fstar);
+    return hipGetLastError();
+}
+
+hipError_t launch64_flush(const Swarm64Args &a, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_flush64, grid64(a), dim3(BLOCK64), 0, stream, a);
     return hipGetLastError();
 }
 
@@ -828,10 +1012,15 @@ int pso64_run(pso_swarm64 *s, int64_t max_iter, double tol, double f_star, doubl
         const uint64_t nd = s->N * (uint64_t)s->D;
         const char *path = getenv("PSO64_PATH"); // tests of every path: block, gang, grid
         bool done_gang = false;
-        if (path ? !strcmp(path, "block") : nd <= block64_max_nd()) {
+        const bool block = path ? !strcmp(path, "block") : nd <= block64_max_nd();
+        const bool gang = !block && (path ? !strcmp(path, "gang") : s->D <= GANG64_MAX_D);
+        // those paths write each pbest position at once: complete the
+        // pending ones a wide grid step left
+        if (block || gang) HIP64_TRY(pso::launch64_flush(s->a, s->stream));
+        if (block) {
             HIP64_TRY(pso::launch64_block_run(s->fitness, s->a, max_iter, s->stream));
             done_gang = true;
-        } else if (path ? !strcmp(path, "gang") : s->D <= GANG64_MAX_D) {
+        } else if (gang) {
             HIP64_TRY(hipMemsetAsync(&s->a.ctrl->gang_arrive, 0, sizeof(unsigned long long), s->stream));
             HIP64_TRY(pso::launch64_gang(s->fitness, s->a, max_iter, s->stream, &done_gang));
         }
@@ -861,6 +1050,7 @@ int pso64_get_state(pso_swarm64 *s, double *x, double *v, double *p, double *pf,
 {
     return pso::guarded([&]() -> int {
         if (!s) return pso_internal_fail(PSO_EINVAL, "swarm is NULL");
+        HIP64_TRY(pso::launch64_flush(s->a, s->stream));
         HIP64_TRY(hipStreamSynchronize(s->stream));
         int rc;
         if ((rc = rows_to_host(s, s->a.x, x)) || (rc = rows_to_host(s, s->a.v, v)) || (rc = rows_to_host(s, s->a.p, p)))

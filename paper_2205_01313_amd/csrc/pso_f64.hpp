@@ -31,6 +31,7 @@ struct Swarm64Args {
     unsigned long long *slot_ord;  // one per grid workgroup (gang kernel: two per workgroup, by parity)
     uint32_t *slot_idx;            // as slot_ord
     double *cand_pos;              // gang kernel: [parity][workgroup][D] staged candidate positions
+    uint8_t *pend;                 // Np: 1 = pbest position of i is x, not yet in p (wide grid step)
     Ctrl64 *ctrl;
     uint32_t N, Np;
     int32_t D;
@@ -39,7 +40,7 @@ struct Swarm64Args {
 };
 
 struct Layout64 {
-    size_t ctrl, gpos, shift, slot_ord, slot_idx, cand_pos, pf, x, v, p, total;
+    size_t ctrl, gpos, shift, slot_ord, slot_idx, cand_pos, pf, pend, x, v, p, total;
     uint64_t Np;
     uint32_t nblocks;
 };
@@ -54,6 +55,9 @@ hipError_t launch64_init(int fitness, const Swarm64Args &a, hipStream_t stream);
 hipError_t launch64_step(int fitness, const Swarm64Args &a, hipStream_t stream);
 hipError_t launch64_block_run(int fitness, const Swarm64Args &a, long long T, hipStream_t stream);
 hipError_t launch64_arm(const Swarm64Args &a, double tol, double fstar, hipStream_t stream);
+// Copies every pending pbest position (wide grid step) from x to p and
+// clears the marks: before the state is read or another path runs.
+hipError_t launch64_flush(const Swarm64Args &a, hipStream_t stream);
 // out[m] = F(pts[m]) in binary64 for M device-resident points (row-major M x D).
 hipError_t launch64_eval(int fitness, const Swarm64Args &a, const double *pts, uint64_t M, double *out,
                          hipStream_t stream);

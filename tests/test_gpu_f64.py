@@ -74,6 +74,48 @@ def test_every_run_path_bit_for_bit(monkeypatch, path, fit, N, D):
     assert_equal64(st, o)
 
 
+@pytest.mark.parametrize("wide", ["0", "1"])
+@pytest.mark.parametrize("fit,N,D", [("sphere", 5001, 7), ("rosenbrock", 3001, 33), ("cubic", 2049, 1),
+                                     ("rosenbrock", 999, 2), ("sphere", 130, 64)])
+def test_wide_and_narrow_grid_steps_bit_for_bit(monkeypatch, wide, fit, N, D):
+    """The grid step with one particle per lane (each new pbest position
+    written at once) and with two (16-byte accesses, new pbest positions
+    deferred into the next iteration's pass): step by step, then continued by
+    pso64_run on the path the shape takes (the one-workgroup and gang paths
+    first complete the deferred positions), both bit for bit against the
+    oracle's binary64 mode."""
+    monkeypatch.setenv("PSO64_WIDE", wide)
+    T1, T2 = 20, 25
+    spec = wl.SwarmSpec(fit, N, D, T1 + T2, seed=3 * N + D, shift_amplitude=1.0)
+    announce(f"f64 wide={wide} {fit} N={N} D={D}")
+    o = oracle_swarm(spec, 8).run_f64(T1 + T2)
+    with gpu64(spec) as g:
+        g.step(T1)
+        mid = g.state()
+        r = g.run(T2)
+        st = g.state()
+    assert mid["t"] == T1 and st["t"] == T1 + T2
+    assert r["gbest_fit"] == o["gbest_fit"] and r["gbest_iter"] == o["giter"]
+    assert np.array_equal(r["gbest_pos"].view(np.uint64), o["gpos"].view(np.uint64))
+    assert st["gbest_idx"] == o["gbest_idx"]
+    assert_equal64(st, o)
+
+
+def test_large_swarm_wide_step_bit_for_bit():
+    """A swarm large enough to take the two-particles-per-lane grid step by
+    default (Sphere, N = 2^18, D = 32, 6 iterations): the state bit for bit."""
+    T = 6
+    spec = wl.SwarmSpec("sphere", 1 << 18, 32, T, seed=41, shift_amplitude=3.0)
+    announce("f64 wide default N=2^18 D=32")
+    o = oracle_swarm(spec, 16).run_f64(T)
+    with gpu64(spec) as g:
+        r = g.run(T)
+        st = g.state()
+    assert r["gbest_fit"] == o["gbest_fit"] and r["gbest_iter"] == o["giter"]
+    assert st["gbest_idx"] == o["gbest_idx"]
+    assert_equal64(st, o)
+
+
 @pytest.mark.parametrize("path", ["block", "gang", "grid"])
 def test_stop_rule_on_every_path(monkeypatch, path):
     monkeypatch.setenv("PSO64_PATH", path)
