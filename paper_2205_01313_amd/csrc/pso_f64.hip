@@ -198,6 +198,50 @@ __device__ void wg_lexmin(unsigned long long &k, uint32_t &i, unsigned long long
     __syncthreads();
 }
 
+// Wavefront lexicographic minimum of the candidates (lanes with i != NO_IDX,
+// k != ~0) in every lane.  Beating the gbest is rare after the first
+// iterations, so a wavefront with no candidate or one takes no shuffles.
+__device__ __forceinline__ void wave_lexmin_sparse(unsigned long long &k, uint32_t &i)
+{
+    const unsigned long long m = __ballot(i != NO_IDX);
+    if (m == 0) {
+        k = ~0ull;
+        i = NO_IDX;
+    } else if ((m & (m - 1)) == 0) {
+        const int l = __builtin_ctzll(m);
+        const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)k, l), hi = __builtin_amdgcn_readlane((uint32_t)(k >> 32), l);
+        k = ((unsigned long long)hi << 32) | lo;
+        i = __builtin_amdgcn_readlane(i, l);
+    } else {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            const unsigned long long k2 = __shfl_xor(k, off, 64);
+            const uint32_t i2 = __shfl_xor(i, off, 64);
+            lexmin(k, i, k2, i2);
+        }
+    }
+}
+
+// Workgroup form of wave_lexmin_sparse: the wavefront minima meet in LDS
+// behind one barrier.  No barrier at the end: the caller holds one between
+// this call and its next.
+template <int LANES>
+__device__ __forceinline__ void wg_lexmin_sparse(unsigned long long &k, uint32_t &i, unsigned long long *s_k,
+                                                 uint32_t *s_i)
+{
+    wave_lexmin_sparse(k, i);
+    constexpr int NW = LANES / 64;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) {
+        s_k[w] = k;
+        s_i[w] = i;
+    }
+    __syncthreads();
+    k = lane < NW ? s_k[lane] : ~0ull;
+    i = lane < NW ? s_i[lane] : NO_IDX;
+    wave_lexmin_sparse(k, i);
+}
+
 // Step 1 for particle i: x ~ U[lo, hi), v ~ U[-vmax, vmax), p = x; returns F(x).
 template <int FIT>
 __device__ double init_particle64(const Swarm64Args &a, uint32_t i, const double *s_shift)
@@ -489,6 +533,101 @@ __global__ void __launch_bounds__(BLOCK64) k_step64w(Swarm64Args a)
     if (post_and_arrive64(a, k, ki, &last)) finish64(a, t, false, s_k, s_i);
 }
 
+// ---------------------------------------------------------------------------
+// Up to T iterations of a small swarm in one workgroup with its whole state
+// in LDS: x, v, p as rows of N doubles, then pf, loaded once and stored back
+// at the end.  An iteration then waits on no device-memory access (the
+// unstaged form below waits on the state's loads, the pbest fitness after
+// the stores, and the new gbest position: about 3 us per iteration at
+// N = 1024, D = 1).  Lane t runs particles t, t + LANES, ... with
+// iterate_particle64's arithmetic, so the results are the same bits.  ONE:
+// the paper's one-dimensional problems, loops resolved at compile time.
+// ---------------------------------------------------------------------------
+template <int FIT, int LANES, bool ONE>
+__global__ void __launch_bounds__(LANES) k_block_run64s(Swarm64Args a, long long T)
+{
+    __shared__ unsigned long long s_k[LANES / 64];
+    __shared__ uint32_t s_i[LANES / 64];
+    extern __shared__ double s_dyn64[]; // gbest position (D), shift (D), x, v, p (D x N each), pf (N)
+    Ctrl64 *c = a.ctrl;
+    const int D = ONE ? 1 : a.D;
+    const uint32_t N = a.N;
+    const size_t Np = a.Np, rows = (size_t)D * N;
+    double *s_g = s_dyn64, *s_shift = s_g + D, *sx = s_shift + D, *sv = sx + rows, *sp = sv + rows, *spf = sp + rows;
+    for (int d = threadIdx.x; d < D; d += LANES) {
+        s_g[d] = a.gpos[d];
+        s_shift[d] = a.shift[d];
+    }
+    for (size_t e = threadIdx.x; e < rows; e += LANES) {
+        const size_t d = e / N, i = e % N, g = d * Np + i;
+        sx[e] = a.x[g];
+        sv[e] = a.v[g];
+        sp[e] = a.p[g];
+    }
+    for (uint32_t i = threadIdx.x; i < N; i += LANES) spf[i] = a.pf[i];
+    unsigned long long gk = c->gord;
+    uint32_t gi = c->gidx;
+    long long giter = c->giter, t = c->t;
+    bool stop = c->stop != 0;
+    const double tol = c->tol, fstar = c->fstar;
+    __syncthreads();
+    for (long long it = 0; it < T && !stop; ++it) {
+        const uint32_t t1 = (uint32_t)(t + 1);
+        unsigned long long k = ~0ull;
+        uint32_t ki = NO_IDX;
+        for (uint32_t i = threadIdx.x; i < N; i += LANES) {
+            Fitness64<FIT> fit;
+            for (int d = 0; d < D; d += 2) {
+                const U4 u = philox4x32_10(a.k0, a.k1, (uint32_t)d >> 1, i, t1, TAG_VEL);
+                for (int h = 0; h < 2 && d + h < D; ++h) {
+                    const double r1 = (double)unit_float(h ? u.c : u.a), r2 = (double)unit_float(h ? u.d : u.b);
+                    const size_t e = (size_t)(d + h) * N + i;
+                    const double x = sx[e], v = sv[e], p = sp[e];
+                    // Eq. 1 left to right, clamp to [-vmax, vmax]; Eq. 2, clamp to [lo, hi]
+                    double vn = a.w * v + a.c1 * r1 * (p - x) + a.c2 * r2 * (s_g[d + h] - x);
+                    vn = clampd(vn, -a.vmax, a.vmax);
+                    const double xn = clampd(x + vn, a.lo, a.hi);
+                    sx[e] = xn;
+                    sv[e] = vn;
+                    fit.add(xn - s_shift[d + h], d + h);
+                }
+            }
+            const double f = fit.value(D);
+            if (f < spf[i]) { // strict; NaN never improves
+                spf[i] = f;
+                for (int d = 0; d < D; ++d) sp[(size_t)d * N + i] = sx[(size_t)d * N + i];
+                const unsigned long long o = ord64(f);
+                if (o < gk || (o == gk && i < gi)) lexmin(k, ki, o, i);
+            }
+        }
+        wg_lexmin_sparse<LANES>(k, ki, s_k, s_i); // its barrier follows every lane's LDS stores
+        if (ki != NO_IDX) {
+            gk = k;
+            gi = ki;
+            giter = t1;
+            for (int d = threadIdx.x; d < D; d += LANES) s_g[d] = sx[(size_t)d * N + gi];
+        }
+        t = t1;
+        stop = tol > 0.0 && fabs(spf[gi] - fstar) < tol;
+        __syncthreads();
+    }
+    for (size_t e = threadIdx.x; e < rows; e += LANES) {
+        const size_t d = e / N, i = e % N, g = d * Np + i;
+        a.x[g] = sx[e];
+        a.v[g] = sv[e];
+        a.p[g] = sp[e];
+    }
+    for (uint32_t i = threadIdx.x; i < N; i += LANES) a.pf[i] = spf[i];
+    for (int d = threadIdx.x; d < D; d += LANES) a.gpos[d] = s_g[d];
+    if (threadIdx.x == 0) {
+        c->gord = gk;
+        c->gidx = gi;
+        c->giter = giter;
+        c->t = t;
+        c->stop = stop ? 1u : 0u;
+    }
+}
+
 // p <- x for every pending particle; clears the marks.
 __global__ void __launch_bounds__(BLOCK64) k_flush64(Swarm64Args a)
 {
@@ -685,6 +824,30 @@ __global__ void k_arm64(Swarm64Args a, double tol, double fstar)
 
 static inline dim3 grid64(const Swarm64Args &a) { return dim3((a.N + BLOCK64 - 1) / BLOCK64); }
 
+// Dynamic LDS of the staged one-workgroup run: gbest position and shift, x,
+// v, p (D x N doubles each) and pf; 0 where it does not fit one workgroup
+// (or PSO64_BLOCK_STAGED=0 in the environment: the unstaged run, for tests).
+static int lds64_max()
+{
+    static const int v = [] {
+        int dev = 0, b = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&b, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+            return 0;
+        return b;
+    }();
+    return v;
+}
+
+static size_t block64_staged_lds(const Swarm64Args &a)
+{
+    if (!lds64_max()) return 0;
+    const char *env = getenv("PSO64_BLOCK_STAGED");
+    if (env && !strcmp(env, "0")) return 0;
+    const size_t bytes = sizeof(double) * (2 * (size_t)a.D + (3 * (size_t)a.D + 1) * a.N);
+    return bytes + 1024 <= (size_t)lds64_max() ? bytes : 0;
+}
+
 // The grid step takes two particles per lane (k_step64w) from N = 2^14 on;
 // PSO64_WIDE=0 or 1 in the environment forces either form (tests of both).
 #ifndef PSO64_WIDE_MIN_N
@@ -759,7 +922,29 @@ template <int FIT>
 static void block64_f(const Swarm64Args &a, long long T, hipStream_t s)
 {
     const size_t lds = 2 * sizeof(double) * a.D;
-    if ((uint64_t)a.N * (uint64_t)a.D <= 512)
+    const bool small = (uint64_t)a.N * (uint64_t)a.D <= 512;
+    const size_t staged = block64_staged_lds(a);
+    if (staged > 0) {
+        const bool one = a.D == 1;
+        const void *f = small ? (one ? reinterpret_cast<const void *>(k_block_run64s<FIT, 256, true>)
+                                     : reinterpret_cast<const void *>(k_block_run64s<FIT, 256, false>))
+                              : (one ? reinterpret_cast<const void *>(k_block_run64s<FIT, 1024, true>)
+                                     : reinterpret_cast<const void *>(k_block_run64s<FIT, 1024, false>));
+        // the most any swarm may ask for, so concurrent callers never lower it
+        if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds64_max() - 1024) == hipSuccess) {
+            const dim3 lanes(small ? 256 : 1024);
+            if (small && one)
+                hipLaunchKernelGGL((k_block_run64s<FIT, 256, true>), dim3(1), lanes, staged, s, a, T);
+            else if (small)
+                hipLaunchKernelGGL((k_block_run64s<FIT, 256, false>), dim3(1), lanes, staged, s, a, T);
+            else if (one)
+                hipLaunchKernelGGL((k_block_run64s<FIT, 1024, true>), dim3(1), lanes, staged, s, a, T);
+            else
+                hipLaunchKernelGGL((k_block_run64s<FIT, 1024, false>), dim3(1), lanes, staged, s, a, T);
+            return;
+        }
+    }
+    if (small)
         hipLaunchKernelGGL((k_block_run64<FIT, 256>), dim3(1), dim3(256), lds, s, a, T);
     else
         hipLaunchKernelGGL((k_block_run64<FIT, 1024>), dim3(1), dim3(1024), lds, s, a, T);
@@ -824,6 +1009,8 @@ hipError_t launch64_step(int fitness, const Swarm64Args &a, hipStream_t stream)
     return hipGetLastError();
 }
 
+bool block64_staged_fits(const Swarm64Args &a) { return block64_staged_lds(a) > 0; }
+
 hipError_t launch64_block_run(int fitness, const Swarm64Args &a, long long T, hipStream_t stream)
 {
     PSO64_DISPATCH(block64_f, a, T, stream);
@@ -865,22 +1052,19 @@ namespace {
         if (e_ != hipSuccess) return pso_internal_fail(PSO_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));      \
     } while (0)
 
-// Paths of pso64_run.  Up to BLOCK64_MAX_ND particle-dimensions the whole
-// run is one workgroup; for D <= GANG64_MAX_D the persistent gang; else one
-// grid launch per iteration.  Measured (Cubic 1D, us per iteration, one
-// workgroup / gang / grid): N = 1024: 3.1 / 4.0 / 5.9; 2048: 3.9 / 4.2 / 6.0;
-// 4096: 5.9 / 4.9 / 6.3; 16384: 17.1 / 6.7 / 7.4; 131072: - / 12.4 / 15.7;
-// at D = 120 the gang and the grid are within 2 % (N = 8192), so the grid
-// runs.  PSO64_BLOCK_MAX_ND and PSO64_PATH (block, gang, grid) override the
-// choice (tests of every path).
+// Paths of pso64_run.  A swarm whose state fits the LDS of one workgroup
+// (x, v, p and pf: about 6 700 particle-dimensions) runs there in one launch;
+// else for D <= GANG64_MAX_D the persistent gang; else one grid launch per
+// iteration.  Measured (Cubic, us per iteration, one workgroup / gang or
+// grid): N = 1024, D = 1: 1.28 / 4.7; 4096, 1: 3.41 / 4.88; 5000, 1:
+// 4.13 / 5.79; 1500, 4: 3.82 / 6.55; 768, 8: 4.33 / 9.32; 384, 16: 6.32 /
+// 10.0 (grid); 64, 100: 25.5 / 29.2 (grid).  Gang against grid (D = 1): N =
+// 16384: 6.7 / 7.4; 131072: 12.4 / 15.7; at D = 120 within 2 % (N = 8192),
+// so the grid runs.  PSO64_PATH (block, gang, grid) overrides the choice
+// (tests of every path); with PSO64_BLOCK_STAGED=0 the one-workgroup run
+// keeps the state in device memory and takes up to BLOCK64_MAX_ND.
 constexpr uint64_t BLOCK64_MAX_ND = 2048;
 constexpr int GANG64_MAX_D = 8;
-
-uint64_t block64_max_nd()
-{
-    const char *env = getenv("PSO64_BLOCK_MAX_ND");
-    return env ? (uint64_t)strtoull(env, nullptr, 10) : BLOCK64_MAX_ND;
-}
 
 void free64(pso_swarm64 *s)
 {
@@ -1012,7 +1196,7 @@ int pso64_run(pso_swarm64 *s, int64_t max_iter, double tol, double f_star, doubl
         const uint64_t nd = s->N * (uint64_t)s->D;
         const char *path = getenv("PSO64_PATH"); // tests of every path: block, gang, grid
         bool done_gang = false;
-        const bool block = path ? !strcmp(path, "block") : nd <= block64_max_nd();
+        const bool block = path ? !strcmp(path, "block") : pso::block64_staged_fits(s->a) || nd <= BLOCK64_MAX_ND;
         const bool gang = !block && (path ? !strcmp(path, "gang") : s->D <= GANG64_MAX_D);
         // those paths write each pbest position at once: complete the
         // pending ones a wide grid step left

@@ -74,6 +74,34 @@ def test_every_run_path_bit_for_bit(monkeypatch, path, fit, N, D):
     assert_equal64(st, o)
 
 
+@pytest.mark.parametrize("staged", ["1", "0"])
+@pytest.mark.parametrize("fit,N,D,tol", [("cubic", 4096, 1, 0.0), ("cubic", 33, 1, 0.0), ("cubic", 1500, 1, 0.0),
+                                         ("rosenbrock", 300, 6, 0.0), ("sphere", 100, 3, 0.0),
+                                         ("sphere", 2000, 4, 0.0), ("sphere", 900, 2, 1e-3),
+                                         ("sphere", 900, 2, 1e-5)])
+def test_one_workgroup_run_in_lds_and_in_memory(monkeypatch, staged, fit, N, D, tol):
+    """The one-workgroup run with the swarm's state in LDS for the whole
+    run (256 or 1024 lanes, the one-dimensional form, up to four particles
+    per lane with a ragged last round) and with it in device memory; Sphere
+    N = 2000, D = 4 does not fit LDS and takes the second form either way.
+    Bit for bit against the oracle's binary64 mode, over two runs (the state
+    is stored back after the first and loaded again), with a stop rule."""
+    monkeypatch.setenv("PSO64_PATH", "block")
+    monkeypatch.setenv("PSO64_BLOCK_STAGED", staged)
+    T = 80
+    spec = wl.SwarmSpec(fit, N, D, T, seed=5 * N + D, shift_amplitude=2.5)
+    announce(f"f64 block staged={staged} {fit} N={N} D={D} tol={tol}")
+    o = oracle_swarm(spec, 8).run_f64(T, tol=tol, f_star=0.0)
+    with gpu64(spec) as g:
+        r1 = g.run(T // 4, tol=tol, f_star=0.0)
+        r2 = g.run(T - r1["iters"], tol=tol, f_star=0.0) if r1["iters"] == T // 4 else r1
+        st = g.state()
+    assert st["t"] == o["iters"] and st["gbest_idx"] == o["gbest_idx"]
+    assert r2["gbest_fit"] == o["gbest_fit"] and r2["gbest_iter"] == o["giter"]
+    assert np.array_equal(r2["gbest_pos"].view(np.uint64), o["gpos"].view(np.uint64))
+    assert_equal64(st, o)
+
+
 @pytest.mark.parametrize("wide", ["0", "1"])
 @pytest.mark.parametrize("fit,N,D", [("sphere", 5001, 7), ("rosenbrock", 3001, 33), ("cubic", 2049, 1),
                                      ("rosenbrock", 999, 2), ("sphere", 130, 64)])
