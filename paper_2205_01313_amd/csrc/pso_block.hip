@@ -519,6 +519,29 @@ __device__ void staged_store(const SwarmArgs &a, const Staged &S)
     }
 }
 
+// workgroup_min for the staged iteration: a wavefront with one candidate
+// (the usual case once the gbest changes rarely) reads it from that lane
+// instead of taking the butterfly.  Same contract: *wg_min holds NO_KEY
+// before the call; ends with a barrier; the minimum in every lane.
+__device__ __forceinline__ unsigned long long workgroup_min_sparse(unsigned long long key, unsigned long long thr,
+                                                                   unsigned long long *wg_min)
+{
+    const unsigned long long c = __ballot(key < thr);
+    if (c) {
+        unsigned long long m;
+        if ((c & (c - 1)) == 0) {
+            const int l = __builtin_ctzll(c);
+            m = ((unsigned long long)__builtin_amdgcn_readlane((uint32_t)(key >> 32), l) << 32) |
+                __builtin_amdgcn_readlane((uint32_t)key, l);
+        } else {
+            m = wave_min_u64(key < thr ? key : NO_KEY);
+        }
+        if ((threadIdx.x & 63) == 0) atomicMin(wg_min, m);
+    }
+    __syncthreads();
+    return *wg_min;
+}
+
 // Up to T iterations of a staged part after L.t, stopping after the first
 // iteration at which the stop rule (tol, fstar) holds (tested before the
 // first one too); a part of several meets the others every iteration.
@@ -560,7 +583,78 @@ __device__ uint32_t staged_iterate(const SwarmArgs &a, const Staged &S, const Pa
             }
         }
     };
+    // Step 5 and the stop rule once the lanes have taken iteration t (key:
+    // the lane's least improved pbest key); ends with a barrier
+    auto end_iteration = [&](uint32_t t, unsigned long long key, long long n) {
+        const unsigned long long m = workgroup_min_sparse(key, L.gkey, &sc->min[t & 1]);
+        if (threadIdx.x == 0) sc->min[(t + 1) & 1] = NO_KEY;
+        unsigned long long g = m;
+        uint32_t owner = 0;
+        if (P.parts > 1) {
+            if (m != NO_KEY) stage_candidate<LANES>(P, t, D, la.x, pitch, (uint32_t)m - ibase);
+            gang_post<LANES>(P, t, m);
+            if (split && n + 1 < T) own_half(t + 1);
+            g = gang_wait<LANES>(P, t, sc, &owner);
+        }
+        if (g < L.gkey) {
+            L.gkey = g;
+            L.giter = t;
+            if (P.parts == 1) {
+                const uint32_t mi = (uint32_t)g - ibase;
+                for (int d = threadIdx.x; d < D; d += LANES) s_g[d] = la.x[(size_t)d * pitch + mi];
+            } else {
+                gather_gbest<LANES>(a, P, t, g, owner, s_g);
+            }
+        }
+        if (hist && threadIdx.x == 0) hist[t & (HIST_CAP - 1)] = L.gkey;
+        L.t = t;
+        L.stop = meets_tol(L.gkey, tol, fstar);
+        __syncthreads();
+    };
     L.stop = L.stop || meets_tol(L.gkey, tol, fstar);
+    if (!split && npairs == 1) {
+        // D <= 2: a lane takes its particles whole, the fitness summed in
+        // registers (add(z, d) = stage then fold), then Step 4; no staged
+        // terms and no barrier between the update and the fold
+        for (long long n = 0; n < T && !L.stop; ++n) {
+            const uint32_t t = (uint32_t)(L.t + 1);
+            unsigned long long key = NO_KEY;
+            for (uint32_t sidx = threadIdx.x; sidx < pitch; sidx += LANES) {
+                const uint32_t i = ibase + sidx;
+                const bool pend = la.pend[sidx] != 0;
+                const U4 u = philox4x32_10(a.k0, a.k1, 0u, i, t, TAG_VEL);
+                Fitness<FIT> fit;
+#pragma unroll
+                for (int d = 0; d < 2; ++d) {
+                    if (d >= D) break;
+                    const size_t e = (size_t)d * pitch + sidx;
+                    const float x = la.x[e], v = la.v[e];
+                    const float p = pend ? x : la.p[e];
+                    const float nv =
+                        velocity_eq1(la, x, v, p, s_g[d], unit_float(word_r1(u, d)), unit_float(word_r2(u, d)));
+                    const float xn = position_eq2(la, x, nv);
+                    la.x[e] = xn;
+                    la.v[e] = nv;
+                    if (pend) la.p[e] = p;
+                    fit.add(xn - s_shift[d], d);
+                }
+                bool imp = false;
+                if (i < a.N) {
+                    const float f = fit.value(D);
+                    imp = f < la.pf[sidx];
+                    if (imp) {
+                        la.pf[sidx] = f;
+                        const unsigned long long kk = make_key(f, i);
+                        key = kk < key ? kk : key;
+                        ++n_imp;
+                    }
+                }
+                la.pend[sidx] = imp ? 1 : 0;
+            }
+            end_iteration(t, key, n);
+        }
+        return n_imp;
+    }
     if (split && T > 0 && !L.stop) own_half((uint32_t)(L.t + 1));
     for (long long n = 0; n < T && !L.stop; ++n) {
         const uint32_t t = (uint32_t)(L.t + 1);
@@ -624,30 +718,7 @@ __device__ uint32_t staged_iterate(const SwarmArgs &a, const Staged &S, const Pa
             }
             la.pend[sidx] = imp ? 1 : 0;
         }
-        const unsigned long long m = workgroup_min(key, L.gkey, &sc->min[t & 1]);
-        if (threadIdx.x == 0) sc->min[(t + 1) & 1] = NO_KEY;
-        unsigned long long g = m;
-        uint32_t owner = 0;
-        if (P.parts > 1) {
-            if (m != NO_KEY) stage_candidate<LANES>(P, t, D, la.x, pitch, (uint32_t)m - ibase);
-            gang_post<LANES>(P, t, m);
-            if (split && n + 1 < T) own_half(t + 1);
-            g = gang_wait<LANES>(P, t, sc, &owner);
-        }
-        if (g < L.gkey) {
-            L.gkey = g;
-            L.giter = t;
-            if (P.parts == 1) {
-                const uint32_t mi = (uint32_t)g - ibase;
-                for (int d = threadIdx.x; d < D; d += LANES) s_g[d] = la.x[(size_t)d * pitch + mi];
-            } else {
-                gather_gbest<LANES>(a, P, t, g, owner, s_g);
-            }
-        }
-        if (hist && threadIdx.x == 0) hist[t & (HIST_CAP - 1)] = L.gkey;
-        L.t = t;
-        L.stop = meets_tol(L.gkey, tol, fstar);
-        __syncthreads();
+        end_iteration(t, key, n);
     }
     return n_imp;
 }
