@@ -36,6 +36,7 @@ namespace pso {
 
 constexpr int BLOCK64 = 256;
 constexpr uint32_t NO_IDX = 0xFFFFFFFFu;
+constexpr uint32_t SPLIT64_MIN_P = 4; // fewest particles per workgroup of the split step
 
 static inline size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
 
@@ -48,8 +49,11 @@ Layout64 layout64_of(uint64_t N, int D)
     L.ctrl = o;     o += al256(sizeof(Ctrl64));
     L.gpos = o;     o += al256(sizeof(double) * D);
     L.shift = o;    o += al256(sizeof(double) * D);
-    L.slot_ord = o; o += al256(sizeof(unsigned long long) * 2 * L.nblocks);
-    L.slot_idx = o; o += al256(sizeof(uint32_t) * 2 * L.nblocks);
+    // one slot per workgroup of a grid step (the split step's may hold only
+    // SPLIT64_MIN_P particles each), two per gang workgroup
+    const uint64_t nslots = std::max<uint64_t>(2 * (uint64_t)L.nblocks, (N + SPLIT64_MIN_P - 1) / SPLIT64_MIN_P);
+    L.slot_ord = o; o += al256(sizeof(unsigned long long) * nslots);
+    L.slot_idx = o; o += al256(sizeof(uint32_t) * nslots);
     L.cand_pos = o; o += al256(sizeof(double) * 2 * L.nblocks * (size_t)D);
     L.pf = o;       o += al256(sizeof(double) * L.Np);
     L.pend = o;     o += al256(L.Np);
@@ -392,6 +396,159 @@ __global__ void __launch_bounds__(BLOCK64) k_step64(Swarm64Args a)
         }
     }
     wg_lexmin(k, ki, s_k, s_i);
+    if (post_and_arrive64(a, k, ki, &last)) finish64(a, t, false, s_k, s_i);
+}
+
+// ---------------------------------------------------------------------------
+// Grid step of a swarm too small to fill the GPU with one particle per lane
+// (N = 1024, D = 120 is four workgroups): P particles per workgroup, L =
+// 256 / P lanes per particle, lane k * P + j takes dimensions [k C, (k+1) C)
+// of particle j (C even: whole Philox pairs), so the P lanes of a chunk read
+// P consecutive doubles of a row.  Each lane stages its dimensions' fitness
+// terms in LDS ([word][d][j]); after a barrier lane j folds particle j's
+// terms in dimension order (the terms are the expressions Fitness64::add
+// evaluates, Rosenbrock's from the staged z), so the fitness is the same
+// sequential sum, bit for bit.  New pbest positions are left in x and
+// marked in pend, as in the wide step; the next iteration writes them to p.
+// ---------------------------------------------------------------------------
+template <int FIT>
+__host__ __device__ constexpr int split64_words() { return FIT == F_ACKLEY ? 2 : 1; }
+
+template <int FIT>
+__device__ __forceinline__ void split64_stage(double z, double *t0, double *t1)
+{
+    if constexpr (FIT == F_SPHERE) {
+        *t0 = z * z;
+    } else if constexpr (FIT == F_RASTRIGIN) {
+        *t0 = z * z - 10.0 * cospi64(2.0 * z);
+    } else if constexpr (FIT == F_ACKLEY) {
+        *t0 = z * z;
+        *t1 = cospi64(2.0 * z);
+    } else if constexpr (FIT == F_CUBIC) {
+        *t0 = z * z * z - 0.8 * z * z - 1000.0 * z + 8000.0;
+    } else {
+        *t0 = z; // Rosenbrock: the fold evaluates the terms
+    }
+}
+
+template <int FIT>
+__device__ __forceinline__ double split64_fold(const double *t0, const double *t1, uint32_t P, int D)
+{
+    Fitness64<FIT> fit;
+    int d = 0;
+    for (; d + 8 <= D; d += 8) {
+        double a0[8], a1[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            a0[u] = t0[(size_t)(d + u) * P];
+            if constexpr (split64_words<FIT>() == 2) a1[u] = t1[(size_t)(d + u) * P];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if constexpr (FIT == F_ROSENBROCK) {
+                fit.add(a0[u], d + u);
+            } else {
+                fit.acc = fit.acc + a0[u];
+                if constexpr (split64_words<FIT>() == 2) fit.aux = fit.aux + a1[u];
+            }
+        }
+    }
+    for (; d < D; ++d) {
+        if constexpr (FIT == F_ROSENBROCK) {
+            fit.add(t0[(size_t)d * P], d);
+        } else {
+            fit.acc = fit.acc + t0[(size_t)d * P];
+            if constexpr (split64_words<FIT>() == 2) fit.aux = fit.aux + t1[(size_t)d * P];
+        }
+    }
+    return fit.value(D);
+}
+
+template <int FIT>
+__global__ void __launch_bounds__(BLOCK64) k_step64s(Swarm64Args a, uint32_t P, uint32_t C)
+{
+    __shared__ unsigned long long s_k[BLOCK64 / 64];
+    __shared__ uint32_t s_i[BLOCK64 / 64];
+    __shared__ int last;
+    extern __shared__ double s_dyn64[]; // gbest position (D), shift (D), terms [word][D][P]
+    Ctrl64 *c = a.ctrl;
+    if (c->stop) return;
+    const int D = a.D;
+    const size_t Np = a.Np;
+    double *s_g = s_dyn64, *s_shift = s_dyn64 + D, *s_t0 = s_shift + D, *s_t1 = s_t0 + (size_t)D * P;
+    for (int d = threadIdx.x; d < D; d += BLOCK64) {
+        s_g[d] = a.gpos[d];
+        s_shift[d] = a.shift[d];
+    }
+    const uint32_t t = (uint32_t)(c->t + 1);
+    const unsigned long long pk = c->gord;
+    const uint32_t pi = c->gidx;
+    const uint32_t j = threadIdx.x % P, kc = threadIdx.x / P;
+    const uint32_t i = blockIdx.x * P + j;
+    const bool act = i < a.N;
+    const bool pend = act && a.pend[i] != 0;
+    const bool folder = act && kc == 0;
+    const double pf_old = folder ? a.pf[i] : 0.0;
+    const int d_begin = (int)(kc * C), d_end = min(D, (int)((kc + 1) * C));
+    // software pipeline over the chunk's dimension pairs: the next pair's
+    // rows are loaded before this pair's stores (the first pair's before
+    // the barrier that publishes the gbest position and shift)
+    double nx[2] = {0.0, 0.0}, nv[2] = {0.0, 0.0}, np[2] = {0.0, 0.0};
+    auto load_pair = [&](int d) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (d + h < d_end) {
+                const size_t e = (size_t)(d + h) * Np + i;
+                nx[h] = a.x[e];
+                nv[h] = a.v[e];
+                np[h] = pend ? nx[h] : a.p[e];
+            }
+        }
+    };
+    if (act) load_pair(d_begin);
+    __syncthreads();
+    if (act) {
+        for (int d = d_begin; d < d_end; d += 2) {
+            const double cx[2] = {nx[0], nx[1]}, cv[2] = {nv[0], nv[1]}, cp[2] = {np[0], np[1]};
+            if (d + 2 < d_end) load_pair(d + 2);
+            const U4 u = philox4x32_10(a.k0, a.k1, (uint32_t)d >> 1, i, t, TAG_VEL);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                if (d + h >= d_end) break;
+                const double r1 = (double)unit_float(h ? u.c : u.a), r2 = (double)unit_float(h ? u.d : u.b);
+                const size_t e = (size_t)(d + h) * Np + i;
+                const double x = cx[h], v = cv[h], p = cp[h];
+                // Eq. 1 left to right, clamp to [-vmax, vmax]; Eq. 2, clamp to [lo, hi]
+                double vn = a.w * v + a.c1 * r1 * (p - x) + a.c2 * r2 * (s_g[d + h] - x);
+                vn = clampd(vn, -a.vmax, a.vmax);
+                const double xn = clampd(x + vn, a.lo, a.hi);
+                a.x[e] = xn;
+                a.v[e] = vn;
+                if (pend) a.p[e] = p;
+                const size_t at = (size_t)(d + h) * P + j;
+                double w1 = 0.0;
+                split64_stage<FIT>(xn - s_shift[d + h], &s_t0[at], &w1);
+                if constexpr (split64_words<FIT>() == 2) s_t1[at] = w1;
+            }
+        }
+    }
+    __syncthreads();
+    unsigned long long k = ~0ull;
+    uint32_t ki = NO_IDX;
+    if (folder) {
+        const double f = split64_fold<FIT>(s_t0 + j, s_t1 + j, P, D);
+        const bool imp = f < pf_old; // strict; NaN never improves
+        if (imp) {
+            a.pf[i] = f;
+            const unsigned long long o = ord64(f);
+            if (o < pk || (o == pk && i < pi)) {
+                k = o;
+                ki = i;
+            }
+        }
+        a.pend[i] = imp ? 1 : 0;
+    }
+    wg_lexmin(k, ki, s_k, s_i); // its barriers order every lane's x stores before the release below
     if (post_and_arrive64(a, k, ki, &last)) finish64(a, t, false, s_k, s_i);
 }
 
@@ -860,6 +1017,45 @@ static bool step64_wide(const Swarm64Args &a)
     return a.N >= PSO64_WIDE_MIN_N;
 }
 
+// The split step (k_step64s) for N <= SPLIT64_MAX_N and D >= SPLIT64_MIN_D:
+// P = 64 particles per workgroup from N = 32768, else 32, halved (down to
+// 4) while fewer than 64 workgroups would run, and halved while the staged
+// terms exceed 63 KiB of LDS; C dimensions per lane.  Measured (Cubic, us
+// per iteration, split / one or two particles per lane): D = 120: N = 128
+// 9.4 / 38.1, 1024 12.9 / 50.5, 8192 20.6 / 61.6, 16384 29.7 / 60.9, 32768
+// 39.9 / 63.4, 65536 80.2 (P = 64) / 71.2; N = 2048, D = 32: 9.8 / 15.0;
+// N = 4096, D = 64: 13.3 / 31.2; at D = 16 the split loses (N = 8192: 12.4 /
+// 11.1; 30000: 28.2 / 15.0): a workgroup's fixed cost over too few updates.
+// PSO64_SPLIT=0 or 1 in the environment turns it off or on wherever the
+// terms of four particles fit (tests of both forms); PSO64_SPLIT_P sets P.
+#ifndef SPLIT64_MIN_D
+#define SPLIT64_MIN_D 32
+#endif
+#ifndef SPLIT64_MAX_N
+#define SPLIT64_MAX_N 32768
+#endif
+static bool split64_shape(const Swarm64Args &a, int words, uint32_t *P, uint32_t *C)
+{
+    const char *env = getenv("PSO64_SPLIT");
+    const bool forced = env && atoi(env) != 0;
+    if (env && !forced) return false;
+    if (!forced && (a.N > SPLIT64_MAX_N || a.D < SPLIT64_MIN_D)) return false;
+    const size_t lds_cap = 63 * 1024;
+    auto fits = [&](uint32_t p) { return sizeof(double) * (2 * (size_t)a.D + (size_t)words * a.D * p) <= lds_cap; };
+    uint32_t p = a.N >= 32768 ? 64 : 32;
+    while (p > SPLIT64_MIN_P && a.N / p < 64) p >>= 1;
+    if (const char *e = getenv("PSO64_SPLIT_P")) p = (uint32_t)atoi(e);
+    if (p < SPLIT64_MIN_P || p > (uint32_t)BLOCK64 || (p & (p - 1))) return false;
+    while (p > SPLIT64_MIN_P && !fits(p)) p >>= 1;
+    if (!fits(p)) return false;
+    const uint32_t L = BLOCK64 / p;
+    uint32_t c = ((uint32_t)a.D + L - 1) / L;
+    c += c & 1u;
+    *P = p;
+    *C = c;
+    return true;
+}
+
 #define PSO64_DISPATCH(FN, ...)                                                                                    \
     switch (fitness) {                                                                                             \
     case F_SPHERE: FN<F_SPHERE>(__VA_ARGS__); break;                                                               \
@@ -904,6 +1100,12 @@ template <int FIT>
 static void step64_f(const Swarm64Args &a, hipStream_t s)
 {
     const size_t lds = 2 * sizeof(double) * a.D;
+    uint32_t P = 0, C = 0;
+    if (split64_shape(a, split64_words<FIT>(), &P, &C)) {
+        const size_t lds_s = sizeof(double) * (2 * (size_t)a.D + (size_t)split64_words<FIT>() * a.D * P);
+        hipLaunchKernelGGL(k_step64s<FIT>, dim3((a.N + P - 1) / P), dim3(BLOCK64), lds_s, s, a, P, C);
+        return;
+    }
     if (!step64_wide(a)) {
         hipLaunchKernelGGL(k_step64<FIT>, grid64(a), dim3(BLOCK64), lds, s, a);
         return;

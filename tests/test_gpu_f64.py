@@ -102,20 +102,29 @@ def test_one_workgroup_run_in_lds_and_in_memory(monkeypatch, staged, fit, N, D, 
     assert_equal64(st, o)
 
 
-@pytest.mark.parametrize("wide", ["0", "1"])
+GRID_FORMS = {"narrow": dict(PSO64_WIDE="0", PSO64_SPLIT="0"), "wide": dict(PSO64_WIDE="1", PSO64_SPLIT="0"),
+              "split": dict(PSO64_SPLIT="1"), "split_p64": dict(PSO64_SPLIT="1", PSO64_SPLIT_P="64"),
+              "split_p16": dict(PSO64_SPLIT="1", PSO64_SPLIT_P="16")}
+
+
+@pytest.mark.parametrize("form", list(GRID_FORMS))
 @pytest.mark.parametrize("fit,N,D", [("sphere", 5001, 7), ("rosenbrock", 3001, 33), ("cubic", 2049, 1),
-                                     ("rosenbrock", 999, 2), ("sphere", 130, 64)])
-def test_wide_and_narrow_grid_steps_bit_for_bit(monkeypatch, wide, fit, N, D):
+                                     ("rosenbrock", 999, 2), ("sphere", 130, 64), ("cubic", 77, 120)])
+def test_grid_step_forms_bit_for_bit(monkeypatch, form, fit, N, D):
     """The grid step with one particle per lane (each new pbest position
-    written at once) and with two (16-byte accesses, new pbest positions
-    deferred into the next iteration's pass): step by step, then continued by
-    pso64_run on the path the shape takes (the one-workgroup and gang paths
-    first complete the deferred positions), both bit for bit against the
+    written at once), with two (16-byte accesses, new pbest positions
+    deferred into the next iteration's pass), and split (several lanes per
+    particle, each over a chunk of its dimensions, the fitness terms folded
+    in dimension order by one lane; pbest positions deferred; 4, 16 or 64
+    particles per workgroup, a ragged last one): step by step, then continued
+    by pso64_run on the path the shape takes (the one-workgroup and gang
+    paths first complete the deferred positions), bit for bit against the
     oracle's binary64 mode."""
-    monkeypatch.setenv("PSO64_WIDE", wide)
+    for k, v in GRID_FORMS[form].items():
+        monkeypatch.setenv(k, v)
     T1, T2 = 20, 25
     spec = wl.SwarmSpec(fit, N, D, T1 + T2, seed=3 * N + D, shift_amplitude=1.0)
-    announce(f"f64 wide={wide} {fit} N={N} D={D}")
+    announce(f"f64 grid form={form} {fit} N={N} D={D}")
     o = oracle_swarm(spec, 8).run_f64(T1 + T2)
     with gpu64(spec) as g:
         g.step(T1)
@@ -127,6 +136,32 @@ def test_wide_and_narrow_grid_steps_bit_for_bit(monkeypatch, wide, fit, N, D):
     assert np.array_equal(r["gbest_pos"].view(np.uint64), o["gpos"].view(np.uint64))
     assert st["gbest_idx"] == o["gbest_idx"]
     assert_equal64(st, o)
+
+
+@pytest.mark.parametrize("fit", ["rastrigin", "ackley"])
+def test_split_step_transcendental_close(monkeypatch, fit):
+    """Rastrigin and Ackley (device cos and exp) through the split step at a
+    shape of the paper's 120-dimensional rows: within 1e-12 relative of the
+    oracle's binary64 mode after one iteration, and the same state as the
+    one-particle-per-lane step after five (the same device functions)."""
+    spec = wl.SwarmSpec(fit, 300, 120, 5, seed=17, shift_amplitude=1.0)
+    announce(f"f64 split {fit} N=300 D=120")
+    o = oracle_swarm(spec, 8).run_f64(1)
+    states = {}
+    for form in ("split", "narrow"):
+        for k in ("PSO64_WIDE", "PSO64_SPLIT", "PSO64_SPLIT_P"):
+            monkeypatch.delenv(k, raising=False)
+        for k, v in GRID_FORMS[form].items():
+            monkeypatch.setenv(k, v)
+        with gpu64(spec) as g:
+            g.step(1)
+            one = g.state()
+            g.step(4)
+            states[form] = g.state()
+        if form == "split":
+            for key in ("x", "v", "pf"):
+                np.testing.assert_allclose(one[key], o[key], rtol=1e-12, atol=1e-300)
+    assert_equal64(states["split"], states["narrow"])
 
 
 def test_large_swarm_wide_step_bit_for_bit():
