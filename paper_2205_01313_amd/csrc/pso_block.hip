@@ -615,7 +615,11 @@ __device__ uint32_t staged_iterate(const SwarmArgs &a, const Staged &S, const Pa
     if (!split && npairs == 1) {
         // D <= 2: a lane takes its particles whole, the fitness summed in
         // registers (add(z, d) = stage then fold), then Step 4; no staged
-        // terms and no barrier between the update and the fold
+        // terms and no barrier between the update and the fold.  The clamp
+        // bounds live in vector registers for the whole run (a select
+        // between a lane value and a scalar operand costs a move).
+        SwarmArgs lv = la;
+        asm volatile("" : "+v"(lv.vmax), "+v"(lv.lo), "+v"(lv.hi));
         for (long long n = 0; n < T && !L.stop; ++n) {
             const uint32_t t = (uint32_t)(L.t + 1);
             unsigned long long key = NO_KEY;
@@ -631,8 +635,8 @@ __device__ uint32_t staged_iterate(const SwarmArgs &a, const Staged &S, const Pa
                     const float x = la.x[e], v = la.v[e];
                     const float p = pend ? x : la.p[e];
                     const float nv =
-                        velocity_eq1(la, x, v, p, s_g[d], unit_float(word_r1(u, d)), unit_float(word_r2(u, d)));
-                    const float xn = position_eq2(la, x, nv);
+                        velocity_eq1(lv, x, v, p, s_g[d], unit_float(word_r1(u, d)), unit_float(word_r2(u, d)));
+                    const float xn = position_eq2(lv, x, nv);
                     la.x[e] = xn;
                     la.v[e] = nv;
                     if (pend) la.p[e] = p;

@@ -727,6 +727,10 @@ __global__ void __launch_bounds__(LANES) k_block_run64s(Swarm64Args a, long long
     long long giter = c->giter, t = c->t;
     bool stop = c->stop != 0;
     const double tol = c->tol, fstar = c->fstar;
+    // the clamp bounds in vector registers for the whole run: a select
+    // between a lane value and a scalar operand costs a move per half
+    double vlo = -a.vmax, vhi = a.vmax, xlo = a.lo, xhi = a.hi;
+    asm volatile("" : "+v"(vlo), "+v"(vhi), "+v"(xlo), "+v"(xhi));
     __syncthreads();
     for (long long it = 0; it < T && !stop; ++it) {
         const uint32_t t1 = (uint32_t)(t + 1);
@@ -742,8 +746,8 @@ __global__ void __launch_bounds__(LANES) k_block_run64s(Swarm64Args a, long long
                     const double x = sx[e], v = sv[e], p = sp[e];
                     // Eq. 1 left to right, clamp to [-vmax, vmax]; Eq. 2, clamp to [lo, hi]
                     double vn = a.w * v + a.c1 * r1 * (p - x) + a.c2 * r2 * (s_g[d + h] - x);
-                    vn = clampd(vn, -a.vmax, a.vmax);
-                    const double xn = clampd(x + vn, a.lo, a.hi);
+                    vn = clampd(vn, vlo, vhi);
+                    const double xn = clampd(x + vn, xlo, xhi);
                     sx[e] = xn;
                     sv[e] = vn;
                     fit.add(xn - s_shift[d + h], d + h);
