@@ -546,8 +546,11 @@ __device__ __forceinline__ unsigned long long workgroup_min_sparse(unsigned long
 // iteration at which the stop rule (tol, fstar) holds (tested before the
 // first one too); a part of several meets the others every iteration.
 // hist (may be null) receives each iteration's gbest key.  Returns this
-// lane's pbest improvements.
-template <int FIT, int LANES>
+// lane's pbest improvements.  PAIR: swarms with D <= 2 take the loop that
+// runs a particle whole in one lane (the one-workgroup run; the batched
+// kernels, which hold every fitness function in one kernel, keep the
+// general loop and its register budget).
+template <int FIT, int LANES, bool PAIR = false>
 __device__ uint32_t staged_iterate(const SwarmArgs &a, const Staged &S, const Part &P, long long T, float tol,
                                    float fstar, float *s_g, const float *s_shift, Scratch *sc,
                                    unsigned long long *hist, SwarmLoop &L)
@@ -611,15 +614,15 @@ __device__ uint32_t staged_iterate(const SwarmArgs &a, const Staged &S, const Pa
         L.stop = meets_tol(L.gkey, tol, fstar);
         __syncthreads();
     };
+    // the clamp bounds in vector registers for the whole call (a select
+    // between a lane value and a scalar operand costs a move per use)
+    SwarmArgs lv = la;
+    asm volatile("" : "+v"(lv.vmax), "+v"(lv.lo), "+v"(lv.hi));
     L.stop = L.stop || meets_tol(L.gkey, tol, fstar);
-    if (!split && npairs == 1) {
+    if (PAIR && !split && npairs == 1) {
         // D <= 2: a lane takes its particles whole, the fitness summed in
         // registers (add(z, d) = stage then fold), then Step 4; no staged
-        // terms and no barrier between the update and the fold.  The clamp
-        // bounds live in vector registers for the whole run (a select
-        // between a lane value and a scalar operand costs a move).
-        SwarmArgs lv = la;
-        asm volatile("" : "+v"(lv.vmax), "+v"(lv.lo), "+v"(lv.hi));
+        // terms and no barrier between the update and the fold.
         for (long long n = 0; n < T && !L.stop; ++n) {
             const uint32_t t = (uint32_t)(L.t + 1);
             unsigned long long key = NO_KEY;
@@ -669,8 +672,8 @@ __device__ uint32_t staged_iterate(const SwarmArgs &a, const Staged &S, const Pa
                 const uint32_t d = gw.row;
                 const size_t e = (size_t)d * pitch + gw.col;
                 const float x = la.x[e];
-                const float nv = velocity_eq1_social(la, la.v[e], s_t0[e], x, s_g[d]);
-                const float xn = position_eq2(la, x, nv);
+                const float nv = velocity_eq1_social(lv, la.v[e], s_t0[e], x, s_g[d]);
+                const float xn = position_eq2(lv, x, nv);
                 la.x[e] = xn;
                 la.v[e] = nv;
                 float t0 = 0.0f, t1 = 0.0f;
@@ -692,8 +695,8 @@ __device__ uint32_t staged_iterate(const SwarmArgs &a, const Staged &S, const Pa
                     const float x = la.x[e], v = la.v[e];
                     const float p = pend ? x : la.p[e];
                     const float nv =
-                        velocity_eq1(la, x, v, p, s_g[d], unit_float(word_r1(u, h)), unit_float(word_r2(u, h)));
-                    const float xn = position_eq2(la, x, nv);
+                        velocity_eq1(lv, x, v, p, s_g[d], unit_float(word_r1(u, h)), unit_float(word_r2(u, h)));
+                    const float xn = position_eq2(lv, x, nv);
                     la.x[e] = xn;
                     la.v[e] = nv;
                     if (pend) la.p[e] = p;
@@ -823,7 +826,8 @@ __global__ void __launch_bounds__(LANES) k_block_run_staged(SwarmArgs a, long lo
     const float tol = c->tol, fstar = c->fstar;
     const Staged S = staged_view<FIT>(a, s_state, 0, (a.N + 3) / 4);
     staged_load<LANES>(a, S); // ends with a barrier (s_g, s_shift, sc too)
-    const uint32_t n_imp = staged_iterate<FIT, LANES>(a, S, whole_swarm(a), T, tol, fstar, s_g, s_shift, &sc, a.hist, L);
+    const uint32_t n_imp =
+        staged_iterate<FIT, LANES, true>(a, S, whole_swarm(a), T, tol, fstar, s_g, s_shift, &sc, a.hist, L);
     staged_store<LANES>(a, S);
     if (n_imp) atomicAdd(&c->improved, (unsigned long long)n_imp);
     for (int d = threadIdx.x; d < D; d += LANES) a.gpos[d] = s_g[d];
