@@ -65,7 +65,10 @@ struct Req {
     bool staged = false;      // runs in LDS-staged launches (else streamed ones)
 };
 
-constexpr int STREAMS = 2;
+#ifndef PSO_SERVER_STREAMS
+#define PSO_SERVER_STREAMS 2
+#endif
+constexpr int STREAMS = PSO_SERVER_STREAMS;
 // Time slice of a launch: every swarm runs as many iterations as fit in it
 // at its own measured speed (the device times each swarm's share of a
 // launch), so a launch lasts about the slice whatever its mix, and a small
@@ -77,13 +80,16 @@ constexpr int STREAMS = 2;
 // 127 / 377 and 235 / 481).
 constexpr double SLICE_US_DEFAULT = 2000.0;
 constexpr uint32_t FIRST_ITERS = 4;
-// Parts of one launch: at most this many per workgroup (a launch's swarms
-// are the longest-waiting ready ones).  Measured on the serving workload with
-// staged launches (p99 ms and requests/s at 10 000 and 50 000 requests/s):
-// 1: 227 / 4.7k, 397 / 4.5k; 2: 198 / 5.1k, 353 / 5.1k; 4: 156 / 5.8k,
-// 308 / 5.7k; 8: 155 / 6.1k, 292 / 6.0k; 16: 204 / 5.9k, 290 / 6.1k; no
-// limit: 295 / 5.1k, 451 / 4.1k.  PSO_SERVER_LAUNCH_WAVES overrides it.
-constexpr int LAUNCH_WAVES_DEFAULT = 8;
+// Parts of one launch: at most this many per workgroup of its grid (a
+// launch's swarms are the longest-waiting ready ones).  Measured on the
+// serving workload with staged launches of half the co-resident workgroups
+// (p99 ms and requests/s at 10 000 and 50 000 requests/s): 1: 227 / 4.7k,
+// 397 / 4.5k; 2: 198 / 5.1k, 353 / 5.1k; 4: 156 / 5.8k, 308 / 5.7k; 8:
+// 155 / 6.1k, 292 / 6.0k; 16: 204 / 5.9k, 290 / 6.1k; no limit: 295 /
+// 5.1k, 451 / 4.1k; with launches of every co-resident workgroup (below),
+// at 10 000 requests/s (p99 ms, requests/s): 2: 169 / 9.3k; 4: 165 / 9.4k;
+// 8: 223 / 9.4k; 16: 274 / 9.3k.  PSO_SERVER_LAUNCH_WAVES overrides it.
+constexpr int LAUNCH_WAVES_DEFAULT = 4;
 constexpr uint32_t MAX_SLICE_ITERS = 4096;
 constexpr int MAX_SERVER_D = 4096; // LDS of a launch is sized for the largest D it lists
 // LDS-staged launches: one 1024-lane workgroup per compute unit with 158 KiB
@@ -104,8 +110,9 @@ struct pso_server {
     size_t budget = 0;
     long long chunk = 1LL << 40; // at most this many particle-dimension updates per swarm and launch
     int max_slots = 0;
-    int grid_cap = 1;            // workgroups of a streamed launch
-    int grid_cap_staged = 0;     // workgroups of a staged launch (0: staging off)
+    int grid_cap = 1;            // parts of a streamed swarm at most: half the co-resident workgroups
+    int grid_cap_staged = 0;     // the same for a staged swarm (0: staging off)
+    int launch_cap_staged = 0;   // workgroups of a staged launch (a streamed one has grid_cap)
     double ticks_per_us = 100.0; // device wall clock
     double slice_us = SLICE_US_DEFAULT;
     int launch_waves = LAUNCH_WAVES_DEFAULT;
@@ -285,7 +292,7 @@ bool launch_ready(pso_server *s, int k)
     // the longest-waiting swarms of that kind, at most launch_waves parts per
     // workgroup, so that a launch lasts about that many slices and the two
     // streams take turns
-    const int grid_cap = staged ? s->grid_cap_staged : s->grid_cap;
+    const int grid_cap = staged ? s->launch_cap_staged : s->grid_cap;
     std::stable_sort(s->ready.begin(), s->ready.end(),
                      [&](int x, int y) { return s->slot_req[x]->t_submit < s->slot_req[y]->t_submit; });
     std::vector<int> sel, rest;
@@ -604,21 +611,35 @@ int pso_server_create(size_t mem_budget, int64_t chunk_updates, pso_server **out
         s->arena = pso::Arena(mem_budget);
         // at most one slot per 64 KiB of budget, within [64, 65536]
         s->max_slots = (int)std::min<size_t>(65536, std::max<size_t>(64, mem_budget / 65536));
-        // two launches may run at once: each gets half of the co-resident
-        // workgroups, so every launch's grid stays fully resident
+        // A multi-part swarm's parts meet every iteration, so they must all be
+        // resident at once: a swarm has at most half the co-resident
+        // workgroups as parts, and a streamed launch takes half of them.  A
+        // staged launch (one 1024-lane workgroup per compute unit, whatever
+        // its swarms) takes all of them (PSO_SERVER_GRID=half: half), so
+        // while one launch drains, the other's workgroups take the compute
+        // units it leaves (9.4k against 8.5k requests/s at 10 000/s).  Two
+        // staged launches cannot wait on each other: in a launch only the
+        // swarm whose parts are being dequeued can wait on workgroups not yet
+        // resident, and only while every resident workgroup of that launch
+        // holds one of its parts; both launches stuck needs more parts in the
+        // two swarms than there are compute units, but each has at most half.
         int capacity = 0;
         if (pso::batch_capacity(MAX_SERVER_D, pso::DEFAULT_BATCH_SHAPE.lanes, &capacity) != hipSuccess || capacity < 2) {
             server_free(s);
             return pso_internal_fail(PSO_EDEVICE, "device query failed");
         }
+        const char *genv = getenv("PSO_SERVER_GRID");
+        const int share = (genv && !strcmp(genv, "half")) ? STREAMS : 1;
         s->grid_cap = capacity / STREAMS;
         {
             const char *env = getenv("PSO_SERVER_STAGED");
             int cap_staged = 0;
             if (!(env && !strcmp(env, "0")) &&
                 pso::batch_capacity(SERVER_STAGE_MAX_D, SERVER_STAGE_LANES, &cap_staged, SERVER_STAGE_KIB) == hipSuccess &&
-                cap_staged >= STREAMS)
+                cap_staged >= STREAMS) {
                 s->grid_cap_staged = cap_staged / STREAMS;
+                s->launch_cap_staged = cap_staged / share;
+            }
         }
         {
             int dev = 0, khz = 0;
