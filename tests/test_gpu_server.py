@@ -43,14 +43,19 @@ def check_same(specs, tickets, res):
         assert np.array_equal(r["gbest_pos"], a["gbest_pos"]), sp
 
 
-@pytest.fixture(params=["staged", "streamed"])
+@pytest.fixture(params=["staged", "staged_half_grid", "streamed"])
 def server_mode(request, monkeypatch):
-    """Requests that fit run in LDS-staged launches by default; the other
-    mode streams every request (PSO_SERVER_STAGED=0)."""
+    """Requests that fit run in LDS-staged launches by default, each launch
+    over every co-resident workgroup; staged_half_grid gives each launch
+    half of them (PSO_SERVER_GRID=half); the last mode streams every
+    request (PSO_SERVER_STAGED=0)."""
+    monkeypatch.delenv("PSO_SERVER_GRID", raising=False)
     if request.param == "streamed":
         monkeypatch.setenv("PSO_SERVER_STAGED", "0")
     else:
         monkeypatch.delenv("PSO_SERVER_STAGED", raising=False)
+    if request.param == "staged_half_grid":
+        monkeypatch.setenv("PSO_SERVER_GRID", "half")
     return request.param
 
 
