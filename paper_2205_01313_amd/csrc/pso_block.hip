@@ -562,12 +562,16 @@ __device__ uint32_t staged_iterate(const SwarmArgs &a, const Staged &S, const Pa
     const uint32_t pitch = S.pitch, ibase = S.ibase;
     const uint32_t npairs = (uint32_t)(D + 1) / 2;
     uint32_t n_imp = 0;
-    // Without a stop rule every iteration of the launch runs, so a part of
-    // several can compute the gbest-independent half of the next iteration's
-    // Eq. 1 -- the Philox draws, (w v) + ((c1 r1)(p - x)) into v's slot and
-    // c2 r2 into the first term slot, the pending pbest positions copied --
-    // while the other parts arrive, and finish it once the gbest is known.
-    const bool split = P.parts > 1 && !(tol > 0.0f);
+    // A part of several computes the gbest-independent half of the next
+    // iteration's Eq. 1 -- the Philox draws, (w v) + ((c1 r1)(p - x)) into
+    // v's slot and c2 r2 into the first term slot, the pending pbest
+    // positions copied -- while the other parts arrive, and finishes it once
+    // the gbest is known.  With a stop rule the next iteration may not run:
+    // then v keeps that half-updated value, but a stopped swarm never runs
+    // again (a batch or server swarm only runs again after Step 1) and its
+    // results -- gbest value, index, iteration, position and iterations run
+    // -- do not read v.
+    const bool split = P.parts > 1;
     auto own_half = [&](uint32_t tn) {
         for (GridWalk<LANES> gw(pitch); gw.row < npairs; gw.next()) {
             const uint32_t pr = gw.row, sidx = gw.col;
