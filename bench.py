@@ -458,8 +458,13 @@ def serving_leg(pso, wl, rates=(2000, 10000, 50000), count=20000, budget=32 << 3
         warm = count // 10
         steady = np.array([lat_ms[t] for t in tickets[warm:] if t in lat_ms])
         q = (lambda f: float(np.percentile(steady, f))) if steady.size else (lambda f: None)
+        # a queue that grows through the run shows as a later half slower
+        # than the earlier one (requests in arrival order)
+        h = steady.size // 2
+        p99_halves = [float(np.percentile(x, 99)) if x.size else None for x in (steady[:h], steady[h:])]
         out[str(rate)] = dict(offered_per_s=rate, requests=count, warmup_requests=warm,
                               completed=int(st["completed"]), p50_ms=q(50), p99_ms=q(99),
+                              p99_first_half_ms=p99_halves[0], p99_second_half_ms=p99_halves[1],
                               max_ms=float(steady.max()) if steady.size else None,
                               all_requests_p50_ms=st["p50_ms"], all_requests_p99_ms=st["p99_ms"],
                               throughput_per_s=st["completed"] / wall, updates_per_s=upd / wall,
