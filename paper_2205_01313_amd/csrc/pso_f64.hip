@@ -1158,16 +1158,16 @@ static void block64_f(const Swarm64Args &a, long long T, hipStream_t s)
 
 // Particles per lane of the gang kernel: fewer, fuller workgroups make the
 // per-iteration meeting cheaper (measured, Cubic 1D, us per iteration at
-// 1/2/4/8 particles per lane: N = 4096: 5.0/4.9/5.9/8.3; 16384: 8.2/6.7/6.7/
-// 8.4; 65536: 20.2/12.8/10.1/10.2; 131072: 40.1/21.1/14.0/12.4).
-// PSO64_GANG_PPL overrides it.
+// 1/2/4/8 particles per lane: N = 4096: 5.0/4.9/5.9/8.3; 8192: 6.1/5.5/6.1/
+// 8.3; 16384: 8.2/6.8/6.8/8.5; 65536: 19.0/11.8/9.5/10.3; 131072: 40.1/21.1/
+// 14.0/12.4).  PSO64_GANG_PPL overrides it.
 static int gang_ppl(uint64_t N)
 {
     if (const char *env = getenv("PSO64_GANG_PPL")) {
         const int v = atoi(env);
         if (v >= 1 && v <= 64) return v;
     }
-    return N <= 4096 ? 2 : N <= 65536 ? 4 : 8;
+    return N <= 16384 ? 2 : N <= 65536 ? 4 : 8;
 }
 
 template <int FIT>
