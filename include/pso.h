@@ -213,12 +213,13 @@ int pso64_step(pso_swarm64 *s);
  * (tol <= 0: off; tested before the first and after every iteration);
  * blocks.  Outputs (each may be NULL, host): gbest fitness, position (D
  * doubles), iteration of the last gbest change, iterations run.  A swarm
- * whose x, v, p and pbest fitness fit one workgroup's LDS ((3D+1)*N
- * doubles, up to about 160 KiB) runs in one workgroup (one launch, the
- * state loaded once and stored back at the end); a larger one with D <= 8
- * runs as one persistent launch of co-resident workgroups that meet once
- * per iteration (same results); others launch one grid step per
- * iteration. */
+ * with D >= 32 and N <= 32768 launches one grid step per iteration (lanes
+ * share each particle's dimensions); else a swarm whose x, v, p and pbest
+ * fitness fit one workgroup's LDS ((3D+1)*N doubles, up to about 160 KiB)
+ * runs in one workgroup (one launch, the state loaded once and stored back
+ * at the end); a larger one with D <= 8 runs as one persistent launch of
+ * co-resident workgroups that meet once per iteration; others launch one
+ * grid step per iteration.  Every path gives the same results. */
 int pso64_run(pso_swarm64 *s, int64_t max_iter, double tol, double f_star, double *gbest_value, double *gbest_pos,
               int64_t *gbest_iter, int64_t *iters_done);
 

@@ -1217,6 +1217,12 @@ hipError_t launch64_step(int fitness, const Swarm64Args &a, hipStream_t stream)
 
 bool block64_staged_fits(const Swarm64Args &a) { return block64_staged_lds(a) > 0; }
 
+bool step64_split(int fitness, const Swarm64Args &a)
+{
+    uint32_t P = 0, C = 0;
+    return split64_shape(a, fitness == F_ACKLEY ? 2 : 1, &P, &C);
+}
+
 hipError_t launch64_block_run(int fitness, const Swarm64Args &a, long long T, hipStream_t stream)
 {
     PSO64_DISPATCH(block64_f, a, T, stream);
@@ -1258,10 +1264,15 @@ namespace {
         if (e_ != hipSuccess) return pso_internal_fail(PSO_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));      \
     } while (0)
 
-// Paths of pso64_run.  A swarm whose state fits the LDS of one workgroup
-// (x, v, p and pf: about 6 700 particle-dimensions) runs there in one launch;
-// else for D <= GANG64_MAX_D the persistent gang; else one grid launch per
-// iteration.  Measured (Cubic, us per iteration, one workgroup / gang or
+// Paths of pso64_run.  A swarm that the split grid step takes (D >= 32,
+// N <= 32768) runs one grid launch per iteration: its lanes share each
+// particle's dimensions, where one workgroup gives a lane a whole particle
+// (Cubic, us per iteration, grid / one workgroup: N = 32, D = 120: 8.8 /
+// 31.1; 64, 100: 8.8 / 24.5; 128, 40: 8.4 / 10.9; 192, 32: 8.6 / 8.9).
+// Else a swarm whose state fits the LDS of one workgroup (x, v, p and pf:
+// about 6 700 particle-dimensions) runs there in one launch (256, 24: 7.1
+// against 12.7 for the grid; 512, 8: 3.4 / 8.1); else for D <= GANG64_MAX_D
+// the persistent gang; else one grid launch per iteration.  Measured (Cubic, us per iteration, one workgroup / gang or
 // grid): N = 1024, D = 1: 1.28 / 4.7; 4096, 1: 3.41 / 4.88; 5000, 1:
 // 4.13 / 5.79; 1500, 4: 3.82 / 6.55; 768, 8: 4.33 / 9.32; 384, 16: 6.32 /
 // 10.0 (grid); 64, 100: 25.5 / 29.2 (grid).  Gang against grid (D = 1): N =
@@ -1402,7 +1413,9 @@ int pso64_run(pso_swarm64 *s, int64_t max_iter, double tol, double f_star, doubl
         const uint64_t nd = s->N * (uint64_t)s->D;
         const char *path = getenv("PSO64_PATH"); // tests of every path: block, gang, grid
         bool done_gang = false;
-        const bool block = path ? !strcmp(path, "block") : pso::block64_staged_fits(s->a) || nd <= BLOCK64_MAX_ND;
+        const bool block = path ? !strcmp(path, "block")
+                                : !pso::step64_split(s->fitness, s->a) &&
+                                      (pso::block64_staged_fits(s->a) || nd <= BLOCK64_MAX_ND);
         const bool gang = !block && (path ? !strcmp(path, "gang") : s->D <= GANG64_MAX_D);
         // those paths write each pbest position at once: complete the
         // pending ones a wide grid step left

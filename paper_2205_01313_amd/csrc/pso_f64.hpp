@@ -56,6 +56,8 @@ hipError_t launch64_step(int fitness, const Swarm64Args &a, hipStream_t stream);
 hipError_t launch64_block_run(int fitness, const Swarm64Args &a, long long T, hipStream_t stream);
 // The swarm's state fits the LDS of the one-workgroup run (and staging is on).
 bool block64_staged_fits(const Swarm64Args &a);
+// The grid step of the swarm is the split one (lanes share a particle).
+bool step64_split(int fitness, const Swarm64Args &a);
 hipError_t launch64_arm(const Swarm64Args &a, double tol, double fstar, hipStream_t stream);
 // Copies every pending pbest position (wide grid step) from x to p and
 // clears the marks: before the state is read or another path runs.
