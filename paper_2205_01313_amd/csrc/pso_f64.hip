@@ -690,6 +690,40 @@ __global__ void __launch_bounds__(BLOCK64) k_step64w(Swarm64Args a)
     if (post_and_arrive64(a, k, ki, &last)) finish64(a, t, false, s_k, s_i);
 }
 
+// Steps 2-4 of iteration t for particle i, column j of the state staged in
+// LDS as rows of nl doubles (x, v, p; pf at j): iterate_particle64's
+// arithmetic; returns the order bits of its new pbest fitness if it
+// improved (strictly), else ~0.  The clamp bounds come in vector registers.
+template <int FIT>
+__device__ __forceinline__ unsigned long long staged_particle64(const Swarm64Args &a, int D, uint32_t nl, uint32_t j,
+                                                               uint32_t i, uint32_t t, double *sx, double *sv,
+                                                               double *sp, double *spf, const double *s_g,
+                                                               const double *s_shift, double vlo, double vhi,
+                                                               double xlo, double xhi)
+{
+    Fitness64<FIT> fit;
+    for (int d = 0; d < D; d += 2) {
+        const U4 u = philox4x32_10(a.k0, a.k1, (uint32_t)d >> 1, i, t, TAG_VEL);
+        for (int h = 0; h < 2 && d + h < D; ++h) {
+            const double r1 = (double)unit_float(h ? u.c : u.a), r2 = (double)unit_float(h ? u.d : u.b);
+            const size_t e = (size_t)(d + h) * nl + j;
+            const double x = sx[e], v = sv[e], p = sp[e];
+            // Eq. 1 left to right, clamp to [-vmax, vmax]; Eq. 2, clamp to [lo, hi]
+            double vn = a.w * v + a.c1 * r1 * (p - x) + a.c2 * r2 * (s_g[d + h] - x);
+            vn = clampd(vn, vlo, vhi);
+            const double xn = clampd(x + vn, xlo, xhi);
+            sx[e] = xn;
+            sv[e] = vn;
+            fit.add(xn - s_shift[d + h], d + h);
+        }
+    }
+    const double f = fit.value(D);
+    if (!(f < spf[j])) return ~0ull; // strict; NaN never improves
+    spf[j] = f;
+    for (int d = 0; d < D; ++d) sp[(size_t)d * nl + j] = sx[(size_t)d * nl + j];
+    return ord64(f);
+}
+
 // ---------------------------------------------------------------------------
 // Up to T iterations of a small swarm in one workgroup with its whole state
 // in LDS: x, v, p as rows of N doubles, then pf, loaded once and stored back
@@ -737,29 +771,9 @@ __global__ void __launch_bounds__(LANES) k_block_run64s(Swarm64Args a, long long
         unsigned long long k = ~0ull;
         uint32_t ki = NO_IDX;
         for (uint32_t i = threadIdx.x; i < N; i += LANES) {
-            Fitness64<FIT> fit;
-            for (int d = 0; d < D; d += 2) {
-                const U4 u = philox4x32_10(a.k0, a.k1, (uint32_t)d >> 1, i, t1, TAG_VEL);
-                for (int h = 0; h < 2 && d + h < D; ++h) {
-                    const double r1 = (double)unit_float(h ? u.c : u.a), r2 = (double)unit_float(h ? u.d : u.b);
-                    const size_t e = (size_t)(d + h) * N + i;
-                    const double x = sx[e], v = sv[e], p = sp[e];
-                    // Eq. 1 left to right, clamp to [-vmax, vmax]; Eq. 2, clamp to [lo, hi]
-                    double vn = a.w * v + a.c1 * r1 * (p - x) + a.c2 * r2 * (s_g[d + h] - x);
-                    vn = clampd(vn, vlo, vhi);
-                    const double xn = clampd(x + vn, xlo, xhi);
-                    sx[e] = xn;
-                    sv[e] = vn;
-                    fit.add(xn - s_shift[d + h], d + h);
-                }
-            }
-            const double f = fit.value(D);
-            if (f < spf[i]) { // strict; NaN never improves
-                spf[i] = f;
-                for (int d = 0; d < D; ++d) sp[(size_t)d * N + i] = sx[(size_t)d * N + i];
-                const unsigned long long o = ord64(f);
-                if (o < gk || (o == gk && i < gi)) lexmin(k, ki, o, i);
-            }
+            const unsigned long long o =
+                staged_particle64<FIT>(a, D, N, i, i, t1, sx, sv, sp, spf, s_g, s_shift, vlo, vhi, xlo, xhi);
+            if (o < gk || (o == gk && i < gi)) lexmin(k, ki, o, i);
         }
         wg_lexmin_sparse<LANES>(k, ki, s_k, s_i); // its barrier follows every lane's LDS stores
         if (ki != NO_IDX) {
@@ -949,6 +963,133 @@ __global__ void __launch_bounds__(BLOCK64) k_gang64(Swarm64Args a, long long T, 
         stop = tol > 0.0 && fabs(ord64_value(gk) - fstar) < tol;
         __syncthreads();
     }
+    if (b == 0) {
+        for (int d = threadIdx.x; d < D; d += BLOCK64) a.gpos[d] = s_g[d];
+        if (threadIdx.x == 0) {
+            c->gord = gk;
+            c->gidx = gi;
+            c->giter = giter;
+            c->t = t;
+            c->stop = stop ? 1u : 0u;
+        }
+    }
+}
+
+// The gang with each workgroup's slice of the swarm (x, v, p as rows of
+// per_wg doubles, pf) in LDS for the whole run, loaded once and stored back
+// at the end.  An iteration then reads no state from device memory, and the
+// release that publishes a workgroup's slot writes back only the slot and
+// the staged candidate position, not the slice's x, v and p (the unstaged
+// gang dirties them in the L2 every iteration, and its acquire then makes
+// the next iteration's loads miss).  Same meeting and arithmetic as
+// k_gang64, so the same results.
+template <int FIT, bool ONE>
+__global__ void __launch_bounds__(BLOCK64) k_gang64s(Swarm64Args a, long long T, uint32_t per_wg)
+{
+    __shared__ unsigned long long s_k[BLOCK64 / 64];
+    __shared__ uint32_t s_i[BLOCK64 / 64];
+    __shared__ int s_fail;
+    extern __shared__ double s_dyn64[]; // gbest position (D), shift (D), x, v, p (D x per_wg each), pf (per_wg)
+    Ctrl64 *c = a.ctrl;
+    const int D = ONE ? 1 : a.D;
+    const uint32_t G = gridDim.x, b = blockIdx.x;
+    const uint32_t i_lo = b * per_wg, n_loc = min(a.N, i_lo + per_wg) - i_lo;
+    const size_t Np = a.Np, rows = (size_t)D * per_wg;
+    double *s_g = s_dyn64, *s_shift = s_g + D, *sx = s_shift + D, *sv = sx + rows, *sp = sv + rows, *spf = sp + rows;
+    for (int d = threadIdx.x; d < D; d += BLOCK64) {
+        s_g[d] = a.gpos[d];
+        s_shift[d] = a.shift[d];
+    }
+    for (size_t e = threadIdx.x; e < rows; e += BLOCK64) {
+        const size_t d = e / per_wg, j = e % per_wg;
+        if (j < n_loc) {
+            const size_t g = d * Np + i_lo + j;
+            sx[e] = a.x[g];
+            sv[e] = a.v[g];
+            sp[e] = a.p[g];
+        }
+    }
+    for (uint32_t j = threadIdx.x; j < n_loc; j += BLOCK64) spf[j] = a.pf[i_lo + j];
+    unsigned long long gk = c->gord;
+    uint32_t gi = c->gidx;
+    long long giter = c->giter, t = c->t;
+    bool stop = c->stop != 0;
+    const double tol = c->tol, fstar = c->fstar;
+    double vlo = -a.vmax, vhi = a.vmax, xlo = a.lo, xhi = a.hi;
+    asm volatile("" : "+v"(vlo), "+v"(vhi), "+v"(xlo), "+v"(xhi));
+    if (threadIdx.x == 0) s_fail = 0;
+    __syncthreads();
+    for (long long it = 0; it < T && !stop; ++it) {
+        const uint32_t t1 = (uint32_t)(t + 1);
+        const int par = (int)(it & 1);
+        unsigned long long k = ~0ull;
+        uint32_t ki = NO_IDX;
+        for (uint32_t j = threadIdx.x; j < n_loc; j += BLOCK64) {
+            const uint32_t i = i_lo + j;
+            const unsigned long long o =
+                staged_particle64<FIT>(a, D, per_wg, j, i, t1, sx, sv, sp, spf, s_g, s_shift, vlo, vhi, xlo, xhi);
+            if (o < gk || (o == gk && i < gi)) lexmin(k, ki, o, i);
+        }
+        wg_lexmin_sparse<BLOCK64>(k, ki, s_k, s_i); // its barrier follows every lane's LDS stores
+        double *mine = a.cand_pos + ((size_t)par * G + b) * D;
+        if (ki != NO_IDX)
+            for (int d = threadIdx.x; d < D; d += BLOCK64) mine[d] = sx[(size_t)d * per_wg + (ki - i_lo)];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            a.slot_ord[par * G + b] = k;
+            a.slot_idx[par * G + b] = ki;
+            __threadfence(); // release the slot and the staged position
+            atomicAdd(&c->gang_arrive, 1ull);
+            const unsigned long long target = (unsigned long long)G * (unsigned long long)(it + 1);
+            const unsigned long long w0 = wall_clock64();
+            while (__hip_atomic_load(&c->gang_arrive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                __builtin_amdgcn_s_sleep(1);
+                if (wall_clock64() - w0 > GANG64_WAIT_TICKS) {
+                    atomicOr(&c->err, 1u);
+                    s_fail = 1;
+                    break;
+                }
+            }
+            __threadfence(); // acquire every slot and staged position
+        }
+        __syncthreads();
+        if (s_fail) break; // uniform
+        // every workgroup reduces the same slots
+        unsigned long long rk = ~0ull;
+        uint32_t ri = NO_IDX;
+        for (uint32_t w = threadIdx.x; w < G; w += BLOCK64) {
+            const unsigned long long sk =
+                __hip_atomic_load(&a.slot_ord[par * G + w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t si = __hip_atomic_load(&a.slot_idx[par * G + w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (sk < rk || (sk == rk && si < ri)) {
+                rk = sk;
+                ri = si;
+            }
+        }
+        wg_lexmin(rk, ri, s_k, s_i);
+        if (ri != NO_IDX) {
+            const double *src = a.cand_pos + ((size_t)par * G + ri / per_wg) * D;
+            for (int d = threadIdx.x; d < D; d += BLOCK64)
+                s_g[d] = __hip_atomic_load(&src[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            gk = rk;
+            gi = ri;
+            giter = t1;
+        }
+        t = t1;
+        // every workgroup holds the same key, so all take the same decision
+        stop = tol > 0.0 && fabs(ord64_value(gk) - fstar) < tol;
+        __syncthreads();
+    }
+    for (size_t e = threadIdx.x; e < rows; e += BLOCK64) {
+        const size_t d = e / per_wg, j = e % per_wg;
+        if (j < n_loc) {
+            const size_t g = d * Np + i_lo + j;
+            a.x[g] = sx[e];
+            a.v[g] = sv[e];
+            a.p[g] = sp[e];
+        }
+    }
+    for (uint32_t j = threadIdx.x; j < n_loc; j += BLOCK64) a.pf[i_lo + j] = spf[j];
     if (b == 0) {
         for (int d = threadIdx.x; d < D; d += BLOCK64) a.gpos[d] = s_g[d];
         if (threadIdx.x == 0) {
@@ -1157,31 +1298,58 @@ static void block64_f(const Swarm64Args &a, long long T, hipStream_t s)
 }
 
 // Particles per lane of the gang kernel: fewer, fuller workgroups make the
-// per-iteration meeting cheaper (measured, Cubic 1D, us per iteration at
-// 1/2/4/8 particles per lane: N = 4096: 5.0/4.9/5.9/8.3; 8192: 6.1/5.5/6.1/
-// 8.3; 16384: 8.2/6.8/6.8/8.5; 65536: 19.0/11.8/9.5/10.3; 131072: 40.1/21.1/
-// 14.0/12.4).  PSO64_GANG_PPL overrides it.
+// per-iteration meeting cheaper (measured with the slices in LDS, Cubic 1D,
+// us per iteration at 1/2/4/8/16 particles per lane: N = 4096: 4.2/3.9/4.3/
+// 5.8/8.4; 8192: 5.2/4.6/4.6/5.8/8.6; 16384: 7.0/5.6/5.2/6.0/8.6; 65536:
+// 17.5/10.2/7.8/7.8/9.5; 131072: 37.9/18.1/12.2/9.7/10.7; in device memory
+// the same choices are within 2 % of the best).  PSO64_GANG_PPL overrides it.
 static int gang_ppl(uint64_t N)
 {
     if (const char *env = getenv("PSO64_GANG_PPL")) {
         const int v = atoi(env);
         if (v >= 1 && v <= 64) return v;
     }
-    return N <= 16384 ? 2 : N <= 65536 ? 4 : 8;
+    return N <= 8192 ? 2 : N <= 65536 ? 4 : 8;
 }
 
+// The gang with its slices in LDS (k_gang64s) where a slice fits
+// (PSO64_GANG_STAGED=0 in the environment: always k_gang64, for tests).
 template <int FIT>
 static hipError_t gang64_f(const Swarm64Args &a, long long T, hipStream_t s, bool *launched)
 {
-    const size_t lds = 2 * sizeof(double) * a.D;
-    int per_cu = 0, dev = 0, cus = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gang64<FIT>, BLOCK64, lds);
-    if (e != hipSuccess) return e;
-    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
-    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
-    const uint64_t cap = (uint64_t)std::max(1, per_cu * cus * 3 / 4); // co-resident with margin
-    uint64_t per_wg = BLOCK64 * (uint64_t)gang_ppl(a.N);              // particles per workgroup
+    const uint64_t per_wg = BLOCK64 * (uint64_t)gang_ppl(a.N); // particles per workgroup
     const uint64_t G = ((uint64_t)a.N + per_wg - 1) / per_wg;
+    int per_cu = 0, dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+    const char *env = getenv("PSO64_GANG_STAGED");
+    const size_t lds_s = sizeof(double) * (2 * (size_t)a.D + (3 * (size_t)a.D + 1) * per_wg);
+    if (!(env && !strcmp(env, "0")) && lds64_max() > 0 && lds_s + 1024 <= (size_t)lds64_max()) {
+        const bool one = a.D == 1;
+        const void *f = one ? reinterpret_cast<const void *>(k_gang64s<FIT, true>)
+                            : reinterpret_cast<const void *>(k_gang64s<FIT, false>);
+        // the most any swarm may ask for, so concurrent callers never lower it
+        if ((e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds64_max() - 1024)) !=
+            hipSuccess)
+            return e;
+        e = one ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gang64s<FIT, true>, BLOCK64, lds_s)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gang64s<FIT, false>, BLOCK64, lds_s);
+        if (e != hipSuccess) return e;
+        if (G <= (uint64_t)std::max(1, per_cu * cus * 3 / 4)) { // co-resident with margin
+            if (one)
+                hipLaunchKernelGGL((k_gang64s<FIT, true>), dim3((unsigned)G), dim3(BLOCK64), lds_s, s, a, T,
+                                   (uint32_t)per_wg);
+            else
+                hipLaunchKernelGGL((k_gang64s<FIT, false>), dim3((unsigned)G), dim3(BLOCK64), lds_s, s, a, T,
+                                   (uint32_t)per_wg);
+            *launched = true;
+            return hipGetLastError();
+        }
+    }
+    const size_t lds = 2 * sizeof(double) * a.D;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gang64<FIT>, BLOCK64, lds)) != hipSuccess) return e;
+    const uint64_t cap = (uint64_t)std::max(1, per_cu * cus * 3 / 4); // co-resident with margin
     if (G > cap) {
         *launched = false;
         return hipSuccess;

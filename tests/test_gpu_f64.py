@@ -56,10 +56,21 @@ def test_exact_functions_bit_for_bit(fit, N, D, how):
     assert_equal64(st, o)
 
 
-@pytest.mark.parametrize("path", ["block", "gang", "grid"])
-@pytest.mark.parametrize("fit,N,D", [("cubic", 2049, 1), ("rosenbrock", 1500, 6), ("sphere", 700, 3)])
+def set_path(monkeypatch, path):
+    """block, grid, gang (each workgroup's slice in LDS where it fits) or
+    gang_unstaged (the slices in device memory)."""
+    monkeypatch.setenv("PSO64_PATH", "gang" if path.startswith("gang") else path)
+    if path == "gang_unstaged":
+        monkeypatch.setenv("PSO64_GANG_STAGED", "0")
+    else:
+        monkeypatch.delenv("PSO64_GANG_STAGED", raising=False)
+
+
+@pytest.mark.parametrize("path", ["block", "gang", "gang_unstaged", "grid"])
+@pytest.mark.parametrize("fit,N,D", [("cubic", 2049, 1), ("rosenbrock", 1500, 6), ("sphere", 700, 3),
+                                     ("cubic", 20000, 1)])
 def test_every_run_path_bit_for_bit(monkeypatch, path, fit, N, D):
-    monkeypatch.setenv("PSO64_PATH", path)
+    set_path(monkeypatch, path)
     T = 60
     spec = wl.SwarmSpec(fit, N, D, T, seed=7 * N + D, shift_amplitude=1.5)
     announce(f"f64 path={path} {fit} N={N} D={D}")
@@ -179,9 +190,9 @@ def test_large_swarm_wide_step_bit_for_bit():
     assert_equal64(st, o)
 
 
-@pytest.mark.parametrize("path", ["block", "gang", "grid"])
+@pytest.mark.parametrize("path", ["block", "gang", "gang_unstaged", "grid"])
 def test_stop_rule_on_every_path(monkeypatch, path):
-    monkeypatch.setenv("PSO64_PATH", path)
+    set_path(monkeypatch, path)
     spec = wl.SwarmSpec("sphere", 3000, 3, 500, seed=4)
     announce(f"f64 stop rule path={path}")
     o = oracle_swarm(spec, 8).run_f64(500, tol=1e-2, f_star=0.0)
