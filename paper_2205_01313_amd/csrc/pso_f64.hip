@@ -692,14 +692,16 @@ __global__ void __launch_bounds__(BLOCK64) k_step64w(Swarm64Args a)
 
 // Steps 2-4 of iteration t for particle i, column j of the state staged in
 // LDS as rows of nl doubles (x, v, p; pf at j): iterate_particle64's
-// arithmetic; returns the order bits of its new pbest fitness if it
-// improved (strictly), else ~0.  The clamp bounds come in vector registers.
+// arithmetic.  A particle whose pbest improves (strictly) and whose key
+// (order bits, index) beats the gbest's (gk, gi) joins the lane's minimum
+// (k, ki); the test runs only in the improving lanes.  The clamp bounds come
+// in vector registers.
 template <int FIT>
-__device__ __forceinline__ unsigned long long staged_particle64(const Swarm64Args &a, int D, uint32_t nl, uint32_t j,
-                                                               uint32_t i, uint32_t t, double *sx, double *sv,
-                                                               double *sp, double *spf, const double *s_g,
-                                                               const double *s_shift, double vlo, double vhi,
-                                                               double xlo, double xhi)
+__device__ __forceinline__ void staged_particle64(const Swarm64Args &a, int D, uint32_t nl, uint32_t j, uint32_t i,
+                                                  uint32_t t, double *sx, double *sv, double *sp, double *spf,
+                                                  const double *s_g, const double *s_shift, double vlo, double vhi,
+                                                  double xlo, double xhi, unsigned long long gk, uint32_t gi,
+                                                  unsigned long long &k, uint32_t &ki)
 {
     Fitness64<FIT> fit;
     for (int d = 0; d < D; d += 2) {
@@ -718,10 +720,12 @@ __device__ __forceinline__ unsigned long long staged_particle64(const Swarm64Arg
         }
     }
     const double f = fit.value(D);
-    if (!(f < spf[j])) return ~0ull; // strict; NaN never improves
-    spf[j] = f;
-    for (int d = 0; d < D; ++d) sp[(size_t)d * nl + j] = sx[(size_t)d * nl + j];
-    return ord64(f);
+    if (f < spf[j]) { // strict; NaN never improves
+        spf[j] = f;
+        for (int d = 0; d < D; ++d) sp[(size_t)d * nl + j] = sx[(size_t)d * nl + j];
+        const unsigned long long o = ord64(f);
+        if (o < gk || (o == gk && i < gi)) lexmin(k, ki, o, i);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -770,11 +774,8 @@ __global__ void __launch_bounds__(LANES) k_block_run64s(Swarm64Args a, long long
         const uint32_t t1 = (uint32_t)(t + 1);
         unsigned long long k = ~0ull;
         uint32_t ki = NO_IDX;
-        for (uint32_t i = threadIdx.x; i < N; i += LANES) {
-            const unsigned long long o =
-                staged_particle64<FIT>(a, D, N, i, i, t1, sx, sv, sp, spf, s_g, s_shift, vlo, vhi, xlo, xhi);
-            if (o < gk || (o == gk && i < gi)) lexmin(k, ki, o, i);
-        }
+        for (uint32_t i = threadIdx.x; i < N; i += LANES)
+            staged_particle64<FIT>(a, D, N, i, i, t1, sx, sv, sp, spf, s_g, s_shift, vlo, vhi, xlo, xhi, gk, gi, k, ki);
         wg_lexmin_sparse<LANES>(k, ki, s_k, s_i); // its barrier follows every lane's LDS stores
         if (ki != NO_IDX) {
             gk = k;
@@ -1024,12 +1025,9 @@ __global__ void __launch_bounds__(BLOCK64) k_gang64s(Swarm64Args a, long long T,
         const int par = (int)(it & 1);
         unsigned long long k = ~0ull;
         uint32_t ki = NO_IDX;
-        for (uint32_t j = threadIdx.x; j < n_loc; j += BLOCK64) {
-            const uint32_t i = i_lo + j;
-            const unsigned long long o =
-                staged_particle64<FIT>(a, D, per_wg, j, i, t1, sx, sv, sp, spf, s_g, s_shift, vlo, vhi, xlo, xhi);
-            if (o < gk || (o == gk && i < gi)) lexmin(k, ki, o, i);
-        }
+        for (uint32_t j = threadIdx.x; j < n_loc; j += BLOCK64)
+            staged_particle64<FIT>(a, D, per_wg, j, i_lo + j, t1, sx, sv, sp, spf, s_g, s_shift, vlo, vhi, xlo, xhi,
+                                   gk, gi, k, ki);
         wg_lexmin_sparse<BLOCK64>(k, ki, s_k, s_i); // its barrier follows every lane's LDS stores
         double *mine = a.cand_pos + ((size_t)par * G + b) * D;
         if (ki != NO_IDX)
@@ -1312,21 +1310,26 @@ static int gang_ppl(uint64_t N)
     return N <= 8192 ? 2 : N <= 65536 ? 4 : 8;
 }
 
-// The gang with its slices in LDS (k_gang64s) where a slice fits
-// (PSO64_GANG_STAGED=0 in the environment: always k_gang64, for tests).
+// The gang with its slices in LDS (k_gang64s) where a slice fits, at the
+// particles per lane gang_ppl gives or half as many (D = 8, N = 16384: 9.7
+// us per iteration at 2 per lane in LDS, 15.4 at 4 in device memory); else
+// k_gang64 at gang_ppl's count (PSO64_GANG_STAGED=0 in the environment:
+// always k_gang64, for tests).
 template <int FIT>
 static hipError_t gang64_f(const Swarm64Args &a, long long T, hipStream_t s, bool *launched)
 {
-    const uint64_t per_wg = BLOCK64 * (uint64_t)gang_ppl(a.N); // particles per workgroup
-    const uint64_t G = ((uint64_t)a.N + per_wg - 1) / per_wg;
+    const int ppl0 = gang_ppl(a.N);
     int per_cu = 0, dev = 0, cus = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
     if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
     const char *env = getenv("PSO64_GANG_STAGED");
-    const size_t lds_s = sizeof(double) * (2 * (size_t)a.D + (3 * (size_t)a.D + 1) * per_wg);
-    if (!(env && !strcmp(env, "0")) && lds64_max() > 0 && lds_s + 1024 <= (size_t)lds64_max()) {
-        const bool one = a.D == 1;
+    const bool one = a.D == 1;
+    for (int ppl = ppl0; !(env && !strcmp(env, "0")) && lds64_max() > 0 && ppl >= std::max(1, ppl0 / 2); ppl /= 2) {
+        const uint64_t per_wg = BLOCK64 * (uint64_t)ppl; // particles per workgroup
+        const uint64_t G = ((uint64_t)a.N + per_wg - 1) / per_wg;
+        const size_t lds_s = sizeof(double) * (2 * (size_t)a.D + (3 * (size_t)a.D + 1) * per_wg);
+        if (lds_s + 1024 > (size_t)lds64_max()) continue;
         const void *f = one ? reinterpret_cast<const void *>(k_gang64s<FIT, true>)
                             : reinterpret_cast<const void *>(k_gang64s<FIT, false>);
         // the most any swarm may ask for, so concurrent callers never lower it
@@ -1336,17 +1339,18 @@ static hipError_t gang64_f(const Swarm64Args &a, long long T, hipStream_t s, boo
         e = one ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gang64s<FIT, true>, BLOCK64, lds_s)
                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gang64s<FIT, false>, BLOCK64, lds_s);
         if (e != hipSuccess) return e;
-        if (G <= (uint64_t)std::max(1, per_cu * cus * 3 / 4)) { // co-resident with margin
-            if (one)
-                hipLaunchKernelGGL((k_gang64s<FIT, true>), dim3((unsigned)G), dim3(BLOCK64), lds_s, s, a, T,
-                                   (uint32_t)per_wg);
-            else
-                hipLaunchKernelGGL((k_gang64s<FIT, false>), dim3((unsigned)G), dim3(BLOCK64), lds_s, s, a, T,
-                                   (uint32_t)per_wg);
-            *launched = true;
-            return hipGetLastError();
-        }
+        if (G > (uint64_t)std::max(1, per_cu * cus * 3 / 4)) continue; // co-resident with margin
+        if (one)
+            hipLaunchKernelGGL((k_gang64s<FIT, true>), dim3((unsigned)G), dim3(BLOCK64), lds_s, s, a, T,
+                               (uint32_t)per_wg);
+        else
+            hipLaunchKernelGGL((k_gang64s<FIT, false>), dim3((unsigned)G), dim3(BLOCK64), lds_s, s, a, T,
+                               (uint32_t)per_wg);
+        *launched = true;
+        return hipGetLastError();
     }
+    const uint64_t per_wg = BLOCK64 * (uint64_t)ppl0;
+    const uint64_t G = ((uint64_t)a.N + per_wg - 1) / per_wg;
     const size_t lds = 2 * sizeof(double) * a.D;
     if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gang64<FIT>, BLOCK64, lds)) != hipSuccess) return e;
     const uint64_t cap = (uint64_t)std::max(1, per_cu * cus * 3 / 4); // co-resident with margin
