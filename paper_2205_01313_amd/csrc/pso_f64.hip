@@ -50,11 +50,12 @@ Layout64 layout64_of(uint64_t N, int D)
     L.gpos = o;     o += al256(sizeof(double) * D);
     L.shift = o;    o += al256(sizeof(double) * D);
     // one slot per workgroup of a grid step (the split step's may hold only
-    // SPLIT64_MIN_P particles each), two per gang workgroup
-    const uint64_t nslots = std::max<uint64_t>(2 * (uint64_t)L.nblocks, (N + SPLIT64_MIN_P - 1) / SPLIT64_MIN_P);
+    // SPLIT64_MIN_P particles each), two per gang workgroup, six tagged
+    // words per staged-gang workgroup
+    const uint64_t nslots = std::max<uint64_t>(6 * (uint64_t)L.nblocks, (N + SPLIT64_MIN_P - 1) / SPLIT64_MIN_P);
     L.slot_ord = o; o += al256(sizeof(unsigned long long) * nslots);
     L.slot_idx = o; o += al256(sizeof(uint32_t) * nslots);
-    L.cand_pos = o; o += al256(sizeof(double) * 2 * L.nblocks * (size_t)D);
+    L.cand_pos = o; o += al256(sizeof(double) * 4 * L.nblocks * (size_t)D); // two parities; tagged words: two per double
     L.pf = o;       o += al256(sizeof(double) * L.Np);
     L.pend = o;     o += al256(L.Np);
     L.x = o;        o += al256(sizeof(double) * L.Np * (size_t)D);
@@ -877,6 +878,7 @@ __global__ void __launch_bounds__(LANES) k_block_run64(Swarm64Args a, long long 
 // wall clock and sets an error bit if it gives up.
 // ---------------------------------------------------------------------------
 constexpr unsigned long long GANG64_WAIT_TICKS = 2000000000ull; // 20 s of the 100 MHz wall clock
+constexpr uint32_t GANG64S_MAX_G = 256;                          // workgroups of a staged gang at most
 
 template <int FIT>
 __global__ void __launch_bounds__(BLOCK64) k_gang64(Swarm64Args a, long long T, uint32_t per_wg)
@@ -978,18 +980,26 @@ __global__ void __launch_bounds__(BLOCK64) k_gang64(Swarm64Args a, long long T, 
 
 // The gang with each workgroup's slice of the swarm (x, v, p as rows of
 // per_wg doubles, pf) in LDS for the whole run, loaded once and stored back
-// at the end.  An iteration then reads no state from device memory, and the
-// release that publishes a workgroup's slot writes back only the slot and
-// the staged candidate position, not the slice's x, v and p (the unstaged
-// gang dirties them in the L2 every iteration, and its acquire then makes
-// the next iteration's loads miss).  Same meeting and arithmetic as
-// k_gang64, so the same results.
+// at the end, so an iteration reads no state from device memory.  The
+// meeting uses no fences: every word a workgroup posts -- its key (order
+// bits in two words, index in one) and its candidate position (two words
+// per double) -- carries the iteration number in its high half and is
+// written and read with relaxed device-scope atomics, which are coherent
+// per word; a reader waits for each word it needs to carry the current
+// iteration.  (An agent-scope release and acquire write back and
+// invalidate the XCD's L2: 1.2-3 us of an iteration.)  Words of the other
+// parity cannot be overwritten early: a workgroup posts iteration t + 2
+// only after every workgroup has posted t + 1, after reading t.  The words
+// are cleared before each launch (a previous run's iteration numbers could
+// match).  Same arithmetic and choice of gbest as k_gang64, so the same
+// results.
 template <int FIT, bool ONE>
 __global__ void __launch_bounds__(BLOCK64) k_gang64s(Swarm64Args a, long long T, uint32_t per_wg)
 {
     __shared__ unsigned long long s_k[BLOCK64 / 64];
     __shared__ uint32_t s_i[BLOCK64 / 64];
     __shared__ int s_fail;
+    __shared__ uint32_t s_word[3 * GANG64S_MAX_G]; // payloads of the tagged words read in a meeting
     extern __shared__ double s_dyn64[]; // gbest position (D), shift (D), x, v, p (D x per_wg each), pf (per_wg)
     Ctrl64 *c = a.ctrl;
     const int D = ONE ? 1 : a.D;
@@ -1029,46 +1039,71 @@ __global__ void __launch_bounds__(BLOCK64) k_gang64s(Swarm64Args a, long long T,
             staged_particle64<FIT>(a, D, per_wg, j, i_lo + j, t1, sx, sv, sp, spf, s_g, s_shift, vlo, vhi, xlo, xhi,
                                    gk, gi, k, ki);
         wg_lexmin_sparse<BLOCK64>(k, ki, s_k, s_i); // its barrier follows every lane's LDS stores
-        double *mine = a.cand_pos + ((size_t)par * G + b) * D;
-        if (ki != NO_IDX)
-            for (int d = threadIdx.x; d < D; d += BLOCK64) mine[d] = sx[(size_t)d * per_wg + (ki - i_lo)];
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            a.slot_ord[par * G + b] = k;
-            a.slot_idx[par * G + b] = ki;
-            __threadfence(); // release the slot and the staged position
-            atomicAdd(&c->gang_arrive, 1ull);
-            const unsigned long long target = (unsigned long long)G * (unsigned long long)(it + 1);
-            const unsigned long long w0 = wall_clock64();
-            while (__hip_atomic_load(&c->gang_arrive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        // post: the key (order bits in two words, index in one) and the
+        // candidate position (two words per double), each word tagged with t1
+        const unsigned long long tag = (unsigned long long)t1 << 32;
+        unsigned long long *kw = a.slot_ord + (size_t)par * G * 3, *pw =
+            reinterpret_cast<unsigned long long *>(a.cand_pos) + (size_t)par * G * 2 * D;
+        if (threadIdx.x < 3) {
+            const uint32_t pay = threadIdx.x == 0 ? (uint32_t)k : threadIdx.x == 1 ? (uint32_t)(k >> 32) : ki;
+            __hip_atomic_store(&kw[(size_t)b * 3 + threadIdx.x], tag | pay, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else if (threadIdx.x < 3 + 2 * (uint32_t)D) {
+            const uint32_t w = threadIdx.x - 3;
+            const double v = ki != NO_IDX ? sx[(size_t)(w >> 1) * per_wg + (ki - i_lo)] : 0.0;
+            const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
+            const uint32_t pay = (w & 1) ? (uint32_t)(bits >> 32) : (uint32_t)bits;
+            __hip_atomic_store(&pw[(size_t)b * 2 * D + w], tag | pay, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        // every workgroup reads every key, each word once it carries t1
+        const unsigned long long w0 = wall_clock64();
+        for (uint32_t q = threadIdx.x; q < 3 * G; q += BLOCK64) {
+            unsigned long long v;
+            while (((v = __hip_atomic_load(&kw[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) >> 32) != t1) {
                 __builtin_amdgcn_s_sleep(1);
                 if (wall_clock64() - w0 > GANG64_WAIT_TICKS) {
-                    atomicOr(&c->err, 1u);
                     s_fail = 1;
                     break;
                 }
             }
-            __threadfence(); // acquire every slot and staged position
+            s_word[q] = (uint32_t)v;
         }
         __syncthreads();
-        if (s_fail) break; // uniform
-        // every workgroup reduces the same slots
+        if (s_fail) { // uniform
+            if (threadIdx.x == 0) atomicOr(&c->err, 1u);
+            break;
+        }
         unsigned long long rk = ~0ull;
         uint32_t ri = NO_IDX;
         for (uint32_t w = threadIdx.x; w < G; w += BLOCK64) {
-            const unsigned long long sk =
-                __hip_atomic_load(&a.slot_ord[par * G + w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const uint32_t si = __hip_atomic_load(&a.slot_idx[par * G + w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned long long sk = ((unsigned long long)s_word[3 * w + 1] << 32) | s_word[3 * w];
+            const uint32_t si = s_word[3 * w + 2];
             if (sk < rk || (sk == rk && si < ri)) {
                 rk = sk;
                 ri = si;
             }
         }
-        wg_lexmin(rk, ri, s_k, s_i);
+        wg_lexmin(rk, ri, s_k, s_i); // ends with a barrier: s_word is free again
         if (ri != NO_IDX) {
-            const double *src = a.cand_pos + ((size_t)par * G + ri / per_wg) * D;
+            // the winner's position, from its workgroup's tagged words
+            const unsigned long long *src = pw + (size_t)(ri / per_wg) * 2 * D;
+            for (uint32_t w = threadIdx.x; w < 2 * (uint32_t)D; w += BLOCK64) {
+                unsigned long long v;
+                while (((v = __hip_atomic_load(&src[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) >> 32) != t1) {
+                    __builtin_amdgcn_s_sleep(1);
+                    if (wall_clock64() - w0 > GANG64_WAIT_TICKS) {
+                        s_fail = 1;
+                        break;
+                    }
+                }
+                s_word[w] = (uint32_t)v;
+            }
+            __syncthreads();
+            if (s_fail) { // uniform
+                if (threadIdx.x == 0) atomicOr(&c->err, 1u);
+                break;
+            }
             for (int d = threadIdx.x; d < D; d += BLOCK64)
-                s_g[d] = __hip_atomic_load(&src[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                s_g[d] = __longlong_as_double((long long)(((unsigned long long)s_word[2 * d + 1] << 32) | s_word[2 * d]));
             gk = rk;
             gi = ri;
             giter = t1;
@@ -1098,6 +1133,12 @@ __global__ void __launch_bounds__(BLOCK64) k_gang64s(Swarm64Args a, long long T,
             c->stop = stop ? 1u : 0u;
         }
     }
+}
+
+// Zeroes n words (the staged gang's tagged slots before a launch).
+__global__ void k_zero64(unsigned long long *w, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) w[i] = 0;
 }
 
 // Clears the control block (a kernel, not a memset: the call may be
@@ -1329,17 +1370,22 @@ static hipError_t gang64_f(const Swarm64Args &a, long long T, hipStream_t s, boo
         const uint64_t per_wg = BLOCK64 * (uint64_t)ppl; // particles per workgroup
         const uint64_t G = ((uint64_t)a.N + per_wg - 1) / per_wg;
         const size_t lds_s = sizeof(double) * (2 * (size_t)a.D + (3 * (size_t)a.D + 1) * per_wg);
-        if (lds_s + 1024 > (size_t)lds64_max()) continue;
+        const size_t lds_static = sizeof(uint32_t) * 3 * GANG64S_MAX_G + 1024; // the kernel's own arrays, with room
+        if (lds_s + lds_static > (size_t)lds64_max()) continue;
         const void *f = one ? reinterpret_cast<const void *>(k_gang64s<FIT, true>)
                             : reinterpret_cast<const void *>(k_gang64s<FIT, false>);
         // the most any swarm may ask for, so concurrent callers never lower it
-        if ((e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds64_max() - 1024)) !=
-            hipSuccess)
+        if ((e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     lds64_max() - (int)lds_static)) != hipSuccess)
             return e;
         e = one ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gang64s<FIT, true>, BLOCK64, lds_s)
                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gang64s<FIT, false>, BLOCK64, lds_s);
         if (e != hipSuccess) return e;
-        if (G > (uint64_t)std::max(1, per_cu * cus * 3 / 4)) continue; // co-resident with margin
+        if (G > (uint64_t)std::max(1, per_cu * cus * 3 / 4) || G > GANG64S_MAX_G) continue; // co-resident with margin
+        // the tagged words of both parities: keys in slot_ord, positions in cand_pos
+        hipLaunchKernelGGL(k_zero64, dim3(4), dim3(256), 0, s, a.slot_ord, (size_t)6 * G);
+        hipLaunchKernelGGL(k_zero64, dim3(4), dim3(256), 0, s, reinterpret_cast<unsigned long long *>(a.cand_pos),
+                           (size_t)4 * G * a.D);
         if (one)
             hipLaunchKernelGGL((k_gang64s<FIT, true>), dim3((unsigned)G), dim3(BLOCK64), lds_s, s, a, T,
                                (uint32_t)per_wg);

@@ -28,9 +28,9 @@ struct Swarm64Args {
     double *x, *v, *p, *pf;        // D*Np, D*Np, D*Np, Np; element (d, i) at d*Np + i
     double *gpos;                  // D
     const double *shift;           // D
-    unsigned long long *slot_ord;  // one per grid workgroup (gang kernel: two per workgroup, by parity)
+    unsigned long long *slot_ord;  // one per grid workgroup (gang: two per workgroup by parity; staged gang: six tagged words)
     uint32_t *slot_idx;            // as slot_ord
-    double *cand_pos;              // gang kernel: [parity][workgroup][D] staged candidate positions
+    double *cand_pos;              // gang: [parity][workgroup][D] candidate positions (staged gang: tagged words)
     uint8_t *pend;                 // Np: 1 = pbest position of i is x, not yet in p (wide grid step)
     Ctrl64 *ctrl;
     uint32_t N, Np;
