@@ -217,9 +217,10 @@ int pso64_step(pso_swarm64 *s);
  * share each particle's dimensions); else a swarm whose x, v, p and pbest
  * fitness fit one workgroup's LDS ((3D+1)*N doubles, up to about 160 KiB)
  * runs in one workgroup (one launch, the state loaded once and stored back
- * at the end); a larger one with D <= 8 runs as one persistent launch of
- * co-resident workgroups that meet once per iteration; others launch one
- * grid step per iteration.  Every path gives the same results. */
+ * at the end), unless D <= 8 and N >= 4096; a swarm with D <= 8 that does
+ * not run there runs as one persistent launch of co-resident workgroups that
+ * meet once per iteration; others launch one grid step per iteration.
+ * Every path gives the same results. */
 int pso64_run(pso_swarm64 *s, int64_t max_iter, double tol, double f_star, double *gbest_value, double *gbest_pos,
               int64_t *gbest_iter, int64_t *iters_done);
 

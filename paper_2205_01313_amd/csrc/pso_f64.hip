@@ -1351,22 +1351,28 @@ static int gang_ppl(uint64_t N)
     return N <= 8192 ? 2 : N <= 65536 ? 4 : 8;
 }
 
-// The gang with its slices in LDS (k_gang64s) where a slice fits, at the
-// particles per lane gang_ppl gives or half as many (D = 8, N = 16384: 9.7
-// us per iteration at 2 per lane in LDS, 15.4 at 4 in device memory); else
-// k_gang64 at gang_ppl's count (PSO64_GANG_STAGED=0 in the environment:
-// always k_gang64, for tests).
+// The gang with its slices in LDS (k_gang64s) where a slice fits and the
+// workgroups are co-resident; else k_gang64 at gang_ppl's count
+// (PSO64_GANG_STAGED=0 in the environment: always k_gang64, for tests).
 template <int FIT>
 static hipError_t gang64_f(const Swarm64Args &a, long long T, hipStream_t s, bool *launched)
 {
     const int ppl0 = gang_ppl(a.N);
+    // staged: the fence-free meeting is cheap, so as many workgroups as the
+    // tagged words allow (Cubic 1D, us per iteration at 1/2/4/8 particles
+    // per lane: N = 4096: 3.0/3.1/3.5/4.6; 16384: 3.6/3.8/4.0/5.0; 65536:
+    // 4.3/4.3/4.7/5.7; 131072: -/4.8/5.0/5.9)
+    const char *penv = getenv("PSO64_GANG_PPL");
+    const int ppl_s = penv ? ppl0
+                           : (int)std::max<uint64_t>(1, ((uint64_t)a.N + (uint64_t)BLOCK64 * GANG64S_MAX_G - 1) /
+                                                             ((uint64_t)BLOCK64 * GANG64S_MAX_G));
     int per_cu = 0, dev = 0, cus = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
     if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
     const char *env = getenv("PSO64_GANG_STAGED");
     const bool one = a.D == 1;
-    for (int ppl = ppl0; !(env && !strcmp(env, "0")) && lds64_max() > 0 && ppl >= std::max(1, ppl0 / 2); ppl /= 2) {
+    for (int ppl = ppl_s; !(env && !strcmp(env, "0")) && lds64_max() > 0 && ppl >= std::max(1, ppl_s / 2); ppl /= 2) {
         const uint64_t per_wg = BLOCK64 * (uint64_t)ppl; // particles per workgroup
         const uint64_t G = ((uint64_t)a.N + per_wg - 1) / per_wg;
         const size_t lds_s = sizeof(double) * (2 * (size_t)a.D + (3 * (size_t)a.D + 1) * per_wg);
@@ -1482,24 +1488,25 @@ namespace {
         if (e_ != hipSuccess) return pso_internal_fail(PSO_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));      \
     } while (0)
 
-// Paths of pso64_run.  A swarm that the split grid step takes (D >= 32,
-// N <= 32768) runs one grid launch per iteration: its lanes share each
-// particle's dimensions, where one workgroup gives a lane a whole particle
-// (Cubic, us per iteration, grid / one workgroup: N = 32, D = 120: 8.8 /
-// 31.1; 64, 100: 8.8 / 24.5; 128, 40: 8.4 / 10.9; 192, 32: 8.6 / 8.9).
-// Else a swarm whose state fits the LDS of one workgroup (x, v, p and pf:
-// about 6 700 particle-dimensions) runs there in one launch (256, 24: 7.1
-// against 12.7 for the grid; 512, 8: 3.4 / 8.1); else for D <= GANG64_MAX_D
-// the persistent gang; else one grid launch per iteration.  Measured (Cubic, us per iteration, one workgroup / gang or
-// grid): N = 1024, D = 1: 1.28 / 4.7; 4096, 1: 3.41 / 4.88; 5000, 1:
-// 4.13 / 5.79; 1500, 4: 3.82 / 6.55; 768, 8: 4.33 / 9.32; 384, 16: 6.32 /
-// 10.0 (grid); 64, 100: 25.5 / 29.2 (grid).  Gang against grid (D = 1): N =
-// 16384: 6.7 / 7.4; 131072: 12.4 / 15.7; at D = 120 within 2 % (N = 8192),
-// so the grid runs.  PSO64_PATH (block, gang, grid) overrides the choice
-// (tests of every path); with PSO64_BLOCK_STAGED=0 the one-workgroup run
-// keeps the state in device memory and takes up to BLOCK64_MAX_ND.
+// Paths of pso64_run (Cubic, us per iteration).  A swarm that the split grid
+// step takes (D >= 32, N <= 32768) runs one grid launch per iteration: its
+// lanes share each particle's dimensions, where one workgroup gives a lane a
+// whole particle (grid / one workgroup: N = 32, D = 120: 8.8 / 31.1; 64,
+// 100: 8.8 / 24.5; 128, 40: 8.4 / 10.9; 192, 32: 8.6 / 8.9).  Else a swarm
+// whose state fits the LDS of one workgroup (x, v, p and pf: about 6 700
+// particle-dimensions) runs there in one launch (256, 24: 7.1 against 12.7
+// for the grid; 512, 8: 3.3 against 4.6 for the gang) unless the gang takes
+// it (D <= GANG64_MAX_D and N >= GANG64_MIN_N; one workgroup / gang at D =
+// 1: N = 3000: 2.55 / 2.82; 4096: 3.21 / 2.87; 5000: 3.86 / 3.03); else for
+// D <= GANG64_MAX_D the persistent gang (N = 16384: 3.4; 131072: 4.7;
+// D = 8, N = 16384: 5.7); else one grid launch per iteration (at D = 120
+// the unstaged gang and the grid were within 2 % at N = 8192).  PSO64_PATH
+// (block, gang, grid) overrides the choice (tests of every path); with
+// PSO64_BLOCK_STAGED=0 the one-workgroup run keeps the state in device
+// memory and takes up to BLOCK64_MAX_ND.
 constexpr uint64_t BLOCK64_MAX_ND = 2048;
 constexpr int GANG64_MAX_D = 8;
+constexpr uint32_t GANG64_MIN_N = 4096; // from here the gang beats one workgroup (D = 1, N = 4096: 2.9 / 3.2 us)
 
 void free64(pso_swarm64 *s)
 {
@@ -1633,6 +1640,7 @@ int pso64_run(pso_swarm64 *s, int64_t max_iter, double tol, double f_star, doubl
         bool done_gang = false;
         const bool block = path ? !strcmp(path, "block")
                                 : !pso::step64_split(s->fitness, s->a) &&
+                                      !(s->D <= GANG64_MAX_D && s->N >= GANG64_MIN_N) &&
                                       (pso::block64_staged_fits(s->a) || nd <= BLOCK64_MAX_ND);
         const bool gang = !block && (path ? !strcmp(path, "gang") : s->D <= GANG64_MAX_D);
         // those paths write each pbest position at once: complete the
