@@ -219,8 +219,9 @@ int pso64_step(pso_swarm64 *s);
  * runs in one workgroup (one launch, the state loaded once and stored back
  * at the end), unless D <= 8 and N >= 4096; a swarm with D <= 8 that does
  * not run there runs as one persistent launch of co-resident workgroups that
- * meet once per iteration; others launch one grid step per iteration.
- * Every path gives the same results. */
+ * meet once per iteration, as does one with D < 32 whose workgroups can hold
+ * their slices of the swarm in LDS; others launch one grid step per
+ * iteration.  Every path gives the same results. */
 int pso64_run(pso_swarm64 *s, int64_t max_iter, double tol, double f_star, double *gbest_value, double *gbest_pos,
               int64_t *gbest_iter, int64_t *iters_done);
 

@@ -1355,7 +1355,7 @@ static int gang_ppl(uint64_t N)
 // workgroups are co-resident; else k_gang64 at gang_ppl's count
 // (PSO64_GANG_STAGED=0 in the environment: always k_gang64, for tests).
 template <int FIT>
-static hipError_t gang64_f(const Swarm64Args &a, long long T, hipStream_t s, bool *launched)
+static hipError_t gang64_f(const Swarm64Args &a, long long T, hipStream_t s, bool *launched, bool staged_only)
 {
     const int ppl0 = gang_ppl(a.N);
     // staged: the fence-free meeting is cheap, so as many workgroups as the
@@ -1401,6 +1401,10 @@ static hipError_t gang64_f(const Swarm64Args &a, long long T, hipStream_t s, boo
         *launched = true;
         return hipGetLastError();
     }
+    if (staged_only) {
+        *launched = false;
+        return hipSuccess;
+    }
     const uint64_t per_wg = BLOCK64 * (uint64_t)ppl0;
     const uint64_t G = ((uint64_t)a.N + per_wg - 1) / per_wg;
     const size_t lds = 2 * sizeof(double) * a.D;
@@ -1415,14 +1419,15 @@ static hipError_t gang64_f(const Swarm64Args &a, long long T, hipStream_t s, boo
     return hipGetLastError();
 }
 
-hipError_t launch64_gang(int fitness, const Swarm64Args &a, long long T, hipStream_t stream, bool *launched)
+hipError_t launch64_gang(int fitness, const Swarm64Args &a, long long T, hipStream_t stream, bool *launched,
+                         bool staged_only)
 {
     switch (fitness) {
-    case F_SPHERE: return gang64_f<F_SPHERE>(a, T, stream, launched);
-    case F_RASTRIGIN: return gang64_f<F_RASTRIGIN>(a, T, stream, launched);
-    case F_ROSENBROCK: return gang64_f<F_ROSENBROCK>(a, T, stream, launched);
-    case F_ACKLEY: return gang64_f<F_ACKLEY>(a, T, stream, launched);
-    case F_CUBIC: return gang64_f<F_CUBIC>(a, T, stream, launched);
+    case F_SPHERE: return gang64_f<F_SPHERE>(a, T, stream, launched, staged_only);
+    case F_RASTRIGIN: return gang64_f<F_RASTRIGIN>(a, T, stream, launched, staged_only);
+    case F_ROSENBROCK: return gang64_f<F_ROSENBROCK>(a, T, stream, launched, staged_only);
+    case F_ACKLEY: return gang64_f<F_ACKLEY>(a, T, stream, launched, staged_only);
+    case F_CUBIC: return gang64_f<F_CUBIC>(a, T, stream, launched, staged_only);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1506,6 +1511,11 @@ namespace {
 // memory and takes up to BLOCK64_MAX_ND.
 constexpr uint64_t BLOCK64_MAX_ND = 2048;
 constexpr int GANG64_MAX_D = 8;
+// with its slices in LDS the gang also beats the grid up to D = 31 (staged
+// gang / grid: N = 4096, D = 12: 6.1 / 9.3; 16384, 16: 7.9 / 14.0; 16384,
+// 24: 9.7 / 17.5); where the slices do not fit or co-reside (N = 65536, D =
+// 16: 29.6 in device memory against 17.2) the grid runs
+constexpr int GANG64_STAGED_MAX_D = 32;
 constexpr uint32_t GANG64_MIN_N = 4096; // from here the gang beats one workgroup (D = 1, N = 4096: 2.9 / 3.2 us)
 
 void free64(pso_swarm64 *s)
@@ -1642,7 +1652,9 @@ int pso64_run(pso_swarm64 *s, int64_t max_iter, double tol, double f_star, doubl
                                 : !pso::step64_split(s->fitness, s->a) &&
                                       !(s->D <= GANG64_MAX_D && s->N >= GANG64_MIN_N) &&
                                       (pso::block64_staged_fits(s->a) || nd <= BLOCK64_MAX_ND);
-        const bool gang = !block && (path ? !strcmp(path, "gang") : s->D <= GANG64_MAX_D);
+        // 8 < D < 32: the gang only with its slices in LDS, else the grid
+        const bool gang_staged_only = !path && s->D > GANG64_MAX_D;
+        const bool gang = !block && (path ? !strcmp(path, "gang") : s->D < GANG64_STAGED_MAX_D);
         // those paths write each pbest position at once: complete the
         // pending ones a wide grid step left
         if (block || gang) HIP64_TRY(pso::launch64_flush(s->a, s->stream));
@@ -1651,7 +1663,7 @@ int pso64_run(pso_swarm64 *s, int64_t max_iter, double tol, double f_star, doubl
             done_gang = true;
         } else if (gang) {
             HIP64_TRY(hipMemsetAsync(&s->a.ctrl->gang_arrive, 0, sizeof(unsigned long long), s->stream));
-            HIP64_TRY(pso::launch64_gang(s->fitness, s->a, max_iter, s->stream, &done_gang));
+            HIP64_TRY(pso::launch64_gang(s->fitness, s->a, max_iter, s->stream, &done_gang, gang_staged_only));
         }
         if (!done_gang) {
             // chunks of launches; every launch returns at once after the stop rule holds

@@ -69,6 +69,8 @@ hipError_t launch64_eval(int fitness, const Swarm64Args &a, const double *pts, u
 // once per iteration (bit-identical to T grid steps); ctrl->gang_arrive must
 // be zero.  *launched = false if the swarm needs more workgroups than can be
 // co-resident (nothing is enqueued then).
-hipError_t launch64_gang(int fitness, const Swarm64Args &a, long long T, hipStream_t stream, bool *launched);
+// staged_only: launch only the gang with its slices in LDS (*launched false otherwise).
+hipError_t launch64_gang(int fitness, const Swarm64Args &a, long long T, hipStream_t stream, bool *launched,
+                         bool staged_only = false);
 
 } // namespace pso
