@@ -85,58 +85,81 @@ struct Scratch {
 
 constexpr unsigned long long GANG_WAIT_TICKS = 2000000000ull; // 20 s of the 100 MHz wall clock
 
+// The parts of a swarm meet without fences: every word a part posts for step
+// tau -- its minimum key as two words (low and high half), its candidate's
+// coordinates one word each -- carries tau + 1 in its high half and moves by
+// relaxed device-scope atomics, which are coherent per word; a reader waits
+// for each word it needs to carry the step's tag.  (An agent-scope release
+// and acquire write back and invalidate the XCD's L2, microseconds a step.)
+// Words of the other parity cannot be overwritten early: a part posts step
+// tau + 2 only after every part has posted tau + 1, after reading tau.  The
+// words are zeroed when the swarm starts (batch reset, server upload), since
+// another swarm's earlier steps could carry the same tags.  Without fences
+// no other memory may pass between parts within a launch: each part
+// initialises and iterates its own particles only.
+__device__ __forceinline__ unsigned long long gang_tag(long long tau)
+{
+    return (unsigned long long)(uint32_t)(tau + 1) << 32;
+}
+
+// Waits until *w carries tag; its payload (0 and sc->err set after the
+// bound).
+__device__ __forceinline__ uint32_t gang_read(const unsigned long long *w, unsigned long long tag, Scratch *sc,
+                                              unsigned long long t0)
+{
+    unsigned long long v;
+    while (((v = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) & 0xFFFFFFFF00000000ull) != tag) {
+        __builtin_amdgcn_s_sleep(1);
+        if (wall_clock64() - t0 > GANG_WAIT_TICKS) {
+            sc->err = 1u;
+            return 0u;
+        }
+    }
+    return (uint32_t)v;
+}
+
 // Posts this part's candidate position for step tau: the D coordinates of
 // memory column mi of row-major state x (row pitch `pitch`).
 template <int LANES>
 __device__ __forceinline__ void stage_candidate(const Part &P, long long tau, int D, const float *x, size_t pitch,
                                                 uint32_t mi)
 {
-    float *dst = P.cand_pos + ((size_t)(tau & 1) * P.parts + P.part) * D;
-    for (int d = threadIdx.x; d < D; d += LANES) dst[d] = x[(size_t)d * pitch + mi];
+    unsigned long long *dst =
+        reinterpret_cast<unsigned long long *>(P.cand_pos) + ((size_t)(tau & 1) * P.parts + P.part) * D;
+    const unsigned long long tag = gang_tag(tau);
+    for (int d = threadIdx.x; d < D; d += LANES)
+        __hip_atomic_store(&dst[d], tag | __float_as_uint(x[(size_t)d * pitch + mi]), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Combining the workgroup minima of step tau over the swarm's parts, in two
 // halves so that a caller can work between them.  gang_post publishes this
-// part's minimum m (its candidate position already posted if m != NO_KEY)
-// and arrives; gang_wait waits for every part and returns the swarm minimum,
-// with *owner the part that posted it (its position is in cand_pos).  One
-// lane arrives and waits; the first wavefront then reads the parts' keys in
-// parallel.
+// part's minimum m (its candidate position already posted if m != NO_KEY);
+// gang_wait waits for every part's key and returns the swarm minimum, with
+// *owner the part that posted it (its position is in cand_pos).  The first
+// wavefront reads the parts' keys in parallel.
 template <int LANES>
 __device__ __forceinline__ void gang_post(const Part &P, long long tau, unsigned long long m)
 {
-    if (threadIdx.x == 0) P.cand_key[(size_t)(tau & 1) * P.parts + P.part] = m;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        // release the candidate before arriving: the barrier orders every
-        // lane's stores before this one fence
-        __threadfence();
-        atomicAdd(&P.gang->arrive, 1ull);
+    if (threadIdx.x < 2) {
+        unsigned long long *kw = P.cand_key + ((size_t)(tau & 1) * P.parts + P.part) * 2;
+        const uint32_t pay = threadIdx.x ? (uint32_t)(m >> 32) : (uint32_t)m;
+        __hip_atomic_store(&kw[threadIdx.x], gang_tag(tau) | pay, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    __syncthreads();
 }
 
 template <int LANES>
 __device__ unsigned long long gang_wait(const Part &P, long long tau, Scratch *sc, uint32_t *owner)
 {
-    const int b = (int)(tau & 1);
     if (threadIdx.x < 64) {
-        if (threadIdx.x == 0) {
-            const unsigned long long target = (unsigned long long)P.parts * (unsigned long long)(tau + 1);
-            const unsigned long long t0 = wall_clock64();
-            while (__hip_atomic_load(&P.gang->arrive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-                __builtin_amdgcn_s_sleep(4);
-                if (wall_clock64() - t0 > GANG_WAIT_TICKS) {
-                    sc->err = 1u;
-                    break;
-                }
-            }
-        }
-        __threadfence(); // acquire every part's candidate
+        const unsigned long long tag = gang_tag(tau), t0 = wall_clock64();
+        const unsigned long long *kw = P.cand_key + (size_t)(tau & 1) * P.parts * 2;
         unsigned long long g = NO_KEY;
         uint32_t o = 0;
         for (uint32_t p = threadIdx.x; p < P.parts; p += 64) {
-            const unsigned long long k = __hip_atomic_load(&P.cand_key[(size_t)b * P.parts + p], __ATOMIC_RELAXED,
-                                                           __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t lo = gang_read(&kw[2 * p], tag, sc, t0), hi = gang_read(&kw[2 * p + 1], tag, sc, t0);
+            const unsigned long long k = ((unsigned long long)hi << 32) | lo;
             if (k < g) {
                 g = k;
                 o = p;
@@ -179,19 +202,21 @@ __device__ unsigned long long gang_min(const SwarmArgs &a, const Part &P, long l
 }
 
 // gbest position <- the particle of key k: from x (one part: stored by this
-// workgroup before the last barrier) or from the owner part's staged copy.
+// workgroup before the last barrier) or from the owner part's posted copy.
 template <int LANES>
 __device__ __forceinline__ void gather_gbest(const SwarmArgs &a, const Part &P, long long tau, unsigned long long k,
-                                             uint32_t owner, float *s_g)
+                                             uint32_t owner, float *s_g, Scratch *sc)
 {
     const int D = a.D;
+    if (k == NO_KEY) return; // no part had a candidate: nothing was posted
     if (P.parts == 1) {
         const size_t gi = (uint32_t)k;
         for (int d = threadIdx.x; d < D; d += LANES) s_g[d] = a.x[(size_t)d * a.Np + gi];
     } else {
-        const float *src = P.cand_pos + ((size_t)(tau & 1) * P.parts + owner) * D;
-        for (int d = threadIdx.x; d < D; d += LANES)
-            s_g[d] = __hip_atomic_load(&src[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long *src =
+            reinterpret_cast<const unsigned long long *>(P.cand_pos) + ((size_t)(tau & 1) * P.parts + owner) * D;
+        const unsigned long long tag = gang_tag(tau), t0 = wall_clock64();
+        for (int d = threadIdx.x; d < D; d += LANES) s_g[d] = __uint_as_float(gang_read(&src[d], tag, sc, t0));
     }
 }
 
@@ -210,7 +235,7 @@ __device__ void block_init(const SwarmArgs &a, const Part &P, const float *s_shi
     if (threadIdx.x == 0) sc->min[1] = NO_KEY;
     uint32_t owner;
     const unsigned long long g = gang_min<LANES>(a, P, 0, m, sc, &owner);
-    gather_gbest<LANES>(a, P, 0, g, owner, s_g);
+    gather_gbest<LANES>(a, P, 0, g, owner, s_g, sc);
     L.gkey = g;
     L.giter = 0;
     L.t = 0;
@@ -245,7 +270,7 @@ __device__ void block_iterate(const SwarmArgs &a, const Part &P, long long T, fl
         if (g < L.gkey) {
             L.gkey = g;
             L.giter = t;
-            gather_gbest<LANES>(a, P, t, g, owner, s_g);
+            gather_gbest<LANES>(a, P, t, g, owner, s_g, sc);
         }
         if (hist && threadIdx.x == 0) hist[t & (HIST_CAP - 1)] = L.gkey;
         L.t = t;
@@ -324,6 +349,11 @@ __global__ void k_batch_reset(const BatchItem *items, BatchResult *results, uint
         if (items[i].parts > 1) {
             items[i].gang->arrive = 0ull;
             items[i].gang->err = 0u;
+            // the meeting's tagged words (keys, then candidate positions)
+            const size_t nk = (size_t)4 * items[i].parts, np = (size_t)2 * items[i].parts * items[i].a.D;
+            for (size_t w = 0; w < nk; ++w) items[i].cand_key[w] = 0ull;
+            unsigned long long *pw = reinterpret_cast<unsigned long long *>(items[i].cand_pos);
+            for (size_t w = 0; w < np; ++w) pw[w] = 0ull;
         }
     }
 }
@@ -347,8 +377,11 @@ __device__ void batch_part(const BatchItem &it, uint32_t part, uint32_t fixed_it
     P.part = part;
     P.q_lo = (uint32_t)((unsigned long long)nq * part / it.parts);
     P.q_hi = (uint32_t)((unsigned long long)nq * (part + 1) / it.parts);
-    P.qi_lo = (uint32_t)((unsigned long long)nqi * part / it.parts);
-    P.qi_hi = (uint32_t)((unsigned long long)nqi * (part + 1) / it.parts);
+    // Step 1 over the quads this part iterates (the last part also takes
+    // the padding): a part reads no state another part wrote during the
+    // launch, so the tagged meeting words are all the parts share
+    P.qi_lo = P.q_lo;
+    P.qi_hi = part + 1 == it.parts ? nqi : P.q_hi;
     P.gang = it.gang;
     P.cand_key = it.cand_key;
     P.cand_pos = it.cand_pos;
@@ -610,7 +643,7 @@ __device__ uint32_t staged_iterate(const SwarmArgs &a, const Staged &S, const Pa
                 const uint32_t mi = (uint32_t)g - ibase;
                 for (int d = threadIdx.x; d < D; d += LANES) s_g[d] = la.x[(size_t)d * pitch + mi];
             } else {
-                gather_gbest<LANES>(a, P, t, g, owner, s_g);
+                gather_gbest<LANES>(a, P, t, g, owner, s_g, sc);
             }
         }
         if (hist && threadIdx.x == 0) hist[t & (HIST_CAP - 1)] = L.gkey;
@@ -955,7 +988,9 @@ size_t gang_bytes(uint32_t parts, int D)
 {
     if (parts <= 1) return 0;
     auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
-    return al(sizeof(GangSync)) + al(sizeof(unsigned long long) * 2 * parts) + al(sizeof(float) * 2 * parts * (size_t)D);
+    // tagged words: two per key and one per coordinate, both parities
+    return al(sizeof(GangSync)) + al(sizeof(unsigned long long) * 4 * parts) +
+           al(sizeof(unsigned long long) * 2 * parts * (size_t)D);
 }
 
 void bind_gang(BatchItem *it, void *region, uint32_t parts)
@@ -971,7 +1006,7 @@ void bind_gang(BatchItem *it, void *region, uint32_t parts)
     char *b = static_cast<char *>(region);
     it->gang = reinterpret_cast<GangSync *>(b);
     it->cand_key = reinterpret_cast<unsigned long long *>(b + al(sizeof(GangSync)));
-    it->cand_pos = reinterpret_cast<float *>(b + al(sizeof(GangSync)) + al(sizeof(unsigned long long) * 2 * parts));
+    it->cand_pos = reinterpret_cast<float *>(b + al(sizeof(GangSync)) + al(sizeof(unsigned long long) * 4 * parts));
 }
 
 // ---------------------------------------------------------------------------
@@ -1060,6 +1095,12 @@ __global__ void __launch_bounds__(64) k_upload(const UploadRec *recs, uint32_t n
         items[u.slot] = u.item;
         state[u.slot] = u.state;
         if (u.reset_gang && u.item.gang) *u.item.gang = GangSync{};
+    }
+    if (u.reset_gang && u.item.gang) { // the meeting's tagged words
+        const size_t nk = (size_t)4 * u.item.parts, np = (size_t)2 * u.item.parts * u.item.a.D;
+        for (size_t w = threadIdx.x; w < nk; w += 64) u.item.cand_key[w] = 0ull;
+        unsigned long long *pw = reinterpret_cast<unsigned long long *>(u.item.cand_pos);
+        for (size_t w = threadIdx.x; w < np; w += 64) pw[w] = 0ull;
     }
     float *shift = const_cast<float *>(u.item.a.shift);
     for (int d = threadIdx.x; d < u.item.a.D; d += 64) shift[d] = pool[u.shift_at + d];

@@ -11,8 +11,9 @@ constexpr uint32_t MAX_STAGED_PARTS = 512; // workgroups one LDS-staged batched 
 
 // Meeting point of the parts of one swarm (parts > 1): each part posts its
 // workgroup-minimum key and, if it has one, that particle's position into the
-// slots of the step's parity, then arrives; the arrival count is monotonic
-// (parts * (steps so far)), so it needs no reset between steps or launches.
+// slots of the step's parity, as words tagged with the step (cand_key,
+// cand_pos); err records a part that waited past the time bound.  The arrival
+// count serves no meeting and stays zero.
 struct GangSync {
     unsigned long long arrive;
     unsigned int err;
@@ -21,7 +22,9 @@ struct GangSync {
 
 // One swarm of a batch: its state view (pointers into the batch's memory,
 // parameters, Philox key), its run limits and, when split into parts, the
-// parts' meeting point: cand_key[2][parts] and cand_pos[2][parts][D].
+// parts' meeting point: cand_key[2][parts][2] (a key's low and high halves)
+// and cand_pos[2][parts][D] (one coordinate's bits), 64-bit words whose high
+// halves carry the step.
 struct BatchItem {
     SwarmArgs a;
     int32_t fitness;
