@@ -335,11 +335,13 @@ __global__ void __launch_bounds__(RUN_LANES) k_block_run(SwarmArgs a, long long 
 // queue order with a part not yet dequeued has all its earlier parts either
 // running or waiting for it, and every swarm before it has all its parts.
 // ---------------------------------------------------------------------------
-__global__ void k_batch_reset(const BatchItem *items, BatchResult *results, uint32_t count, unsigned int *next)
+__global__ void __launch_bounds__(64) k_batch_reset(const BatchItem *items, BatchResult *results, uint32_t count,
+                                                     unsigned int *next)
 {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) *next = 0u;
-    if (i < count) {
+    const uint32_t i = blockIdx.x; // one wavefront per swarm
+    if (i >= count) return;
+    if (threadIdx.x == 0) {
+        if (i == 0) *next = 0u;
         results[i].gkey = NO_KEY;
         results[i].giter = 0;
         results[i].iters = 0;
@@ -349,12 +351,13 @@ __global__ void k_batch_reset(const BatchItem *items, BatchResult *results, uint
         if (items[i].parts > 1) {
             items[i].gang->arrive = 0ull;
             items[i].gang->err = 0u;
-            // the meeting's tagged words (keys, then candidate positions)
-            const size_t nk = (size_t)4 * items[i].parts, np = (size_t)2 * items[i].parts * items[i].a.D;
-            for (size_t w = 0; w < nk; ++w) items[i].cand_key[w] = 0ull;
-            unsigned long long *pw = reinterpret_cast<unsigned long long *>(items[i].cand_pos);
-            for (size_t w = 0; w < np; ++w) pw[w] = 0ull;
         }
+    }
+    if (items[i].parts > 1) { // the meeting's tagged words (keys, then candidate positions)
+        const size_t nk = (size_t)4 * items[i].parts, np = (size_t)2 * items[i].parts * items[i].a.D;
+        for (size_t w = threadIdx.x; w < nk; w += 64) items[i].cand_key[w] = 0ull;
+        unsigned long long *pw = reinterpret_cast<unsigned long long *>(items[i].cand_pos);
+        for (size_t w = threadIdx.x; w < np; w += 64) pw[w] = 0ull;
     }
 }
 
@@ -1117,7 +1120,8 @@ hipError_t launch_upload(const UploadRec *recs, uint32_t n, const float *pool, B
 hipError_t launch_batch_reset(const BatchItem *items, BatchResult *results, uint32_t count, unsigned int *next,
                               hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_batch_reset, dim3((count + 255) / 256), dim3(256), 0, stream, items, results, count, next);
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_reset, dim3(count), dim3(64), 0, stream, items, results, count, next);
     return hipGetLastError();
 }
 
