@@ -607,7 +607,9 @@ __device__ uint32_t staged_iterate(const SwarmArgs &a, const Staged &S, const Pa
     // again (a batch or server swarm only runs again after Step 1) and its
     // results -- gbest value, index, iteration, position and iterations run
     // -- do not read v.
-    const bool split = P.parts > 1;
+    // the next iteration's own half between the meeting's two halves (the
+    // batched parts); the single-swarm gang (PAIR) updates whole particles
+    const bool split = !PAIR && P.parts > 1;
     auto own_half = [&](uint32_t tn) {
         for (GridWalk<LANES> gw(pitch); gw.row < npairs; gw.next()) {
             const uint32_t pr = gw.row, sidx = gw.col;
@@ -881,6 +883,75 @@ __global__ void __launch_bounds__(LANES) k_block_run_staged(SwarmArgs a, long lo
     }
 }
 
+// ---------------------------------------------------------------------------
+// A single swarm whose state does not fit one workgroup's LDS, run as a gang
+// of co-resident workgroups (one per part, gridDim.x parts): each stages a
+// contiguous slice of quads, iterates it in LDS with the staged iteration,
+// and meets the others once per step through the step-tagged words (`words`:
+// 4 * parts key words, then 2 * parts * D coordinate words, zero at launch).
+// Continues from and updates the control block, as k_block_run_staged.
+// ---------------------------------------------------------------------------
+template <int FIT, int LANES>
+__global__ void __launch_bounds__(LANES) k_gang_staged(SwarmArgs a, long long T, unsigned long long *words)
+{
+    __shared__ Scratch sc;
+    extern __shared__ float s_dyn[]; // gbest position, shift (D floats each, rounded up to 16 bytes), state
+    Ctrl *c = a.ctrl;
+    const int D = a.D;
+    const int head = (D + 3) & ~3;
+    float *s_g = s_dyn, *s_shift = s_dyn + head, *s_state = s_dyn + 2 * head;
+    for (int d = threadIdx.x; d < D; d += LANES) {
+        s_g[d] = a.gpos[d];
+        s_shift[d] = a.shift[d];
+    }
+    if (threadIdx.x == 0) {
+        sc.min[0] = NO_KEY;
+        sc.min[1] = NO_KEY;
+        sc.err = 0;
+    }
+    // every part reads the control block before any part can finish: part 0
+    // writes it back only after all parts have met at every step
+    SwarmLoop L;
+    L.gkey = c->gkey_prev;
+    L.giter = c->giter;
+    L.t = c->t;
+    L.stop = c->stop != 0u;
+    const float tol = c->tol, fstar = c->fstar;
+    const uint32_t parts = gridDim.x, part = blockIdx.x, nq = (a.N + 3) / 4;
+    Part P{};
+    P.parts = parts;
+    P.part = part;
+    P.q_lo = (uint32_t)((unsigned long long)nq * part / parts);
+    P.q_hi = (uint32_t)((unsigned long long)nq * (part + 1) / parts);
+    P.qi_lo = P.q_lo;
+    P.qi_hi = P.q_hi;
+    P.cand_key = words;
+    P.cand_pos = reinterpret_cast<float *>(words + (size_t)4 * parts);
+    const Staged S = staged_view<FIT>(a, s_state, P.q_lo, P.q_hi);
+    staged_load<LANES>(a, S); // ends with a barrier (s_g, s_shift, sc too)
+    const uint32_t n_imp = staged_iterate<FIT, LANES, true>(a, S, P, T, tol, fstar, s_g, s_shift, &sc,
+                                                            part == 0 ? a.hist : nullptr, L);
+    staged_store<LANES>(a, S);
+    if (n_imp) atomicAdd(&c->improved, (unsigned long long)n_imp);
+    if (threadIdx.x == 0 && sc.err) atomicOr(&c->err, ERR_GANG_WAIT);
+    if (part != 0) return;
+    for (int d = threadIdx.x; d < D; d += LANES) a.gpos[d] = s_g[d];
+    if (threadIdx.x == 0) {
+        c->gkey = L.gkey;
+        c->gkey_prev = L.gkey;
+        c->pubkey = L.gkey;
+        c->giter = L.giter;
+        c->t = L.t;
+        c->stop = L.stop ? 1u : 0u;
+    }
+}
+
+__global__ void k_zero_words(unsigned long long *w, size_t n)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        w[i] = 0ull;
+}
+
 template <int LANES>
 __global__ void __launch_bounds__(LANES) k_batch(const BatchItem *items, const BatchEntry *entries,
                                                  BatchResult *results, uint32_t count, unsigned int *next,
@@ -1088,6 +1159,76 @@ hipError_t launch_block_run(int fitness, const SwarmArgs &a, long long T, hipStr
     return hipGetLastError();
 }
 
+
+// The gang: one particle per lane of 256, at least two parts, every part
+// co-resident (at most one per compute unit's share of the occupancy).
+constexpr int GANG_LANES = 256;
+constexpr uint32_t GANG_MAX_PARTS = 256;
+
+static const void *gang_kernel(int fitness)
+{
+    switch (fitness) {
+    case F_SPHERE: return reinterpret_cast<const void *>(k_gang_staged<F_SPHERE, GANG_LANES>);
+    case F_RASTRIGIN: return reinterpret_cast<const void *>(k_gang_staged<F_RASTRIGIN, GANG_LANES>);
+    case F_ROSENBROCK: return reinterpret_cast<const void *>(k_gang_staged<F_ROSENBROCK, GANG_LANES>);
+    case F_ACKLEY: return reinterpret_cast<const void *>(k_gang_staged<F_ACKLEY, GANG_LANES>);
+    default: return reinterpret_cast<const void *>(k_gang_staged<F_CUBIC, GANG_LANES>);
+    }
+}
+
+uint32_t gang_run_parts(int fitness, const SwarmArgs &a)
+{
+    const char *env = getenv("PSO_GANG");
+    if (env && !strcmp(env, "0")) return 0;
+    if (a.D > 2 || fitness < F_SPHERE || fitness > F_CUBIC) return 0;
+    const uint32_t nq = (a.N + 3) / 4;
+    const uint32_t parts = (nq + GANG_LANES / 4 - 1) / (GANG_LANES / 4);
+    if (parts < 2 || parts > GANG_MAX_PARTS) return 0;
+    const size_t lds = sizeof(float) * 2 * (((size_t)a.D + 3) & ~(size_t)3) +
+                       (size_t)((nq + parts - 1) / parts) * staged_quad_bytes(a.D, fitness);
+    if (lds + sizeof(Scratch) + 1024 > (size_t)device_lds_max()) return 0;
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, gang_kernel(fitness), GANG_LANES, lds) != hipSuccess)
+        return 0;
+    return (uint64_t)per_cu * (uint64_t)cus >= parts ? parts : 0;
+}
+
+size_t gang_run_words(uint32_t parts, int D)
+{
+    return (size_t)4 * parts + (size_t)2 * parts * (size_t)D;
+}
+
+template <int FIT>
+static hipError_t launch_gang_staged(const SwarmArgs &a, long long T, uint32_t parts, unsigned long long *words,
+                                     hipStream_t stream)
+{
+    const uint32_t nq = (a.N + 3) / 4;
+    const size_t lds = sizeof(float) * 2 * (((size_t)a.D + 3) & ~(size_t)3) +
+                       (size_t)((nq + parts - 1) / parts) * staged_quad_bytes(a.D, FIT);
+    // the most any swarm may ask for, so concurrent callers never lower it
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_gang_staged<FIT, GANG_LANES>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, device_lds_max() - 1024);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_zero_words, dim3(4), dim3(256), 0, stream, words, gang_run_words(parts, a.D));
+    hipLaunchKernelGGL((k_gang_staged<FIT, GANG_LANES>), dim3(parts), dim3(GANG_LANES), lds, stream, a, T, words);
+    return hipGetLastError();
+}
+
+hipError_t launch_gang_run(int fitness, const SwarmArgs &a, long long T, uint32_t parts, unsigned long long *words,
+                           hipStream_t stream)
+{
+    switch (fitness) {
+    case F_SPHERE: return launch_gang_staged<F_SPHERE>(a, T, parts, words, stream);
+    case F_RASTRIGIN: return launch_gang_staged<F_RASTRIGIN>(a, T, parts, words, stream);
+    case F_ROSENBROCK: return launch_gang_staged<F_ROSENBROCK>(a, T, parts, words, stream);
+    case F_ACKLEY: return launch_gang_staged<F_ACKLEY>(a, T, parts, words, stream);
+    case F_CUBIC: return launch_gang_staged<F_CUBIC>(a, T, parts, words, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
 
 __global__ void __launch_bounds__(64) k_upload(const UploadRec *recs, uint32_t n, const float *pool, BatchItem *items,
                                                 BatchResult *state)

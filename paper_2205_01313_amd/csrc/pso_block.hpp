@@ -106,6 +106,17 @@ hipError_t launch_block_run(int fitness, const SwarmArgs &a, long long T, hipStr
 // Whether a pso_run of this swarm should take the one-workgroup run: its
 // state fits one workgroup's LDS (always true under PSO_BLOCK_STAGED=0).
 bool block_run_suits(int fitness, const SwarmArgs &a);
+// A single swarm too large for one workgroup's LDS, with D <= 2: the parts
+// of its gang (one particle per lane of 256, all co-resident), or 0 when the
+// gang does not suit it (or PSO_GANG=0 in the environment).
+uint32_t gang_run_parts(int fitness, const SwarmArgs &a);
+// Device words its meeting needs (64-bit each).
+size_t gang_run_words(uint32_t parts, int D);
+// Runs up to T more iterations of the swarm as that gang, continuing from
+// and updating its control block (stop rule included); words: at least
+// gang_run_words(parts, D), cleared by the launch itself.
+hipError_t launch_gang_run(int fitness, const SwarmArgs &a, long long T, uint32_t parts, unsigned long long *words,
+                           hipStream_t stream);
 
 // Marks results[0..count) not started (and their gangs unused); clears the
 // work counter.

@@ -105,6 +105,9 @@ struct pso_swarm {
     hipGraph_t steps_graph = nullptr;
     hipGraphExec_t steps_exec = nullptr;
     int steps_key = -1;
+    // the gang run's meeting words (allocated at its first run)
+    unsigned long long *gang_words = nullptr;
+    size_t gang_words_n = 0;
 };
 
 namespace {
@@ -392,11 +395,26 @@ int pso_run(pso_swarm *s, int64_t max_iter, float tol, float f_star, float *gbes
         HIP_TRY(pso::launch_arm(s->args, tol, f_star, s->stream));
         const bool block_path = s->variant == PSO_SYNC && int64_t(s->N) * s->D <= BLOCK_RUN_MAX_ND &&
                                 pso::block_run_suits(s->fitness, s->args);
+        const uint32_t gang_parts =
+            s->variant == PSO_SYNC && !block_path ? pso::gang_run_parts(s->fitness, s->args) : 0u;
         if (s->variant == PSO_PERSISTENT) {
             int rc = persistent_launch(s, max_iter);
             if (rc) return rc;
         } else if (block_path) {
             if (max_iter > 0) HIP_TRY(pso::launch_block_run(s->fitness, s->args, max_iter, s->stream));
+        } else if (gang_parts > 0) {
+            const size_t n = pso::gang_run_words(gang_parts, s->D);
+            if (n > s->gang_words_n) {
+                HIP_TRY(hipStreamSynchronize(s->stream));
+                if (s->gang_words) (void)hipFree(s->gang_words);
+                s->gang_words = nullptr;
+                s->gang_words_n = 0;
+                if (hipMalloc(reinterpret_cast<void **>(&s->gang_words), n * sizeof(unsigned long long)) != hipSuccess)
+                    return fail(PSO_ENOMEM, "gang meeting words: device allocation failed");
+                s->gang_words_n = n;
+            }
+            if (max_iter > 0)
+                HIP_TRY(pso::launch_gang_run(s->fitness, s->args, max_iter, gang_parts, s->gang_words, s->stream));
         } else if (tol > 0.0f) {
             // Chunks of iterations with one chunk always queued ahead; the
             // device skips iterations once the stop rule holds, and the host
@@ -582,6 +600,7 @@ int pso_destroy(pso_swarm *s)
         if (!s) return fail(PSO_EINVAL, "swarm is NULL");
         (void)hipStreamSynchronize(s->stream);
         drop_steps_graph(s);
+        if (s->gang_words) (void)hipFree(s->gang_words);
         if (s->owns_ws) (void)hipFree(s->ws);
         if (s->owns_stream) (void)hipStreamDestroy(s->stream);
         (void)hipHostFree(s->host_ctrl);

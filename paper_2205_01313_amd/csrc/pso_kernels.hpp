@@ -42,6 +42,7 @@ static_assert(sizeof(Ctrl) == 1024, "Ctrl layout");
 
 constexpr unsigned int ERR_SEQLOCK_SPIN = 1u; // a seqlock wait gave up
 constexpr unsigned int ERR_STALE_WAIT = 2u;   // a bounded-staleness wait gave up
+constexpr unsigned int ERR_GANG_WAIT = 4u;    // a gang part waited past the time bound
 
 // Aggregation variants (values of PSO_SYNC / PSO_ASYNC / PSO_REDUCE /
 // PSO_REDUCE_UNROLLED in pso.h).

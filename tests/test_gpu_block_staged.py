@@ -45,3 +45,29 @@ def test_staged_block_run_equals_streamed_and_oracle(monkeypatch, fit, N, D):
     o = oracle_swarm(spec, 8).run_f32(T, tol=tol, f_star=f_star)
     assert s1["iters"] + s2["iters"] == o["iters"] and s2["gbest_fit"] == o["gbest_fit"]
     assert s2["gbest_iter"] == o["giter"] and np.array_equal(s2["gbest_pos"], o["gpos"])
+
+
+@pytest.mark.parametrize("fit,N,D", [("cubic", 16384, 1), ("sphere", 9000, 2), ("rastrigin", 20001, 1),
+                                     ("rosenbrock", 12000, 2), ("ackley", 65536, 2)])
+def test_gang_run_equals_step_launches_and_oracle(monkeypatch, fit, N, D):
+    """Swarms with D <= 2 too large for one workgroup's LDS run as a gang of
+    co-resident workgroups (one particle per lane, a step-tagged meeting per
+    iteration): the same bits as the graph-replayed step launches (PSO_GANG=0)
+    and as the oracle, across runs that continue each other."""
+    T = 90
+    spec = wl.SwarmSpec(fit, N, D, T, seed=N * 5 + D, shift_amplitude=2.0)
+    tol, f_star = (1e-3, 0.0) if fit == "sphere" else (0.0, 0.0)
+    announce(f"gang run {fit} N={N} D={D}")
+    monkeypatch.delenv("PSO_GANG", raising=False)
+    s1, s2, st, hist, imp = run_twice(spec, T, tol, f_star)
+    monkeypatch.setenv("PSO_GANG", "0")
+    q1, q2, qt, qhist, qimp = run_twice(spec, T, tol, f_star)
+    for a, b in ((s1, q1), (s2, q2)):
+        assert a["gbest_fit"] == b["gbest_fit"] and a["gbest_iter"] == b["gbest_iter"] and a["iters"] == b["iters"]
+        assert np.array_equal(a["gbest_pos"], b["gbest_pos"])
+    assert st["t"] == qt["t"] and st["gkey"] == qt["gkey"]
+    assert np.array_equal(hist, qhist) and imp == qimp
+    assert_state_equal(st, qt, N, D)
+    o = oracle_swarm(spec, 8).run_f32(T, tol=tol, f_star=f_star)
+    assert s1["iters"] + s2["iters"] == o["iters"] and s2["gbest_fit"] == o["gbest_fit"]
+    assert s2["gbest_iter"] == o["giter"] and np.array_equal(s2["gbest_pos"], o["gpos"])
