@@ -134,9 +134,13 @@ int pso_step(pso_swarm *s);
  * initialisation) and the number of iterations this call ran.  Any output
  * pointer may be NULL.  A synchronous swarm with N*D <= 65536 whose state
  * fits one workgroup's LDS runs the whole call as one launch of one
- * workgroup (its state staged in LDS); others take one launch per
- * iteration (PSO_PERSISTENT: one persistent launch).  Every path computes
- * the same bits. */
+ * workgroup (its state staged in LDS); a synchronous swarm with D <= 2 that
+ * does not fit runs it as one launch of ceil(N / 256) co-resident
+ * workgroups (2 to 256), each holding a slice in LDS and meeting the others
+ * once per iteration (PSO_GANG=0 in the environment turns this off; a part
+ * that waits past 20 s sets a device error, returned as PSO_EDEVICE); others
+ * take one launch per iteration (PSO_PERSISTENT: one persistent launch).
+ * Every path computes the same bits. */
 int pso_run(pso_swarm *s, int64_t max_iter, float tol, float f_star, float *gbest_value,
             float *gbest_pos_host, int64_t *gbest_iter, int64_t *iters_done);
 
