@@ -1161,9 +1161,15 @@ hipError_t launch_block_run(int fitness, const SwarmArgs &a, long long T, hipStr
 
 
 // The gang: one particle per lane of 256, at least two parts, every part
-// co-resident (at most one per compute unit's share of the occupancy).
+// co-resident (checked against the occupancy).
 constexpr int GANG_LANES = 256;
 constexpr uint32_t GANG_MAX_PARTS = 256;
+// D <= 2 takes the fused loop, larger D the staged general loop; past
+// D = 16 the step launches keep up with the gang (Rastrigin, N = 16 384 and
+// 65 536: D = 8 5.3 / 7.0 against 10.5 / 11.0 us per iteration, D = 31
+// 13.4 / 15.2 against 12.4 / 16.0).  PSO_GANG_MAX_D in the environment
+// moves the limit (up to 64).
+constexpr int GANG_MAX_D = 16;
 
 static const void *gang_kernel(int fitness)
 {
@@ -1180,7 +1186,9 @@ uint32_t gang_run_parts(int fitness, const SwarmArgs &a)
 {
     const char *env = getenv("PSO_GANG");
     if (env && !strcmp(env, "0")) return 0;
-    if (a.D > 2 || fitness < F_SPHERE || fitness > F_CUBIC) return 0;
+    const char *max_d_env = getenv("PSO_GANG_MAX_D");
+    const int max_d = max_d_env ? atoi(max_d_env) : GANG_MAX_D;
+    if (a.D > max_d || a.D > 64 || fitness < F_SPHERE || fitness > F_CUBIC) return 0;
     const uint32_t nq = (a.N + 3) / 4;
     const uint32_t parts = (nq + GANG_LANES / 4 - 1) / (GANG_LANES / 4);
     if (parts < 2 || parts > GANG_MAX_PARTS) return 0;

@@ -106,7 +106,7 @@ hipError_t launch_block_run(int fitness, const SwarmArgs &a, long long T, hipStr
 // Whether a pso_run of this swarm should take the one-workgroup run: its
 // state fits one workgroup's LDS (always true under PSO_BLOCK_STAGED=0).
 bool block_run_suits(int fitness, const SwarmArgs &a);
-// A single swarm too large for one workgroup's LDS, with D <= 2: the parts
+// A single swarm too large for one workgroup's LDS, with D <= 16: the parts
 // of its gang (one particle per lane of 256, all co-resident), or 0 when the
 // gang does not suit it (or PSO_GANG=0 in the environment).
 uint32_t gang_run_parts(int fitness, const SwarmArgs &a);

@@ -48,9 +48,10 @@ def test_staged_block_run_equals_streamed_and_oracle(monkeypatch, fit, N, D):
 
 
 @pytest.mark.parametrize("fit,N,D", [("cubic", 16384, 1), ("sphere", 9000, 2), ("rastrigin", 20001, 1),
-                                     ("rosenbrock", 12000, 2), ("ackley", 65536, 2)])
+                                     ("rosenbrock", 12000, 2), ("ackley", 65536, 2), ("rastrigin", 16384, 8),
+                                     ("rosenbrock", 9000, 5), ("ackley", 20000, 16), ("sphere", 30001, 3)])
 def test_gang_run_equals_step_launches_and_oracle(monkeypatch, fit, N, D):
-    """Swarms with D <= 2 too large for one workgroup's LDS run as a gang of
+    """Swarms with D <= 16 too large for one workgroup's LDS run as a gang of
     co-resident workgroups (one particle per lane, a step-tagged meeting per
     iteration): the same bits as the graph-replayed step launches (PSO_GANG=0)
     and as the oracle, across runs that continue each other."""
