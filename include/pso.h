@@ -134,8 +134,9 @@ int pso_step(pso_swarm *s);
  * initialisation) and the number of iterations this call ran.  Any output
  * pointer may be NULL.  A synchronous swarm with N*D <= 65536 whose state
  * fits one workgroup's LDS runs the whole call as one launch of one
- * workgroup (its state staged in LDS); a synchronous swarm with D <= 16 that
- * does not fit runs it as one launch of ceil(N / 256) co-resident
+ * workgroup (its state staged in LDS), unless N >= 4096 or N*D >= 8192 and
+ * the gang below has 8 parts or more; a synchronous swarm with D <= 16 that
+ * does not take it runs the call as one launch of ceil(N / 256) co-resident
  * workgroups (2 to 256), each holding a slice in LDS and meeting the others
  * once per iteration (PSO_GANG=0 in the environment turns this off; a part
  * that waits past 20 s sets a device error, returned as PSO_EDEVICE); others

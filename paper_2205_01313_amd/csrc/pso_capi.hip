@@ -393,10 +393,20 @@ int pso_run(pso_swarm *s, int64_t max_iter, float tol, float f_star, float *gbes
         if (max_iter < 0) return fail(PSO_EINVAL, "max_iter < 0");
         if (std::isnan(tol) || std::isnan(f_star)) return fail(PSO_EINVAL, "tol and f_star must not be NaN");
         HIP_TRY(pso::launch_arm(s->args, tol, f_star, s->stream));
-        const bool block_path = s->variant == PSO_SYNC && int64_t(s->N) * s->D <= BLOCK_RUN_MAX_ND &&
-                                pso::block_run_suits(s->fitness, s->args);
-        const uint32_t gang_parts =
-            s->variant == PSO_SYNC && !block_path ? pso::gang_run_parts(s->fitness, s->args) : 0u;
+        bool block_path = s->variant == PSO_SYNC && int64_t(s->N) * s->D <= BLOCK_RUN_MAX_ND &&
+                          pso::block_run_suits(s->fitness, s->args);
+        uint32_t gang_parts = s->variant == PSO_SYNC ? pso::gang_run_parts(s->fitness, s->args) : 0u;
+        if (block_path) {
+            // a gang of 8 or more parts meets in about 2 us per iteration and
+            // overtakes one workgroup from N = 4096 or N*D = 8192 (Cubic 1D
+            // N = 4096: 2.34 against 2.85 us; Rastrigin D = 4, N = 2048: 3.38
+            // against 5.71; below, one workgroup: D = 2, N = 2048 2.00 against 2.25)
+            const bool gang_first = gang_parts >= 8 && (s->N >= 4096 || int64_t(s->N) * s->D >= 8192);
+            if (gang_first)
+                block_path = false;
+            else
+                gang_parts = 0;
+        }
         if (s->variant == PSO_PERSISTENT) {
             int rc = persistent_launch(s, max_iter);
             if (rc) return rc;

@@ -32,6 +32,7 @@ def test_staged_block_run_equals_streamed_and_oracle(monkeypatch, fit, N, D):
     spec = wl.SwarmSpec(fit, N, D, T, seed=N * 7 + D, shift_amplitude=2.0)
     tol, f_star = (1e-3, 0.0) if fit == "sphere" else (0.0, 0.0)
     announce(f"staged one-workgroup run {fit} N={N} D={D}")
+    monkeypatch.setenv("PSO_GANG", "0")  # the one-workgroup run, where a gang would overtake it
     monkeypatch.delenv("PSO_BLOCK_STAGED", raising=False)
     s1, s2, st, hist, imp = run_twice(spec, T, tol, f_star)
     monkeypatch.setenv("PSO_BLOCK_STAGED", "0")
@@ -49,7 +50,8 @@ def test_staged_block_run_equals_streamed_and_oracle(monkeypatch, fit, N, D):
 
 @pytest.mark.parametrize("fit,N,D", [("cubic", 16384, 1), ("sphere", 9000, 2), ("rastrigin", 20001, 1),
                                      ("rosenbrock", 12000, 2), ("ackley", 65536, 2), ("rastrigin", 16384, 8),
-                                     ("rosenbrock", 9000, 5), ("ackley", 20000, 16), ("sphere", 30001, 3)])
+                                     ("rosenbrock", 9000, 5), ("ackley", 20000, 16), ("sphere", 30001, 3),
+                                     ("cubic", 4097, 1), ("rastrigin", 2049, 4)])
 def test_gang_run_equals_step_launches_and_oracle(monkeypatch, fit, N, D):
     """Swarms with D <= 16 too large for one workgroup's LDS run as a gang of
     co-resident workgroups (one particle per lane, a step-tagged meeting per
